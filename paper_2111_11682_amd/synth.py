@@ -1,0 +1,289 @@
+"""Seeded synthetic rating matrices with the shapes of the paper's workloads.
+
+This module is the only code shared by the HIP path's tests and the oracle.
+It produces inputs only -- COO ratings, a train/held-out split, the random
+user hash strings H_i (an input of the CULSH algorithm, Sec. 4.1 Alg. 1) and
+initial factor tables (an input of the CULSH-MF algorithm, Sec. 4.2 Alg. 3).
+It holds none of the method's arithmetic (no hashing, no baselines, no SGD).
+
+Recipe (stand-in for the Netflix / MovieLens data of Sec. 5.1, Table "Data
+sets", which are not available):
+
+* item popularity: Zipf(s) over popularity ranks; rank -> item id through a
+  seeded permutation so an id carries no popularity signal;
+* user degrees: lognormal, rescaled to the exact rating total, clipped to
+  [d_min, N // 2];
+* each user draws its items by successive sampling without replacement
+  (draw with replacement in Zipf order, keep the first d_u distinct items);
+* ratings carry planted structure so that held-out RMSE and neighbours are
+  informative: z = sqrt(.5) * standardise(a_u + c_i + x_u . y_i) +
+  sqrt(.5) * eps, with x, y in R^8 and y drawn around 64 item clusters, then
+  r = clip(round(3.5 + 1.1 z)) on the integer 1..5 scale or the half-step
+  0.5..5.0 scale;
+* ratings are stored as integer codes rc = rscale * r (rscale 1 for integer
+  ratings, 2 for half-steps), so rc is in 1..5 or 1..10;
+* H_i: B uniformly random bits per user, packed LSB-first in uint32 words;
+* U0, V0: k / 2048 with k uniform in [-128, 128), exact in bf16/fp32/fp64.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import Dict, Optional, Tuple
+
+import numpy as np
+
+MASTER_SEED = 2111_11682
+
+
+@dataclasses.dataclass(frozen=True)
+class Workload:
+    name: str
+    M: int                   # users (rows)
+    N: int                   # items (columns)
+    nnz: int                 # total ratings before the split
+    rscale: int              # 1: integer ratings 1..5; 2: half-steps 0.5..5
+    zipf_s: float            # item popularity exponent
+    deg_kind: str            # "c1" (min 20 + lognormal extra) or "lognormal"
+    deg_mu: float            # lognormal location (log scale)
+    deg_sigma: float
+    deg_min: int
+    n_test: int              # held-out ratings
+    F: int
+    K: int
+    G: int                   # bits per simLSH hash (a byte in the paper)
+    p: int                   # hashes per coarse band
+    q: int                   # bands (fine-grained OR)
+    epochs: int
+    alpha: Tuple[float, ...]   # learning rates  (b, bh, u, v, w, c)
+    lam: Tuple[float, ...]     # regularisers    (b, bh, u, v, w, c)
+    beta: float                # learning-rate decay, Eq. learn_rate
+    n_strata: int = 256
+
+    @property
+    def B(self) -> int:
+        return self.G * self.p * self.q
+
+
+def _ln_mu_for_mean(mean: float, sigma: float) -> float:
+    return math.log(mean) - 0.5 * sigma * sigma
+
+
+# Hyper-parameters: Table "The initial learning speed and regularization
+# parameters of CULSH-MF" (MovieLens and Netflix columns) and beta = 0.3.
+_ML_ALPHA = (0.035, 0.035, 0.035, 0.035, 0.002, 0.002)
+_ML_LAM = (0.02, 0.02, 0.02, 0.02, 0.002, 0.002)
+_NF_ALPHA = (0.02, 0.02, 0.02, 0.02, 0.001, 0.001)
+_NF_LAM = (0.01, 0.01, 0.01, 0.01, 0.05, 0.05)
+
+WORKLOADS: Dict[str, Workload] = {
+    # MovieLens-100k-shaped plain case
+    "ml100k": Workload("ml100k", 943, 1682, 100_000, 1, 1.0, "c1", 0.0, 1.0, 20,
+                       10_000, 32, 10, 8, 1, 8, 5,
+                       (0.01,) * 6, (0.05,) * 6, 0.0, n_strata=16),
+    # MovieLens-10M-shaped (Table "Data sets", MovieLens column)
+    "ml10m": Workload("ml10m", 69_878, 10_677, 10_000_000, 2, 1.1, "lognormal",
+                      _ln_mu_for_mean(143.0, 1.2), 1.2, 20,
+                      100_000, 64, 50, 8, 1, 16, 20, _ML_ALPHA, _ML_LAM, 0.3,
+                      n_strata=256),
+    # Netflix-shaped (Table "Data sets", Netflix column)
+    "netflix": Workload("netflix", 480_189, 17_770, 100_000_000, 1, 1.2, "lognormal",
+                        4.5, 1.2, 1, 1_408_395, 128, 100, 8, 1, 16, 20,
+                        _NF_ALPHA, _NF_LAM, 0.3, n_strata=256),
+    # small shapes for CPU tests
+    "tiny": Workload("tiny", 120, 90, 2_400, 1, 1.0, "c1", 0.0, 1.0, 5,
+                     240, 8, 6, 8, 1, 4, 3, (0.01,) * 6, (0.05,) * 6, 0.0,
+                     n_strata=4),
+    "small": Workload("small", 700, 500, 30_000, 2, 1.1, "lognormal",
+                      _ln_mu_for_mean(43.0, 1.0), 1.0, 5,
+                      2_000, 64, 50, 8, 1, 16, 2, _ML_ALPHA, _ML_LAM, 0.3,
+                      n_strata=8),
+}
+
+
+def derive_seed(*parts: int) -> int:
+    """Independent sub-stream seeds from the master seed (numpy SeedSequence)."""
+    ss = np.random.SeedSequence([MASTER_SEED, *parts])
+    return int(ss.generate_state(1, dtype=np.uint64)[0])
+
+
+def _rng(seed: int, stream: int) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(np.random.SeedSequence([seed, stream])))
+
+
+def user_degrees(w: Workload, rng: np.random.Generator, M: Optional[int] = None,
+                 total: Optional[int] = None) -> np.ndarray:
+    M = w.M if M is None else M
+    total = w.nnz if total is None else total
+    dmax = max(w.N // 2, 1)
+    dmin = min(w.deg_min, dmax)
+    if w.deg_kind == "c1":
+        extra = rng.lognormal(0.0, w.deg_sigma, M)
+        raw = dmin + extra * max(total - dmin * M, 0) / extra.sum()
+    else:
+        raw = rng.lognormal(w.deg_mu, w.deg_sigma, M)
+    if total > dmax * M or total < dmin * M:
+        raise ValueError("rating total not reachable with the degree bounds")
+    d = raw * (total / raw.sum())
+    for _ in range(100):           # rescale the unclipped part until the total fits
+        d = np.clip(d, dmin, dmax)
+        free = (d > dmin) & (d < dmax)
+        gap = total - d.sum()
+        if abs(gap) < 0.5 or not free.any():
+            break
+        d[free] *= 1.0 + gap / d[free].sum()
+    base = np.floor(d).astype(np.int64)
+    base = np.clip(base, dmin, dmax)
+    rem = total - int(base.sum())
+    frac = d - np.floor(d)
+    order = np.argsort(-frac, kind="stable")
+    step = 1 if rem > 0 else -1
+    k = 0
+    while rem != 0:                # largest-remainder rounding to the exact total
+        idx = order[k % M]
+        nv = base[idx] + step
+        if dmin <= nv <= dmax:
+            base[idx] = nv
+            rem -= step
+        k += 1
+    return base
+
+
+def sample_items(deg: np.ndarray, N: int, s: float, rng: np.random.Generator
+                 ) -> Tuple[np.ndarray, np.ndarray]:
+    """Successive sampling without replacement from Zipf(s) popularity ranks.
+
+    Returns (user, rank) pairs, users ascending, ranks in draw order per user.
+    """
+    w = np.arange(1, N + 1, dtype=np.float64) ** (-s)
+    cdf = np.cumsum(w)
+    cdf /= cdf[-1]
+    M = deg.shape[0]
+    need = deg.astype(np.int64).copy()
+    got_u = []
+    got_r = []
+    chosen = np.empty(0, dtype=np.int64)          # sorted keys user*N + rank
+    factor = 1.6
+    while True:
+        users = np.nonzero(need > 0)[0]
+        if users.size == 0:
+            break
+        T = np.ceil(need[users] * factor).astype(np.int64) + 16
+        du = np.repeat(users.astype(np.int64), T)
+        ranks = np.searchsorted(cdf, rng.random(du.size), side="right")
+        np.minimum(ranks, N - 1, out=ranks)
+        keys = du * N + ranks
+        uniq, first = np.unique(keys, return_index=True)
+        if chosen.size:
+            pos = np.searchsorted(chosen, uniq)
+            pos = np.minimum(pos, chosen.size - 1)
+            fresh = chosen[pos] != uniq
+            uniq, first = uniq[fresh], first[fresh]
+        order = np.argsort(first, kind="stable")
+        uniq, first = uniq[order], first[order]
+        uu = uniq // N
+        # rank of each fresh item within its user, in draw order
+        starts = np.searchsorted(uu, users)
+        within = np.arange(uu.size) - np.repeat(starts, np.diff(np.append(starts, uu.size)))
+        take = within < need[uu]
+        uniq = uniq[take]
+        got_u.append(uniq // N)
+        got_r.append(uniq % N)
+        np.subtract.at(need, uniq // N, 1)
+        chosen = np.sort(np.concatenate([chosen, uniq]))
+        factor *= 2.0
+    u = np.concatenate(got_u) if got_u else np.empty(0, np.int64)
+    r = np.concatenate(got_r) if got_r else np.empty(0, np.int64)
+    order = np.argsort(u, kind="stable")
+    return u[order], r[order]
+
+
+def planted_ratings(u: np.ndarray, item: np.ndarray, M: int, N: int, rscale: int,
+                    rng: np.random.Generator, chunk: int = 8_000_000) -> np.ndarray:
+    """Integer rating codes rc = rscale * r with planted low-rank/cluster structure."""
+    a = rng.standard_normal(M).astype(np.float32)
+    c = rng.standard_normal(N).astype(np.float32)
+    x = (rng.standard_normal((M, 8)) / math.sqrt(8.0)).astype(np.float32)
+    cent = rng.standard_normal((64, 8)).astype(np.float32)
+    cl = rng.integers(0, 64, N)
+    y = (cent[cl] + 0.5 * rng.standard_normal((N, 8))).astype(np.float32)
+    n = u.shape[0]
+    s = np.empty(n, dtype=np.float32)
+    for lo in range(0, n, chunk):
+        hi = min(n, lo + chunk)
+        uu, ii = u[lo:hi], item[lo:hi]
+        s[lo:hi] = a[uu] + c[ii] + np.einsum("ij,ij->i", x[uu], y[ii])
+    mean = float(s.mean(dtype=np.float64))
+    std = float(s.std(dtype=np.float64)) or 1.0
+    rc = np.empty(n, dtype=np.uint8)
+    lo_code, hi_code = (1, 5) if rscale == 1 else (1, 10)
+    for lo in range(0, n, chunk):
+        hi = min(n, lo + chunk)
+        z = math.sqrt(0.5) * (s[lo:hi] - mean) / std + \
+            math.sqrt(0.5) * rng.standard_normal(hi - lo).astype(np.float32)
+        code = np.rint(rscale * (3.5 + 1.1 * z))
+        rc[lo:hi] = np.clip(code, lo_code, hi_code).astype(np.uint8)
+    return rc
+
+
+def init_table(rows: int, F: int, rng: np.random.Generator) -> np.ndarray:
+    """k / 2048, k uniform in [-128, 128): uniform on [-1/16, 1/16), exact in bf16."""
+    k = rng.integers(-128, 128, size=(rows, F), dtype=np.int32)
+    return (k.astype(np.float32) * np.float32(1.0 / 2048.0))
+
+
+def hash_strings(M: int, B: int, rng: np.random.Generator) -> np.ndarray:
+    """H_i: B random bits per user, bit b in word b // 32 at position b % 32."""
+    if B % 32:
+        words = (B + 31) // 32
+    else:
+        words = B // 32
+    H = rng.integers(0, 1 << 32, size=(M, words), dtype=np.uint64).astype(np.uint32)
+    if B % 32:
+        H[:, -1] &= np.uint32((1 << (B % 32)) - 1)
+    return H
+
+
+def generate(w: Workload, seed: int = MASTER_SEED, with_tables: bool = True) -> Dict[str, np.ndarray]:
+    """All inputs of one workload, deterministic in (w, seed).
+
+    Keys: train_u, train_i, train_rc, test_u, test_i, test_rc (int32/uint8 COO),
+    H (uint32 [M, ceil(B/32)]), U0 (f32 [M, F]), V0 (f32 [N, F]).
+    """
+    rng_deg = _rng(seed, 1)
+    rng_items = _rng(seed, 2)
+    rng_perm = _rng(seed, 3)
+    rng_rate = _rng(seed, 4)
+    rng_split = _rng(seed, 5)
+    rng_hash = _rng(seed, 6)
+    rng_init = _rng(seed, 7)
+
+    deg = user_degrees(w, rng_deg)
+    u, rank = sample_items(deg, w.N, w.zipf_s, rng_items)
+    user_perm = rng_perm.permutation(w.M)
+    item_perm = rng_perm.permutation(w.N)
+    uid = user_perm[u].astype(np.int32)
+    iid = item_perm[rank].astype(np.int32)
+    rc = planted_ratings(uid, iid, w.M, w.N, w.rscale, rng_rate)
+    order = rng_split.permutation(uid.shape[0])
+    test_idx = np.sort(order[: w.n_test])
+    train_idx = np.sort(order[w.n_test:])
+    out = {
+        "train_u": np.ascontiguousarray(uid[train_idx]),
+        "train_i": np.ascontiguousarray(iid[train_idx]),
+        "train_rc": np.ascontiguousarray(rc[train_idx]),
+        "test_u": np.ascontiguousarray(uid[test_idx]),
+        "test_i": np.ascontiguousarray(iid[test_idx]),
+        "test_rc": np.ascontiguousarray(rc[test_idx]),
+        "H": hash_strings(w.M, w.B, rng_hash),
+    }
+    if with_tables:
+        out["U0"] = init_table(w.M, w.F, rng_init)
+        out["V0"] = init_table(w.N, w.F, rng_init)
+    return out
+
+
+def random_queries(M: int, N: int, n: int, seed: int) -> Tuple[np.ndarray, np.ndarray]:
+    """Uniform (user, item) query pairs for predict."""
+    rng = _rng(seed, 11)
+    return (rng.integers(0, M, n).astype(np.int32), rng.integers(0, N, n).astype(np.int32))

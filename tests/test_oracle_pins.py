@@ -1,0 +1,436 @@
+"""Pins of the FP64 oracle against facts fixed by the paper and by mathematics.
+
+Each test names what it pins.  None re-derives an expected value by re-running
+the oracle's own formula: expected values come from the paper's worked
+example and tables, closed forms worked by hand, exact enumeration,
+finite-difference gradients, brute force on tiny inputs, or invariants.
+"""
+import itertools
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle import oracle as orc
+from paper_2111_11682_amd import synth
+
+
+# --------------------------------------------------------------------------
+# Random source
+# --------------------------------------------------------------------------
+def test_splitmix64_published_vectors(golden_dir):
+    with open(os.path.join(golden_dir, "splitmix64_seed0.txt")) as f:
+        rows = [l.split() for l in f if l.strip() and not l.startswith("#")]
+    for c, hexout in rows:
+        assert orc.splitmix64(0, int(c)) == int(hexout, 16)
+
+
+# --------------------------------------------------------------------------
+# simLSH coding, Eq. (item_hash)
+# --------------------------------------------------------------------------
+def _strings_to_words(strings):
+    words = []
+    for s in strings:
+        w = 0
+        for pos, ch in enumerate(s):     # first character = bit 0
+            if ch == "1":
+                w |= 1 << pos
+        words.append([w])
+    return np.array(words, np.uint32)
+
+
+def test_simlsh_worked_example(golden_dir):
+    ex = json.load(open(os.path.join(golden_dir, "simlsh_worked_example.json")))
+    H = _strings_to_words(ex["strings"])
+    M, N, B = len(ex["strings"]), 1, ex["G"]
+    u = np.arange(M, dtype=np.int32)
+    it = np.zeros(M, np.int32)
+    rc = np.array(ex["ratings"], np.uint8)
+    acc, sig = orc.simlsh(M, N, B, u, it, rc, H, psi_exp=ex["psi_exp"])
+    assert acc[0].tolist() == ex["sums"]
+    bits = "".join(str((int(sig[0, 0]) >> b) & 1) for b in range(B))
+    assert bits == ex["signature"]
+
+
+def test_simlsh_zero_sum_maps_to_one():
+    # Upsilon maps non-negative sums to 1 (Sec. 4.1): equal and opposite
+    # contributions give a zero sum and a set bit; psi = r^2 in the example.
+    H = np.array([[0b01], [0b10]], np.uint32)
+    acc, sig = orc.simlsh(2, 1, 2, [0, 1], [0, 0], [3, 3], H, psi_exp=2)
+    assert acc[0].tolist() == [0, 0]
+    assert int(sig[0, 0]) == 0b11
+
+
+def test_simlsh_psi_square_and_sign():
+    # one rater: every bit of the item equals the rater's bit (sum = +-psi)
+    rng = np.random.default_rng(3)
+    H = rng.integers(0, 2**32, size=(1, 2), dtype=np.uint64).astype(np.uint32)
+    acc, sig = orc.simlsh(1, 1, 64, [0], [0], [4], H, psi_exp=2)
+    assert np.array_equal(sig[0], H[0])
+    bits = np.array([(int(H[0, b // 32]) >> (b % 32)) & 1 for b in range(64)])
+    assert np.array_equal(acc[0], 16 * (2 * bits - 1))
+
+
+def _exact_bit_collision(x, y):
+    """P(sign bits of x and y agree) for uniform +-1 weights, by enumeration."""
+    n = len(x)
+    agree = 0
+    for signs in itertools.product((-1, 1), repeat=n):
+        s = np.array(signs)
+        agree += (np.dot(s, x) >= 0) == (np.dot(s, y) >= 0)
+    return agree / 2 ** n
+
+
+def test_collision_probability_matches_enumeration():
+    # Two items over a 10-user support; their bits collide with probability
+    # pi (exact by enumeration of all 2^10 sign patterns).  Bits of the hash
+    # are independent, so one band of p*G bits collides with pi^(pG) and at
+    # least one of q bands with 1 - (1 - pi^(pG))^q (Sec. 4.1 coarse/fine).
+    rng = np.random.default_rng(11)
+    M = 10
+    ra = np.array([5, 4, 0, 3, 5, 0, 2, 4, 1, 0])
+    rb = np.array([4, 5, 2, 3, 0, 1, 2, 5, 0, 3])
+    pi = _exact_bit_collision(ra ** 2, rb ** 2)
+    B = 8192
+    u = np.concatenate([np.nonzero(ra)[0], np.nonzero(rb)[0]]).astype(np.int32)
+    it = np.concatenate([np.zeros((ra > 0).sum()), np.ones((rb > 0).sum())]).astype(np.int32)
+    rc = np.concatenate([ra[ra > 0], rb[rb > 0]]).astype(np.uint8)
+    H = rng.integers(0, 2**32, size=(M, B // 32), dtype=np.uint64).astype(np.uint32)
+    _, sig = orc.simlsh(M, 2, B, u, it, rc, H, psi_exp=2)
+    eq = ~(sig[0] ^ sig[1])
+    bits = np.unpackbits(eq.view(np.uint8), bitorder="little").astype(bool)
+    n = bits.size
+    rate = bits.mean()
+    assert abs(rate - pi) <= 4 * math.sqrt(pi * (1 - pi) / n) + 1e-12
+    # band level: G = 4, p = 1 -> 2048 bands of 4 bits
+    G, p = 4, 1
+    keys = orc.band_keys(sig, B, G, p, B // (G * p))
+    band_eq = keys[0] == keys[1]
+    pb = pi ** (G * p)
+    assert abs(band_eq.mean() - pb) <= 4 * math.sqrt(pb * (1 - pb) / band_eq.size)
+    q = 4
+    groups = band_eq.reshape(-1, q).any(axis=1)
+    pq = 1 - (1 - pb) ** q
+    assert abs(groups.mean() - pq) <= 4 * math.sqrt(pq * (1 - pq) / groups.size)
+
+
+def test_identical_columns_always_collide():
+    # pi = 1 for identical psi-weighted columns; pi = 0 for opposite signs is
+    # impossible with positive psi, but disjoint supports give pi = 1/2 only
+    # up to the tie rule, so check the identical case exactly.
+    rng = np.random.default_rng(5)
+    M, B = 30, 128
+    rows = rng.choice(M, 12, replace=False).astype(np.int32)
+    r = rng.integers(1, 6, 12).astype(np.uint8)
+    H = rng.integers(0, 2**32, size=(M, B // 32), dtype=np.uint64).astype(np.uint32)
+    _, sig = orc.simlsh(M, 2, B, np.concatenate([rows, rows]),
+                        np.repeat(np.array([0, 1], np.int32), 12), np.concatenate([r, r]), H)
+    assert np.array_equal(sig[0], sig[1])
+
+
+# --------------------------------------------------------------------------
+# Banding and top-K, Sec. 4.1 / Alg. CULSH
+# --------------------------------------------------------------------------
+def _bucket_counts(keys):
+    """Collision counts by hash buckets (a different algorithm than pairwise)."""
+    N, q = keys.shape
+    counts = np.zeros((N, N), np.int64)
+    for t in range(q):
+        buckets = {}
+        for j in range(N):
+            buckets.setdefault(int(keys[j, t]), []).append(j)
+        for members in buckets.values():
+            for a in members:
+                for b in members:
+                    if a != b:
+                        counts[a, b] += 1
+    return counts
+
+
+def test_pair_counts_match_bucket_bruteforce():
+    rng = np.random.default_rng(7)
+    N, B, G, p, q = 60, 96, 4, 2, 12
+    sig = rng.integers(0, 2**32, size=(N, 3), dtype=np.uint64).astype(np.uint32)
+    sig[5] = sig[9]          # an exact duplicate item
+    sig[:, 1] &= 0x0000FFFF  # make some bands low-entropy (big buckets)
+    keys = orc.band_keys(sig, B, G, p, q)
+    ref = _bucket_counts(keys)
+    for j in range(N):
+        assert np.array_equal(orc.pair_counts(keys, j), ref[j])
+    assert orc.pair_counts(keys, 5)[9] == q
+
+
+def test_band_key_bits_lsb_first():
+    sig = np.array([[0x000000F0, 0x80000001]], np.uint32)
+    # band 0 with G=8, p=1: bits 0..7 of word 0 -> 0xF0
+    assert orc.band_keys(sig, 64, 8, 1, 8)[0, 0] == 0xF0
+    # band 3 of 8 bits starting at bit 24: 0x00 ; band 4 bits 32..39 -> 0x01
+    assert orc.band_keys(sig, 64, 8, 1, 8)[0, 3] == 0x00
+    assert orc.band_keys(sig, 64, 8, 1, 8)[0, 4] == 0x01
+    assert orc.band_keys(sig, 64, 8, 1, 8)[0, 7] == 0x80
+    # 16-bit band straddling nothing: bits 16..31 -> 0x0000
+    assert orc.band_keys(sig, 64, 8, 2, 4)[0, 1] == 0x0000
+    # 24-bit band 1 spans words 0/1: bits 24..47 -> 0x000100
+    assert orc.band_keys(sig, 64, 8, 3, 2)[0, 1] == 0x000100
+
+
+def test_topk_rule_and_fill():
+    rng = np.random.default_rng(8)
+    N, B, G, p, q, K = 40, 64, 8, 1, 8, 6
+    sig = rng.integers(0, 2**32, size=(N, 2), dtype=np.uint64).astype(np.uint32)
+    sig[3] = sig[17]
+    sig[21, 0] = sig[3, 0]              # shares bands 0..3 with items 3 and 17
+    keys = orc.band_keys(sig, B, G, p, q)
+    counts = _bucket_counts(keys)
+    seed = 1234
+    JK = orc.topk(sig, B, G, p, q, K, seed)
+    for j in range(N):
+        cand = [x for x in range(N) if counts[j, x] > 0]
+        cand.sort(key=lambda x: (-counts[j, x], x))
+        chosen = cand[:K]
+        a = 0
+        while len(chosen) < K:
+            x = orc.splitmix64(seed, (j << 32) + a + 1) % N
+            a += 1
+            if x != j and x not in chosen:
+                chosen.append(x)
+        assert JK[j].tolist() == sorted(chosen), j
+    assert 17 in JK[3] and 21 in JK[3]
+    assert all(j not in JK[j] for j in range(N))
+
+
+def test_lsh_recall_beats_random_and_grows_with_q():
+    # Planted clusters: LSH neighbours must agree with the brute-force
+    # cosine and GSM top-K far more often than random lists (K/(N-1)),
+    # and recall must not drop when q grows (Sec. 4.1 amplification).
+    w = synth.WORKLOADS["tiny"]
+    d = synth.generate(w)
+    M, N, K = w.M, w.N, 6
+    u, it, rc = d["train_u"], d["train_i"], d["train_rc"]
+    rng = np.random.default_rng(1)
+    cos_top = orc.topk_by_score(orc.cosine_psi(M, N, u, it, rc), K)
+    gsm_top = orc.topk_by_score(orc.gsm(M, N, u, it, rc, w.rscale), K)
+    rand = K / (N - 1)
+    rec = {}
+    for q in (4, 32):
+        B = 8 * q
+        H = rng.integers(0, 2**32, size=(M, B // 32), dtype=np.uint64).astype(np.uint32)
+        _, sig = orc.simlsh(M, N, B, u, it, rc, H)
+        JK = orc.topk(sig, B, 8, 1, q, K, 99)
+        rc_cos = np.mean([len(set(JK[j]) & set(cos_top[j])) / K for j in range(N)])
+        rc_gsm = np.mean([len(set(JK[j]) & set(gsm_top[j])) / K for j in range(N)])
+        rec[q] = (rc_cos, rc_gsm)
+    assert rec[32][0] > 3 * rand
+    assert rec[32][1] > 1.5 * rand
+    assert rec[32][0] >= rec[4][0]
+
+
+def test_space_table_reproduced(golden_dir):
+    t = json.load(open(os.path.join(golden_dir, "space_table.json")))
+    # the table prints three decimals, sometimes rounded, sometimes truncated
+    for name, N in t["N"].items():
+        assert abs(orc.space_mib_gsm(N) - t["gsm_mb"][name]) < 1e-3
+        assert abs(orc.space_mib_simlsh(N, 3, 100) - t["simlsh_p3_q100_mb"][name]) < 1e-3
+        assert abs(orc.space_mib_simlsh(N, 3, 200) - t["simlsh_p3_q200_mb"][name]) < 1e-3
+
+
+# --------------------------------------------------------------------------
+# Prediction, Eq. (rr), closed forms worked by hand
+# --------------------------------------------------------------------------
+def _hand_model():
+    # 2 users x 3 items, integer ratings: u0 rated i0=4, i1=2; u1 rated i1=5, i2=3
+    u = np.array([0, 0, 1, 1], np.int32)
+    it = np.array([0, 1, 1, 2], np.int32)
+    rc = np.array([4, 2, 5, 3], np.uint8)
+    JK = np.array([[1, 2], [0, 2], [0, 1]], np.int32)
+    U0 = np.array([[1.0, 2.0], [0.5, -1.0]])
+    V0 = np.array([[0.2, 0.1], [-0.3, 0.4], [0.0, 0.5]])
+    W0 = np.array([[0.5, -0.25], [0.2, 0.4], [1.0, -1.0]])
+    C0 = np.array([[0.1, 0.2], [0.3, -0.3], [0.05, 0.15]])
+    m = orc.Model(2, 3, 2, 2, 1, u, it, rc, JK, U0, V0, W0=W0, C0=C0,
+                  bu0=np.array([0.1, -0.2]), bv0=np.array([0.3, 0.0, -0.1]))
+    return m
+
+
+def test_baselines_simple_case():
+    m = _hand_model()
+    # mu = (4+2+5+3)/4; row means 3, 4; column means 4, 3.5, 3
+    assert m.mu == 3.5
+    assert m.b0.tolist() == [-0.5, 0.5]
+    assert m.bh0.tolist() == [0.5, 0.0, -0.5]
+
+
+def test_predict_closed_form():
+    m = _hand_model()
+    # (u0, i2): base 3.5+0.1-0.1 = 3.5; u.v = 1.0; both neighbours {0,1} rated:
+    #   resid(i0) = 4-(3.5-0.5+0.5) = 0.5, resid(i1) = 2-(3.5-0.5+0) = -1
+    #   w-term = (0.5*1.0 + (-1)*(-1.0)) / sqrt(2); no c-term
+    # (u1, i0): base 3.6; u.v = 0; neighbours {1,2} rated: resid 1.0, -0.5
+    #   w-term = (1.0*0.5 + (-0.5)*(-0.25)) / sqrt(2)
+    # (u0, i1): base 3.6; u.v = 0.5; neighbour 0 rated (resid 0.5, w=0.2),
+    #   neighbour 2 not rated (c=-0.3); both sides have one member
+    # (u1, i1): base 3.3; u.v = -0.55; neighbour 2 rated (resid -0.5, w=0.4),
+    #   neighbour 0 not rated (c=0.3)
+    expect = [3.5 + 1.0 + 1.5 / math.sqrt(2),
+              3.6 + 0.0 + 0.625 / math.sqrt(2),
+              3.6 + 0.5 + 0.1 - 0.3,
+              3.3 - 0.55 - 0.2 + 0.3]
+    got = m.predict([0, 1, 0, 1], [2, 0, 1, 1])
+    assert np.allclose(got, expect, rtol=0, atol=1e-14)
+
+
+def test_predict_reduces_to_biased_mf_when_w_c_zero():
+    w = synth.WORKLOADS["tiny"]
+    d = synth.generate(w)
+    rng = np.random.default_rng(2)
+    JK = np.sort(np.stack([rng.choice(np.delete(np.arange(w.N), j), w.K, replace=False)
+                           for j in range(w.N)]), axis=1)
+    m = orc.Model(w.M, w.N, w.F, w.K, w.rscale, d["train_u"], d["train_i"], d["train_rc"],
+                  JK, d["U0"], d["V0"], bu0=rng.normal(size=w.M), bv0=rng.normal(size=w.N))
+    qu, qi = synth.random_queries(w.M, w.N, 500, 3)
+    ref = m.mu + m.bu[qu] + m.bv[qi] + np.einsum("nf,nf->n", m.U[qu], m.V[qi])
+    assert np.allclose(m.predict(qu, qi), ref, rtol=0, atol=1e-12)
+
+
+def test_predict_no_c_term_when_all_neighbours_rated():
+    m = _hand_model()
+    base = m.predict([0], [2])[0]
+    m.C[2] = 123.0          # item 2's implicit weights are unused for u0
+    assert m.predict([0], [2])[0] == base
+    m.W[2] = 0.0            # ... and the w-term is its only neighbour term
+    assert m.predict([0], [2])[0] == pytest.approx(3.5 + 1.0, abs=1e-14)
+
+
+# --------------------------------------------------------------------------
+# SGD update, Eq. (sgd_update) = -gamma/2 * gradient of Eq. (loss_r) terms
+# --------------------------------------------------------------------------
+def test_sgd_step_is_half_gradient_of_sample_loss():
+    base = _hand_model()
+    g = np.array([0.01, 0.02, 0.03, 0.04, 0.05, 0.06])
+    lam = np.array([0.1, 0.2, 0.3, 0.4, 0.5, 0.6])
+    for (i, j, r) in [(0, 1, 2), (1, 1, 5), (1, 2, 3), (0, 0, 4)]:
+        m0 = _hand_model()
+        m1 = _hand_model()
+        m1.sgd_one(i, j, r, g, lam)
+        e = r - m0.predict([i], [j])[0]
+        groups = [("bu", i, None, 0), ("bv", j, None, 1), ("U", i, slice(None), 2),
+                  ("V", j, slice(None), 3), ("W", j, slice(None), 4), ("C", j, slice(None), 5)]
+        for name, row, cols, gi in groups:
+            before = getattr(m0, name)
+            after = getattr(m1, name)
+            idxs = [(row,)] if cols is None else [(row, c) for c in range(before.shape[1])]
+            for idx in idxs:
+                h = 1e-6
+                mp, mm = _hand_model(), _hand_model()
+                getattr(mp, name)[idx] += h
+                getattr(mm, name)[idx] -= h
+                drhat = (mp.predict([i], [j])[0] - mm.predict([i], [j])[0]) / (2 * h)
+                theta = before[idx]
+                # d/dtheta [ (r - rhat)^2 + lam theta^2 ] = -2 e drhat + 2 lam theta
+                half_grad = -e * drhat + lam[gi] * theta
+                if name in ("W", "C") and abs(drhat) < 1e-9:
+                    expect = theta          # slot outside R^K / N^K: untouched
+                else:
+                    expect = theta - g[gi] * half_grad
+                assert after[idx] == pytest.approx(expect, abs=1e-8), (name, idx)
+        # untouched rows stay
+        other = 1 - i
+        assert np.array_equal(m1.U[other], m0.U[other])
+    del base
+
+
+def test_sgd_frozen_sides():
+    g = np.full(6, 0.05)
+    lam = np.full(6, 0.1)
+    m0, mu_, mi_ = _hand_model(), _hand_model(), _hand_model()
+    mu_.sgd_one(1, 1, 5, g, lam, upd=1)     # user side only
+    mi_.sgd_one(1, 1, 5, g, lam, upd=2)     # item side only
+    assert np.array_equal(mu_.V, m0.V) and np.array_equal(mu_.W, m0.W) and \
+        np.array_equal(mu_.C, m0.C) and np.array_equal(mu_.bv, m0.bv)
+    assert not np.array_equal(mu_.U, m0.U)
+    assert np.array_equal(mi_.U, m0.U) and np.array_equal(mi_.bu, m0.bu)
+    assert not np.array_equal(mi_.V, m0.V)
+
+
+def test_learning_rate_schedule():
+    g, _ = orc.rates_for_epoch([0.035] * 6, [0.02] * 6, 0.3, 0)
+    assert np.allclose(g, 0.035)
+    g, _ = orc.rates_for_epoch([0.035] * 6, [0.02] * 6, 0.3, 4)
+    assert np.allclose(g, 0.035 / (1 + 0.3 * 8.0))     # 4^1.5 = 8
+
+
+# --------------------------------------------------------------------------
+# Stratified order: block independence and monotone loss
+# --------------------------------------------------------------------------
+def _model_for(wname, P=None):
+    w = synth.WORKLOADS[wname]
+    d = synth.generate(w)
+    _, sig = orc.simlsh(w.M, w.N, w.B, d["train_u"], d["train_i"], d["train_rc"], d["H"])
+    JK = orc.topk(sig, w.B, w.G, w.p, w.q, w.K, 77)
+    m = orc.Model(w.M, w.N, w.F, w.K, w.rscale, d["train_u"], d["train_i"], d["train_rc"],
+                  JK, d["U0"], d["V0"])
+    return w, d, m
+
+
+def test_schedule_blocks_are_conflict_free():
+    w = synth.WORKLOADS["small"]
+    d = synth.generate(w)
+    P = 8
+    order, blk = orc.schedule(P, d["train_u"], d["train_i"])
+    assert np.array_equal(np.sort(order), np.arange(d["train_u"].size))
+    for s in range(P):
+        users, items = set(), set()
+        for b in range(P):
+            sl = order[blk[s * P + b]: blk[s * P + b + 1]]
+            bu = set(d["train_u"][sl].tolist())
+            bi = set(d["train_i"][sl].tolist())
+            assert not (bu & users) and not (bi & items)
+            users |= bu
+            items |= bi
+            assert all(x % P == b for x in bu)
+            assert all(x % P == (b + s) % P for x in bi)
+            jj = d["train_i"][sl].astype(np.int64) * w.M + d["train_u"][sl]
+            assert np.all(np.diff(jj) > 0)            # (j asc, i asc) inside a block
+
+
+def test_block_order_invariance_bit_exact():
+    w, d, m1 = _model_for("small")
+    _, _, m2 = _model_for("small")
+    for t in range(2):
+        m1.sgd_epoch(w.n_strata, w.alpha, w.lam, w.beta, t, reverse_blocks=False)
+        m2.sgd_epoch(w.n_strata, w.alpha, w.lam, w.beta, t, reverse_blocks=True)
+    for a in ("U", "V", "bu", "bv", "W", "C"):
+        assert np.array_equal(getattr(m1, a), getattr(m2, a)), a
+
+
+def test_monotone_loss_ml100k():
+    # five epochs of the 943 x 1682 case in deterministic stratified order
+    w, d, m = _model_for("ml100k")
+    losses = [m.loss(w.lam)]
+    for t in range(w.epochs):
+        m.sgd_epoch(w.n_strata, w.alpha, w.lam, w.beta, t)
+        losses.append(m.loss(w.lam))
+    assert all(b < a for a, b in zip(losses, losses[1:])), losses
+    r = m.rmse(d["test_u"], d["test_i"], d["test_rc"])
+    assert 0.5 < r < 1.5
+
+
+def test_lsh_neighbours_not_worse_than_random():
+    # Table of top-K methods: RMSE with simLSH neighbours <= RMSE with random
+    w = synth.WORKLOADS["small"]
+    d = synth.generate(w)
+    _, sig = orc.simlsh(w.M, w.N, w.B, d["train_u"], d["train_i"], d["train_rc"], d["H"])
+    JK = orc.topk(sig, w.B, w.G, w.p, w.q, w.K, 5)
+    rng = np.random.default_rng(4)
+    JR = np.sort(np.stack([rng.choice(np.delete(np.arange(w.N), j), w.K, replace=False)
+                           for j in range(w.N)]), axis=1)
+    res = {}
+    for name, J in (("lsh", JK), ("rand", JR)):
+        m = orc.Model(w.M, w.N, w.F, w.K, w.rscale, d["train_u"], d["train_i"], d["train_rc"],
+                      J, d["U0"], d["V0"])
+        for t in range(6):
+            m.sgd_epoch(w.n_strata, w.alpha, w.lam, w.beta, t)
+        res[name] = m.rmse(d["test_u"], d["test_i"], d["test_rc"])
+    assert res["lsh"] <= res["rand"] + 1e-3, res
