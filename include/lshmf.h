@@ -1,0 +1,184 @@
+/*
+ * liblshmf -- LSH-aggregated neighbourhood matrix factorisation on MI355X.
+ *
+ * C ABI of the HIP library.  Every entry point is asynchronous on the
+ * caller's HIP stream, returns LSHMF_OK (0) or a negative status, and never
+ * lets a C++ exception cross the boundary.  lshmf_last_error() returns a
+ * thread-local message for the last failure.
+ *
+ * Ownership: the caller owns all device memory.  The library allocates no
+ * device memory at all; it carves its internal buffers out of one caller
+ * supplied arena whose size lshmf_arena_bytes() reports.  Host memory is used
+ * only for the opaque context object.  All pointers named d_* are device
+ * pointers; layouts are row-major and dense unless stated otherwise.
+ *
+ * Notation follows the paper (arXiv 2111.11682, Table "symbols"):
+ * M users (rows, set I), N items (columns, set J), F factor rank, K
+ * neighbours per item, ratings r_ij.  Ratings travel as integer codes
+ * rc = rscale * r (rscale 1: integer ratings 1..5; rscale 2: half-steps
+ * 0.5..5.0), so rc is in 1..15.
+ */
+#ifndef LSHMF_H
+#define LSHMF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ihipStream_t* lshmf_stream_t; /* hipStream_t; NULL = default stream */
+
+enum {
+    LSHMF_OK = 0,
+    LSHMF_EINVAL = -1,    /* bad dimensions, null pointer, id out of range   */
+    LSHMF_ESTATE = -2,    /* call order violated (e.g. sgd before neighbours) */
+    LSHMF_ECAPACITY = -3, /* arena too small or a block too large for LDS     */
+    LSHMF_EDEVICE = -4    /* a HIP runtime error; message has its string      */
+};
+
+enum { LSHMF_FP32 = 0, LSHMF_BF16 = 1 };
+
+typedef struct lshmf_dims {
+    int32_t M, N;      /* users, items                                       */
+    int32_t F;         /* rank of U (M x F) and V (N x F), 1..256            */
+    int32_t K;         /* neighbours per item, 1..128, K <= N - 1            */
+    int32_t G, p, q;   /* simLSH: G bits per hash, p hashes ANDed per band,
+                          q bands ORed (Sec. 4.1); B = G*p*q <= 256 bits,
+                          band width p*G <= 32                               */
+    int32_t rscale;    /* rating code scale, 1 or 2                          */
+    int32_t psi_exp;   /* Psi(r) = rc^psi_exp in the hash sums (2: Psi = r^2) */
+    int32_t n_strata;  /* P: users and items split into P blocks by id mod P */
+    int32_t storage;   /* LSHMF_FP32 (BF16 reserved)                         */
+    int32_t reserved;
+    int64_t nnz;       /* training ratings                                   */
+} lshmf_dims;
+
+/* Learning rates alpha and regularisers lambda, in the order
+ * (b_i, bh_j, u_i, v_j, w_j, c_j) of Eq. (sgd_update); the rate of epoch t is
+ * alpha / (1 + beta * t^1.5), Eq. (learn_rate). */
+typedef struct lshmf_hparams {
+    float alpha[6];
+    float lambda[6];
+    float beta;
+    int32_t reserved;
+} lshmf_hparams;
+
+/* Model tables: caller-owned device buffers, FP32, row-major.
+ *   U  [M*F]   V  [N*F]          factor rows u_i, v_j              (Eq. rr, part 4)
+ *   bu [M]     bv [N]            learned deviations b_i, bh_j       (Eq. rr, part 1)
+ *   W  [N*K]   C  [N*K]          explicit / implicit influence w_j, c_j, slot k
+ *                                 refers to neighbour JK[j*K + k]    (Eq. rr, parts 2, 3)
+ *   JK [N*K]   int32             top-K neighbours, ascending ids per row
+ *   acc[N*B]   int32             simLSH pre-sign sums (kept for online learning)
+ *   sig[N*ceil(B/32)] uint32     simLSH signatures, bit b at word b/32, bit b%32
+ *   b0 [M]     bh0 [N]           fixed baseline deviations of the "simple case"
+ *   mu [1]     double            global mean
+ * U, V, bu, bv, W, C are read and written by sgd_epoch; the caller initialises
+ * them (the paper's Alg. CULSH-MF takes the initial values as input). */
+typedef struct lshmf_tables {
+    float* U;
+    float* V;
+    float* bu;
+    float* bv;
+    float* W;
+    float* C;
+    int32_t* JK;
+    int32_t* acc;
+    uint32_t* sig;
+    float* b0;
+    float* bh0;
+    double* mu;
+} lshmf_tables;
+
+typedef struct lshmf_ctx lshmf_ctx; /* opaque, host memory */
+
+/* Creates a context for the given dimensions (validated here). */
+int lshmf_create(const lshmf_dims* dims, lshmf_ctx** out);
+void lshmf_destroy(lshmf_ctx* ctx);
+
+/* Device bytes the library needs for its layout and scratch buffers. */
+int lshmf_arena_bytes(const lshmf_ctx* ctx, size_t* bytes);
+
+/* Binds caller-owned tables and arena (device pointers, 256-byte aligned
+ * arena).  The pointers must stay valid until the context is destroyed. */
+int lshmf_bind(lshmf_ctx* ctx, const lshmf_tables* tables, void* d_arena, size_t arena_bytes);
+
+/* Ingest and layout of the training ratings (COO, d_u[n], d_i[n], d_rc[n],
+ * n = dims.nnz, each (u, i) pair at most once): CSR by user, CSC by item,
+ * the stratified block stream and the fixed baselines mu, b0, bh0 (Sec. 3.2,
+ * the "simple case" means, reduced in FP64).  Ids outside [0,M) x [0,N) give
+ * LSHMF_EINVAL after a stream synchronisation. */
+int lshmf_ingest(lshmf_ctx* ctx, const int32_t* d_u, const int32_t* d_i, const uint8_t* d_rc,
+                 int64_t n, lshmf_stream_t stream);
+
+/* simLSH neighbours without the N x N similarity matrix (Sec. 4.1, Eq.
+ * item_hash and Alg. CULSH): pre-sign sums acc = sum Psi(r) (2 H_i - 1),
+ * signatures, q band keys of p*G bits, bucket collisions counted per item,
+ * the K most frequent partners (ties by smaller id), a seeded random
+ * supplement when fewer than K exist (SplitMix64(seed_fill, j*2^32 + a + 1)
+ * mod N, a = 0, 1, ...), rows stored by ascending id.  d_H holds the random
+ * user strings H_i, M rows of ceil(B/32) uint32 words.  Also resolves, for
+ * every training rating (i, j), which neighbours of j user i has rated.
+ * Requires lshmf_ingest. */
+int build_lsh_neighbours(lshmf_ctx* ctx, const uint32_t* d_H, uint64_t seed_fill,
+                         lshmf_stream_t stream);
+
+/* One SGD epoch t (0-based) over all training ratings in the stratified
+ * order: stratum s = 0..P-1 runs the P blocks (b, (b+s) mod P) of users
+ * i mod P = b and items j mod P = (b+s) mod P; inside a block, items
+ * ascending and users ascending within an item.  Each rating applies Eq.
+ * (sgd_update) with the prediction of Eq. (rr), N(i) the complement of R(i)
+ * (the CULSH-MF adjustment), and the residual baseline of the w-term fixed to
+ * the simple-case means.  Results do not depend on how blocks are scheduled.
+ * Requires build_lsh_neighbours. */
+int sgd_epoch(lshmf_ctx* ctx, const lshmf_hparams* hp, int32_t epoch, lshmf_stream_t stream);
+
+/* Eq. (rr) for n query pairs (d_u[x], d_i[x]) -> d_out[x] (FP32), with R(i)
+ * the user's training items.  Ids out of range give NaN for that query. */
+int predict(lshmf_ctx* ctx, const int32_t* d_u, const int32_t* d_i, int64_t n, float* d_out,
+            lshmf_stream_t stream);
+
+/* RMSE of predictions against rating codes (Sec. 5.1), reduced in FP64 in a
+ * fixed order: d_out[0] = sqrt(sum (rc/rscale - pred)^2 / n). */
+int lshmf_rmse(lshmf_ctx* ctx, const float* d_pred, const uint8_t* d_rc, int64_t n,
+               double* d_out, lshmf_stream_t stream);
+
+/* Read-only device pointers into the arena, for inspection and tests: the
+ * stratified stream (pk = user << 4 | code, sj = item, dep = previous rating
+ * of the same user in the block or -1, nib = K 4-bit neighbour codes per
+ * rating, nstride bytes each), block and segment ranges, and the CSR / CSC
+ * copies of the training set.  Valid after lshmf_ingest (nib after
+ * build_lsh_neighbours) until the next lshmf_bind. */
+typedef struct lshmf_layout {
+    const uint32_t* pk;
+    const int32_t* sj;
+    const int32_t* dep;
+    const uint8_t* nib;
+    const int64_t* blk_ptr;   /* P*P + 1, block b of stratum s at s*P + b */
+    const int64_t* blk_seg;   /* P*P + 1 */
+    const int32_t* seg_col;
+    const int64_t* seg_start;
+    const int64_t* row_ptr;   /* M + 1 */
+    const int32_t* csr_col;
+    const uint8_t* csr_rc;
+    const int64_t* col_ptr;   /* N + 1 */
+    const int32_t* csc_row;
+    const uint8_t* csc_rc;
+    const int32_t* err;       /* device status word: 0 while healthy; bit 1 set if
+                                 an SGD dependency wait hit its spin limit */
+    int32_t nstride;
+    int32_t P;
+} lshmf_layout;
+
+int lshmf_export_layout(const lshmf_ctx* ctx, lshmf_layout* out);
+
+/* Thread-local message describing the last non-OK status. */
+const char* lshmf_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LSHMF_H */

@@ -1,0 +1,307 @@
+// C ABI of liblshmf: validation, arena layout and the entry points declared
+// in include/lshmf.h.  No C++ exception crosses this boundary.
+#include <cstring>
+#include <new>
+
+#include "common.hpp"
+
+namespace lshmf {
+const char* last_error();
+int ingest(lshmf_ctx* c, const int32_t* u, const int32_t* it, const uint8_t* rc, int64_t n, hipStream_t s);
+int build_neighbours(lshmf_ctx* c, const uint32_t* H, uint64_t seed_fill, hipStream_t s);
+int run_sgd_epoch(lshmf_ctx* c, const lshmf_hparams* hp, int epoch, hipStream_t s);
+int run_predict(lshmf_ctx* c, const int32_t* qu, const int32_t* qi, int64_t n, float* out, hipStream_t s);
+int run_rmse(lshmf_ctx* c, const float* pred, const uint8_t* rc, int64_t n, double* out, hipStream_t s);
+
+namespace {
+
+struct Carver {
+    char* base;
+    size_t off = 0;
+    template <typename T>
+    T* take(size_t count)
+    {
+        off = (off + 255) & ~size_t(255);
+        T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+        off += count * sizeof(T);
+        return p;
+    }
+};
+
+// One walk over the arena, used both to size it (base == nullptr) and to
+// assign the regions.
+size_t carve(lshmf_ctx* c, char* base)
+{
+    const lshmf_dims& d = c->d;
+    const int64_t nnz = d.nnz, P = c->P, nq = (int64_t)d.q * d.N;
+    Carver k{base};
+    c->row_ptr = k.take<int64_t>(d.M + 1);
+    c->csr_col = k.take<int32_t>(nnz);
+    c->csr_rc = k.take<uint8_t>(nnz);
+    c->col_ptr = k.take<int64_t>(d.N + 1);
+    c->csc_row = k.take<int32_t>(nnz);
+    c->csc_rc = k.take<uint8_t>(nnz);
+    c->pk = k.take<uint32_t>(nnz);
+    c->sj = k.take<int32_t>(nnz);
+    c->dep = k.take<int32_t>(nnz);
+    c->nib = k.take<uint8_t>((size_t)nnz * c->nstride);
+    c->blk_ptr = k.take<int64_t>(P * P + 1);
+    c->blk_seg = k.take<int64_t>(P * P + 1);
+    c->seg_col = k.take<int32_t>(nnz);
+    c->seg_start = k.take<int64_t>(nnz + 1);
+    c->csr_spos = k.take<int32_t>(nnz);
+    int64_t cn = nnz;
+    if (d.M > cn) cn = d.M;
+    if (d.N > cn) cn = d.N;
+    if (P * P > cn) cn = P * P;
+    if (nq > cn) cn = nq;
+    c->cnt = k.take<int64_t>(cn + 2);
+    c->sort_n = (nnz > nq ? nnz : nq) + 2;
+    c->sk[0] = k.take<uint64_t>(c->sort_n);
+    c->sk[1] = k.take<uint64_t>(c->sort_n);
+    c->sv[0] = k.take<uint32_t>(c->sort_n);
+    c->sv[1] = k.take<uint32_t>(c->sort_n);
+    const size_t hist_n = radix_hist_elems(c->sort_n);
+    c->hist = k.take<int64_t>(hist_n);
+    size_t scan_n = scan_tmp_elems((int64_t)hist_n);
+    const size_t scan_n2 = scan_tmp_elems(c->sort_n);
+    if (scan_n2 > scan_n) scan_n = scan_n2;
+    c->scan_tmp = k.take<int64_t>(scan_n);
+    c->red = k.take<double>(1024);
+    c->bitem = k.take<int32_t>(nq);
+    c->bbegin = k.take<int32_t>(nq + 1);
+    c->bpos = k.take<int32_t>(nq);
+    c->err = k.take<int32_t>(64);
+    return (k.off + 255) & ~size_t(255);
+}
+
+int validate(const lshmf_dims* d)
+{
+    if (!d) {
+        set_error("dims is NULL");
+        return LSHMF_EINVAL;
+    }
+    const int64_t B = (int64_t)d->G * d->p * d->q;
+    if (d->M < 1 || d->N < 2 || d->M >= (1 << 28)) {
+        set_error("need 1 <= M < 2^28 and N >= 2 (M=%d N=%d)", d->M, d->N);
+        return LSHMF_EINVAL;
+    }
+    if (d->F < 1 || d->F > 256) {
+        set_error("F=%d outside 1..256", d->F);
+        return LSHMF_EINVAL;
+    }
+    if (d->K < 1 || d->K > 128 || d->K > d->N - 1) {
+        set_error("K=%d outside 1..min(128, N-1)", d->K);
+        return LSHMF_EINVAL;
+    }
+    if (d->G < 1 || d->p < 1 || d->q < 1 || B > 256 || (int64_t)d->G * d->p > 32 || d->q > 2048) {
+        set_error("simLSH shape G=%d p=%d q=%d: need G*p*q <= 256, G*p <= 32", d->G, d->p, d->q);
+        return LSHMF_EINVAL;
+    }
+    if (d->rscale != 1 && d->rscale != 2) {
+        set_error("rscale=%d must be 1 or 2", d->rscale);
+        return LSHMF_EINVAL;
+    }
+    if (d->psi_exp < 1 || d->psi_exp > 4) {
+        set_error("psi_exp=%d outside 1..4", d->psi_exp);
+        return LSHMF_EINVAL;
+    }
+    // |acc| <= M * 15^psi_exp must fit int32
+    double bound = (double)d->M;
+    for (int e = 0; e < d->psi_exp; ++e) bound *= 15.0;
+    if (bound >= 2147483647.0) {
+        set_error("M * 15^psi_exp overflows the int32 hash sums");
+        return LSHMF_EINVAL;
+    }
+    if (d->n_strata < 1 || d->n_strata > 4096) {
+        set_error("n_strata=%d outside 1..4096", d->n_strata);
+        return LSHMF_EINVAL;
+    }
+    if (d->storage != LSHMF_FP32) {
+        set_error("only LSHMF_FP32 storage is available");
+        return LSHMF_EINVAL;
+    }
+    if (d->nnz < 0 || d->nnz >= ((int64_t)1 << 31)) {
+        set_error("nnz=%lld outside [0, 2^31)", (long long)d->nnz);
+        return LSHMF_EINVAL;
+    }
+    return LSHMF_OK;
+}
+
+}  // namespace
+}  // namespace lshmf
+
+using namespace lshmf;
+
+extern "C" {
+
+int lshmf_create(const lshmf_dims* dims, lshmf_ctx** out)
+{
+    if (!out) {
+        set_error("out is NULL");
+        return LSHMF_EINVAL;
+    }
+    *out = nullptr;
+    LSHMF_TRY(validate(dims));
+    lshmf_ctx* c = new (std::nothrow) lshmf_ctx();
+    if (!c) {
+        set_error("out of host memory");
+        return LSHMF_EINVAL;
+    }
+    c->d = *dims;
+    c->B = dims->G * dims->p * dims->q;
+    c->words = (c->B + 31) / 32;
+    c->pG = dims->G * dims->p;
+    c->P = dims->n_strata;
+    c->nstride = (((dims->K + 1) / 2) + 3) & ~3;
+    carve(c, nullptr);
+    *out = c;
+    return LSHMF_OK;
+}
+
+void lshmf_destroy(lshmf_ctx* ctx) { delete ctx; }
+
+int lshmf_arena_bytes(const lshmf_ctx* ctx, size_t* bytes)
+{
+    if (!ctx || !bytes) {
+        set_error("NULL argument");
+        return LSHMF_EINVAL;
+    }
+    lshmf_ctx tmp = *ctx;
+    *bytes = carve(&tmp, nullptr);
+    return LSHMF_OK;
+}
+
+int lshmf_bind(lshmf_ctx* ctx, const lshmf_tables* t, void* d_arena, size_t arena_bytes)
+{
+    if (!ctx || !t || !d_arena) {
+        set_error("NULL argument");
+        return LSHMF_EINVAL;
+    }
+    if (!t->U || !t->V || !t->bu || !t->bv || !t->W || !t->C || !t->JK || !t->acc || !t->sig || !t->b0 ||
+        !t->bh0 || !t->mu) {
+        set_error("a table pointer is NULL");
+        return LSHMF_EINVAL;
+    }
+    if (reinterpret_cast<uintptr_t>(d_arena) & 255) {
+        set_error("arena must be 256-byte aligned");
+        return LSHMF_EINVAL;
+    }
+    const size_t need = carve(ctx, nullptr);
+    if (arena_bytes < need) {
+        set_error("arena of %zu bytes, need %zu", arena_bytes, need);
+        return LSHMF_ECAPACITY;
+    }
+    carve(ctx, static_cast<char*>(d_arena));
+    ctx->t = *t;
+    ctx->bound = true;
+    ctx->ingested = ctx->neighbours = false;
+    return LSHMF_OK;
+}
+
+int lshmf_ingest(lshmf_ctx* ctx, const int32_t* d_u, const int32_t* d_i, const uint8_t* d_rc, int64_t n,
+                 lshmf_stream_t stream)
+{
+    if (!ctx || !ctx->bound) {
+        set_error("context not bound");
+        return LSHMF_ESTATE;
+    }
+    if (n != ctx->d.nnz) {
+        set_error("ingest: n=%lld differs from dims.nnz=%lld", (long long)n, (long long)ctx->d.nnz);
+        return LSHMF_EINVAL;
+    }
+    if (n > 0 && (!d_u || !d_i || !d_rc)) {
+        set_error("ingest: NULL rating array");
+        return LSHMF_EINVAL;
+    }
+    ctx->ingested = ctx->neighbours = false;
+    LSHMF_TRY(ingest(ctx, d_u, d_i, d_rc, n, reinterpret_cast<hipStream_t>(stream)));
+    ctx->ingested = true;
+    return LSHMF_OK;
+}
+
+int build_lsh_neighbours(lshmf_ctx* ctx, const uint32_t* d_H, uint64_t seed_fill, lshmf_stream_t stream)
+{
+    if (!ctx || !ctx->ingested) {
+        set_error("build_lsh_neighbours: ratings not ingested");
+        return LSHMF_ESTATE;
+    }
+    if (!d_H) {
+        set_error("build_lsh_neighbours: H is NULL");
+        return LSHMF_EINVAL;
+    }
+    LSHMF_TRY(build_neighbours(ctx, d_H, seed_fill, reinterpret_cast<hipStream_t>(stream)));
+    ctx->neighbours = true;
+    return LSHMF_OK;
+}
+
+int sgd_epoch(lshmf_ctx* ctx, const lshmf_hparams* hp, int32_t epoch, lshmf_stream_t stream)
+{
+    if (!ctx || !ctx->neighbours) {
+        set_error("sgd_epoch: neighbours not built");
+        return LSHMF_ESTATE;
+    }
+    if (!hp || epoch < 0) {
+        set_error("sgd_epoch: bad hyper-parameters or epoch");
+        return LSHMF_EINVAL;
+    }
+    return run_sgd_epoch(ctx, hp, epoch, reinterpret_cast<hipStream_t>(stream));
+}
+
+int predict(lshmf_ctx* ctx, const int32_t* d_u, const int32_t* d_i, int64_t n, float* d_out,
+            lshmf_stream_t stream)
+{
+    if (!ctx || !ctx->neighbours) {
+        set_error("predict: neighbours not built");
+        return LSHMF_ESTATE;
+    }
+    if (n < 0 || (n > 0 && (!d_u || !d_i || !d_out))) {
+        set_error("predict: bad query arrays");
+        return LSHMF_EINVAL;
+    }
+    return run_predict(ctx, d_u, d_i, n, d_out, reinterpret_cast<hipStream_t>(stream));
+}
+
+int lshmf_rmse(lshmf_ctx* ctx, const float* d_pred, const uint8_t* d_rc, int64_t n, double* d_out,
+               lshmf_stream_t stream)
+{
+    if (!ctx || !ctx->bound) {
+        set_error("lshmf_rmse: context not bound");
+        return LSHMF_ESTATE;
+    }
+    if (n < 0 || !d_out || (n > 0 && (!d_pred || !d_rc))) {
+        set_error("lshmf_rmse: bad arguments");
+        return LSHMF_EINVAL;
+    }
+    return run_rmse(ctx, d_pred, d_rc, n, d_out, reinterpret_cast<hipStream_t>(stream));
+}
+
+int lshmf_export_layout(const lshmf_ctx* ctx, lshmf_layout* out)
+{
+    if (!ctx || !out || !ctx->bound) {
+        set_error("lshmf_export_layout: context not bound");
+        return LSHMF_ESTATE;
+    }
+    out->pk = ctx->pk;
+    out->sj = ctx->sj;
+    out->dep = ctx->dep;
+    out->nib = ctx->nib;
+    out->blk_ptr = ctx->blk_ptr;
+    out->blk_seg = ctx->blk_seg;
+    out->seg_col = ctx->seg_col;
+    out->seg_start = ctx->seg_start;
+    out->row_ptr = ctx->row_ptr;
+    out->csr_col = ctx->csr_col;
+    out->csr_rc = ctx->csr_rc;
+    out->col_ptr = ctx->col_ptr;
+    out->csc_row = ctx->csc_row;
+    out->csc_rc = ctx->csc_rc;
+    out->err = ctx->err;
+    out->nstride = ctx->nstride;
+    out->P = ctx->P;
+    return LSHMF_OK;
+}
+
+const char* lshmf_last_error(void) { return lshmf::last_error(); }
+
+}  // extern "C"

@@ -1,0 +1,108 @@
+// Internal declarations shared by the HIP sources of liblshmf.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "lshmf.h"
+
+namespace lshmf {
+
+constexpr int kWave = 64;
+
+// ---------------------------------------------------------------- errors
+void set_error(const char* fmt, ...);
+int hip_fail(hipError_t e, const char* what);
+
+#define LSHMF_TRY(expr)                                   \
+    do {                                                  \
+        int st_ = (expr);                                 \
+        if (st_ != LSHMF_OK) return st_;                  \
+    } while (0)
+
+#define LSHMF_HIP(expr)                                   \
+    do {                                                  \
+        hipError_t e_ = (expr);                           \
+        if (e_ != hipSuccess) return ::lshmf::hip_fail(e_, #expr); \
+    } while (0)
+
+#define LSHMF_LAUNCHED(name)                              \
+    do {                                                  \
+        hipError_t e_ = hipGetLastError();                \
+        if (e_ != hipSuccess) return ::lshmf::hip_fail(e_, name); \
+    } while (0)
+
+inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+inline int bits_for(uint64_t v)  // bits needed to represent values in [0, v)
+{
+    int b = 0;
+    while (b < 64 && (v - 1) >> b) ++b;
+    return b;
+}
+
+// ------------------------------------------------------- device primitives
+// Exclusive prefix sum of n int64 values; out has n+1 entries, out[n] = total.
+// in == out is allowed.  tmp must hold scan_tmp_elems(n) int64.
+size_t scan_tmp_elems(int64_t n);
+int scan_excl(const int64_t* in, int64_t* out, int64_t n, int64_t* tmp, hipStream_t s);
+
+// Stable LSD radix sort of (key, value) pairs by the low `bits` key bits.
+// Input in keys[0]/vals[0]; the sorted pairs end in keys[r]/vals[r] where r
+// is the returned index (0 or 1).  hist needs radix_hist_elems(n) int64.
+size_t radix_hist_elems(int64_t n);
+int radix_sort(uint64_t* keys[2], uint32_t* vals[2], int64_t n, int bits, int64_t* hist,
+               int64_t* scan_tmp, hipStream_t s, int* result_index);
+
+// Per-bin counts of idx[0..n) into cnt[0..nbins) (cnt zeroed by the call).
+int count_bins(const int32_t* idx, int64_t n, int64_t* cnt, int64_t nbins, hipStream_t s);
+
+// Fills.
+int fill_i64(int64_t* p, int64_t n, int64_t v, hipStream_t s);
+int fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
+int fill_f32(float* p, int64_t n, float v, hipStream_t s);
+
+}  // namespace lshmf
+
+// ------------------------------------------------------------ the context
+struct lshmf_ctx {
+    lshmf_dims d;
+    int B;         // hash bits G*p*q
+    int words;     // uint32 words per signature
+    int pG;        // band width in bits
+    int P;         // strata
+    int nstride;   // bytes of neighbour codes per rating (K nibbles, padded)
+    int64_t sort_n;  // capacity of the sort buffers
+
+    lshmf_tables t;
+    bool bound = false, ingested = false, neighbours = false;
+
+    // arena regions (device)
+    int64_t* row_ptr;    // M+1   CSR by user
+    int32_t* csr_col;    // nnz   items, ascending per user
+    uint8_t* csr_rc;     // nnz
+    int64_t* col_ptr;    // N+1   CSC by item
+    int32_t* csc_row;    // nnz   users, ascending per item
+    uint8_t* csc_rc;     // nnz
+    uint32_t* pk;        // nnz   block stream: (i << 4) | rc
+    int32_t* sj;         // nnz   item of each stream rating
+    int32_t* dep;        // nnz   previous rating of the same user inside the block (local), -1
+    uint8_t* nib;        // nnz*nstride  4-bit codes of r_{i, JK[j][k]} (0: not rated)
+    int64_t* blk_ptr;    // P*P+1 block b of stratum s = entry s*P + b
+    int64_t* blk_seg;    // P*P+1 first segment of each block
+    int32_t* seg_col;    // nnz   item of each segment (a run of one item inside a block)
+    int64_t* seg_start;  // nnz+1
+    int32_t* csr_spos;   // nnz   stream position of each CSR rating
+    int64_t* cnt;        // max(M,N,P*P,nnz)+1 counters / flags
+    uint64_t* sk[2];     // sort keys
+    uint32_t* sv[2];     // sort values
+    int64_t* hist;       // radix histogram
+    int64_t* scan_tmp;
+    double* red;         // FP64 reduction partials
+    int32_t* bitem;      // q*N  items sorted by (band, key)
+    int32_t* bbegin;     // q*N+1 bucket starts (by bucket id)
+    int32_t* bpos;       // q*N  bucket id of (band t, item j) at t*N + j
+    int32_t* err;        // device error flag
+    int64_t max_block_nnz;  // host copy after ingest
+};

@@ -1,0 +1,394 @@
+// simLSH neighbour search without the N x N similarity matrix (Sec. 4.1).
+//
+//   k_simlsh_acc    pre-sign sums acc[j][b] = sum_{i in col j} Psi(r_ij)(2 H_ib - 1)
+//                   (Eq. item_hash).  Integer arithmetic, so the sums are exact
+//                   and independent of the order of the atomic flushes.
+//   k_simlsh_sign   Upsilon: bit b of item j is set iff acc[j][b] >= 0.
+//   k_band_keys     q band keys of p*G bits (p hashes ANDed per band).
+//   k_bucket_*      one radix sort of (band, key) groups the items of every
+//                   bucket; a bucket id per (band, item).
+//   k_topk          per item: collision counts over its q buckets in an LDS
+//                   hash table, the K most frequent partners by (count desc,
+//                   id asc), seeded SplitMix64 supplement, ids ascending.
+//   k_nbr_codes     per training rating (i, j): the rating code of user i for
+//                   each neighbour JK[j][k] (0 if not rated), 4 bits per slot;
+//                   this resolves R^K(i;j) and N^K(i;j) once for all epochs.
+#include "common.hpp"
+
+namespace lshmf {
+
+// ------------------------------------------------------------ projection
+constexpr int kAccChunk = 512;     // CSC positions per wave
+constexpr int kMaxBitsPerLane = 4; // B <= 256
+
+__global__ __launch_bounds__(256) void k_simlsh_acc(const int64_t* col_ptr, const int32_t* row,
+                                                    const uint8_t* rc, int64_t nnz, int32_t N,
+                                                    const uint32_t* H, int words, int B, int psi_exp,
+                                                    int32_t* acc)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kWave;
+    const int64_t p0 = wave * kAccChunk;
+    if (p0 >= nnz) return;
+    const int64_t p1 = p0 + kAccChunk < nnz ? p0 + kAccChunk : nnz;
+    // column containing p0: largest j with col_ptr[j] <= p0
+    int32_t lo = 0, hi = N;  // invariant col_ptr[lo] <= p0 < col_ptr[hi]
+    while (hi - lo > 1) {
+        const int32_t mid = (lo + hi) >> 1;
+        if (col_ptr[mid] <= p0) lo = mid;
+        else hi = mid;
+    }
+    int32_t j = lo;
+    int64_t jend = col_ptr[j + 1];
+    int32_t a[kMaxBitsPerLane] = {0, 0, 0, 0};
+    const int nsl = (B + kWave - 1) / kWave;
+    for (int64_t p = p0; p < p1; ++p) {
+        while (p >= jend) {
+            for (int sl = 0; sl < nsl; ++sl) {
+                const int b = lane + sl * kWave;
+                if (b < B && a[sl] != 0) atomicAdd(&acc[(int64_t)j * B + b], a[sl]);
+                a[sl] = 0;
+            }
+            ++j;
+            jend = col_ptr[j + 1];
+        }
+        const int64_t i = row[p];
+        const int code = rc[p];
+        int32_t w = 1;
+        for (int e = 0; e < psi_exp; ++e) w *= code;
+#pragma unroll
+        for (int sl = 0; sl < kMaxBitsPerLane; ++sl) {
+            if (sl < nsl) {
+                const int b = lane + sl * kWave;
+                if (b < B) {
+                    const uint32_t hw = H[i * words + (b >> 5)];
+                    a[sl] += ((hw >> (b & 31)) & 1u) ? w : -w;
+                }
+            }
+        }
+    }
+    for (int sl = 0; sl < nsl; ++sl) {
+        const int b = lane + sl * kWave;
+        if (b < B && a[sl] != 0) atomicAdd(&acc[(int64_t)j * B + b], a[sl]);
+    }
+}
+
+__global__ void k_simlsh_sign(const int32_t* acc, int32_t N, int B, int words, uint32_t* sig)
+{
+    for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < (int64_t)N * words;
+         x += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t j = x / words;
+        const int w = (int)(x % words);
+        uint32_t v = 0;
+        for (int t = 0; t < 32; ++t) {
+            const int b = w * 32 + t;
+            if (b < B && acc[j * B + b] >= 0) v |= 1u << t;
+        }
+        sig[x] = v;
+    }
+}
+
+// --------------------------------------------------------------- banding
+__global__ void k_band_keys(const uint32_t* sig, int32_t N, int words, int pG, int q, uint64_t* keys,
+                            uint32_t* vals)
+{
+    const int64_t n = (int64_t)q * N;
+    for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < n;
+         x += (int64_t)gridDim.x * blockDim.x) {
+        const int t = (int)(x / N);
+        const int64_t j = x % N;
+        const int off = t * pG;
+        const int w0 = off >> 5, sh = off & 31;  // pG <= 32: two words suffice
+        uint64_t v = sig[j * words + w0];
+        if (w0 + 1 < words) v |= (uint64_t)sig[j * words + w0 + 1] << 32;
+        v >>= sh;
+        const uint64_t key = v & ((pG >= 64) ? ~0ull : ((1ull << pG) - 1ull));
+        keys[x] = ((uint64_t)t << pG) | key;
+        vals[x] = (uint32_t)j;
+    }
+}
+
+__global__ void k_bucket_flags(const uint64_t* keys, int64_t n, int64_t* flag)
+{
+    for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < n;
+         x += (int64_t)gridDim.x * blockDim.x)
+        flag[x] = (x == 0 || keys[x] != keys[x - 1]) ? 1 : 0;
+}
+
+// bucket id of sorted position x is incl[x] - 1 = ex[x+1] - 1
+__global__ void k_bucket_fill(const uint64_t* keys, const uint32_t* items, const int64_t* ex, int64_t n,
+                              int32_t N, int pG, int32_t* bitem, int32_t* bbegin, int32_t* bpos)
+{
+    for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < n;
+         x += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t id = (int32_t)(ex[x + 1] - 1);
+        const uint32_t j = items[x];
+        const int64_t t = (int64_t)(keys[x] >> pG);
+        bitem[x] = (int32_t)j;
+        if (x == 0 || keys[x] != keys[x - 1]) bbegin[id] = (int32_t)x;
+        bpos[t * N + j] = id;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) bbegin[ex[n]] = (int32_t)n;
+}
+
+// ------------------------------------------------------------------ top-K
+constexpr int kTopkThreads = 256;
+constexpr int kTabCap = 4096;              // LDS hash slots
+constexpr int kRangeCap = kTabCap / 2;     // occurrences admitted per range
+constexpr int kMaxK = 128;
+
+__device__ inline uint64_t splitmix64(uint64_t seed, uint64_t c)
+{
+    // SplitMix64 (Steele, Lea, Flood 2014): output c of the stream at `seed`
+    uint64_t z = seed + c * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+__device__ inline uint32_t slot_hash(uint32_t x) { return (x * 2654435761u) >> 20; }  // 12 bits
+
+// Bitonic sort of buf[0..n2) ascending, n2 a power of two, whole workgroup.
+__device__ void bitonic_sort(uint64_t* buf, int n2)
+{
+    for (int k = 2; k <= n2; k <<= 1) {
+        for (int jj = k >> 1; jj > 0; jj >>= 1) {
+            for (int t = threadIdx.x; t < (n2 >> 1); t += blockDim.x) {
+                const int i = 2 * jj * (t / jj) + (t % jj);
+                const int l = i + jj;
+                const bool up = (i & k) == 0;
+                const uint64_t a = buf[i], b = buf[l];
+                if ((a > b) == up) {
+                    buf[i] = b;
+                    buf[l] = a;
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+__device__ inline int block_sum_int(int v, int* scratch)
+{
+    for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_down(v, o, kWave);
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    __syncthreads();
+    if (lane == 0) scratch[wave] = v;
+    __syncthreads();
+    int tot = 0;
+    for (int w = 0; w < (int)(blockDim.x / kWave); ++w) tot += scratch[w];
+    return tot;
+}
+
+// One workgroup per item.  Candidate ids are processed in id ranges small
+// enough that their occurrences fit the LDS table; a running best list of K
+// (count desc, id asc) keys is merged with each range by a bitonic sort.
+__global__ __launch_bounds__(kTopkThreads) void k_topk(const int32_t* bitem, const int32_t* bbegin,
+                                                       const int32_t* bpos, int32_t N, int q, int K,
+                                                       uint64_t seed_fill, int32_t* JK, int32_t j_first)
+{
+    __shared__ uint64_t buf[kTabCap];      // hash table (key | count) / sort buffer
+    __shared__ uint64_t best[kMaxK];
+    __shared__ int32_t chosen[kMaxK];
+    __shared__ int red[kTopkThreads / kWave];
+    __shared__ int nbest_s, nent_s;
+    uint32_t* tkey = reinterpret_cast<uint32_t*>(buf);             // kTabCap keys
+    uint32_t* tcnt = reinterpret_cast<uint32_t*>(buf) + kTabCap;   // kTabCap counts
+
+    const int32_t j = j_first + blockIdx.x;
+    if (j >= N) return;
+    const int tid = threadIdx.x;
+    if (tid == 0) nbest_s = 0;
+    int32_t lo = 0, span = N;
+    while (lo < N) {
+        const int32_t hi = (int32_t)((int64_t)lo + span < N ? lo + span : N);
+        // occurrences of ids in [lo, hi) over the q buckets of j
+        int occ = 0;
+        for (int t = 0; t < q; ++t) {
+            const int32_t id = bpos[(int64_t)t * N + j];
+            const int32_t a = bbegin[id], z = bbegin[id + 1];
+            for (int32_t x = a + tid; x < z; x += kTopkThreads) {
+                const int32_t c = bitem[x];
+                occ += (c != j && c >= lo && c < hi);
+            }
+        }
+        occ = block_sum_int(occ, red);
+        if (occ > kRangeCap && hi - lo > 1) {
+            span = (hi - lo) / 2;
+            continue;
+        }
+        for (int x = tid; x < kTabCap; x += kTopkThreads) {
+            tkey[x] = 0xFFFFFFFFu;
+            tcnt[x] = 0;
+        }
+        __syncthreads();
+        for (int t = 0; t < q; ++t) {
+            const int32_t id = bpos[(int64_t)t * N + j];
+            const int32_t a = bbegin[id], z = bbegin[id + 1];
+            for (int32_t x = a + tid; x < z; x += kTopkThreads) {
+                const uint32_t c = (uint32_t)bitem[x];
+                if ((int32_t)c == j || (int32_t)c < lo || (int32_t)c >= hi) continue;
+                uint32_t h = slot_hash(c) & (kTabCap - 1);
+                while (true) {
+                    const uint32_t old = atomicCAS(&tkey[h], 0xFFFFFFFFu, c);
+                    if (old == 0xFFFFFFFFu || old == c) {
+                        atomicAdd(&tcnt[h], 1u);
+                        break;
+                    }
+                    h = (h + 1) & (kTabCap - 1);
+                }
+            }
+        }
+        __syncthreads();
+        // extract (q - count, id) keys into registers, then into buf
+        constexpr int kPer = kTabCap / kTopkThreads;
+        uint64_t ent[kPer];
+        int nmine = 0;
+#pragma unroll
+        for (int r = 0; r < kPer; ++r) {
+            const int x = tid + r * kTopkThreads;
+            ent[r] = ~0ull;
+            if (tkey[x] != 0xFFFFFFFFu) {
+                ent[r] = ((uint64_t)(q - (int)tcnt[x]) << 32) | tkey[x];
+                ++nmine;
+            }
+        }
+        if (tid == 0) nent_s = 0;
+        __syncthreads();
+        int pos = nmine ? atomicAdd(&nent_s, nmine) : 0;
+#pragma unroll
+        for (int r = 0; r < kPer; ++r)
+            if (ent[r] != ~0ull) buf[pos++] = ent[r];
+        __syncthreads();
+        const int nent = nent_s, nb = nbest_s;
+        for (int x = tid; x < nb; x += kTopkThreads) buf[nent + x] = best[x];
+        int n2 = 1;
+        while (n2 < nent + nb) n2 <<= 1;
+        for (int x = nent + nb + tid; x < n2; x += kTopkThreads) buf[x] = ~0ull;
+        __syncthreads();
+        if (n2 > 1) bitonic_sort(buf, n2);
+        const int keep = (nent + nb) < K ? (nent + nb) : K;
+        for (int x = tid; x < keep; x += kTopkThreads) best[x] = buf[x];
+        __syncthreads();
+        if (tid == 0) nbest_s = keep;
+        __syncthreads();
+        lo = hi;
+    }
+    // random supplement, ids ascending
+    if (tid == 0) {
+        int n = nbest_s;
+        for (int x = 0; x < n; ++x) chosen[x] = (int32_t)(best[x] & 0xFFFFFFFFu);
+        for (uint64_t a = 0; n < K; ++a) {
+            const int32_t cand = (int32_t)(splitmix64(seed_fill, ((uint64_t)j << 32) + a + 1) % (uint64_t)N);
+            bool dup = cand == j;
+            for (int y = 0; y < n && !dup; ++y) dup = chosen[y] == cand;
+            if (!dup) chosen[n++] = cand;
+        }
+        for (int x = 1; x < K; ++x) {  // insertion sort, K <= 128
+            const int32_t v = chosen[x];
+            int y = x - 1;
+            while (y >= 0 && chosen[y] > v) {
+                chosen[y + 1] = chosen[y];
+                --y;
+            }
+            chosen[y + 1] = v;
+        }
+    }
+    __syncthreads();
+    for (int x = tid; x < K; x += kTopkThreads) JK[(int64_t)j * K + x] = chosen[x];
+}
+
+// -------------------------------------------------------- neighbour codes
+// One wave per stream rating; lane L resolves slots L and L + 64 by binary
+// search in the user's CSR row, then byte x of the record packs slots 2x
+// (low nibble) and 2x+1 (high nibble).
+__global__ __launch_bounds__(256) void k_nbr_codes(const uint32_t* pk, const int32_t* sj, int64_t n,
+                                                   const int32_t* JK, int K, const int64_t* row_ptr,
+                                                   const int32_t* csr_col, const uint8_t* csr_rc,
+                                                   uint8_t* nib, int nstride)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t w0 = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kWave;
+    const int64_t nw = (int64_t)gridDim.x * blockDim.x / kWave;
+    for (int64_t p = w0; p < n; p += nw) {
+        const int64_t i = pk[p] >> 4;
+        const int64_t j = sj[p];
+        const int64_t a = row_ptr[i], z = row_ptr[i + 1];
+        int code[2] = {0, 0};
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int k = lane + h * kWave;
+            if (k < K) {
+                const int32_t nb = JK[j * K + k];
+                int64_t l = a, r = z;
+                while (l < r) {
+                    const int64_t m = (l + r) >> 1;
+                    if (csr_col[m] < nb) l = m + 1;
+                    else r = m;
+                }
+                code[h] = (l < z && csr_col[l] == nb) ? csr_rc[l] : 0;
+            }
+        }
+        // byte `lane` packs slots 2*lane and 2*lane+1
+        const int s0 = 2 * lane, s1 = 2 * lane + 1;
+        const int lo0 = __shfl(code[0], s0 & 63, kWave), hi0 = __shfl(code[1], s0 & 63, kWave);
+        const int lo1 = __shfl(code[0], s1 & 63, kWave), hi1 = __shfl(code[1], s1 & 63, kWave);
+        const int c0 = s0 < 64 ? lo0 : hi0;
+        const int c1 = s1 < 64 ? lo1 : hi1;
+        if (lane < nstride) nib[p * nstride + lane] = (uint8_t)(c0 | (c1 << 4));
+    }
+}
+
+static unsigned grid_for(int64_t n, int threads = 256, int64_t cap = 16384)
+{
+    int64_t b = ceil_div(n > 0 ? n : 1, threads);
+    return (unsigned)(b > cap ? cap : b);
+}
+
+int build_neighbours(lshmf_ctx* c, const uint32_t* H, uint64_t seed_fill, hipStream_t s)
+{
+    const lshmf_dims& d = c->d;
+    const int64_t nnz = d.nnz;
+    // projection and signs
+    LSHMF_TRY(fill_i32(c->t.acc, (int64_t)d.N * c->B, 0, s));
+    const int64_t waves = ceil_div(nnz, kAccChunk);
+    if (waves > 0) {
+        hipLaunchKernelGGL(k_simlsh_acc, dim3((unsigned)ceil_div(waves * kWave, 256)), dim3(256), 0, s,
+                           c->col_ptr, c->csc_row, c->csc_rc, nnz, d.N, H, c->words, c->B, d.psi_exp,
+                           c->t.acc);
+        LSHMF_LAUNCHED("k_simlsh_acc");
+    }
+    hipLaunchKernelGGL(k_simlsh_sign, dim3(grid_for((int64_t)d.N * c->words)), dim3(256), 0, s, c->t.acc,
+                       d.N, c->B, c->words, c->t.sig);
+    LSHMF_LAUNCHED("k_simlsh_sign");
+    // band keys and buckets
+    const int64_t nq = (int64_t)d.q * d.N;
+    hipLaunchKernelGGL(k_band_keys, dim3(grid_for(nq)), dim3(256), 0, s, c->t.sig, d.N, c->words, c->pG, d.q,
+                       c->sk[0], c->sv[0]);
+    LSHMF_LAUNCHED("k_band_keys");
+    int ri = 0;
+    LSHMF_TRY(radix_sort(c->sk, c->sv, nq, c->pG + bits_for((uint64_t)d.q), c->hist, c->scan_tmp, s, &ri));
+    hipLaunchKernelGGL(k_bucket_flags, dim3(grid_for(nq)), dim3(256), 0, s, c->sk[ri], nq, c->cnt);
+    LSHMF_LAUNCHED("k_bucket_flags");
+    int64_t* ex = reinterpret_cast<int64_t*>(c->sk[ri ^ 1]);
+    LSHMF_TRY(scan_excl(c->cnt, ex, nq, c->scan_tmp, s));
+    hipLaunchKernelGGL(k_bucket_fill, dim3(grid_for(nq)), dim3(256), 0, s, c->sk[ri], c->sv[ri], ex, nq, d.N,
+                       c->pG, c->bitem, c->bbegin, c->bpos);
+    LSHMF_LAUNCHED("k_bucket_fill");
+    // top-K per item (grid chunks keep the launch size modest)
+    for (int32_t j0 = 0; j0 < d.N; j0 += 65535) {
+        const int32_t nj = d.N - j0 < 65535 ? d.N - j0 : 65535;
+        hipLaunchKernelGGL(k_topk, dim3((unsigned)nj), dim3(kTopkThreads), 0, s, c->bitem, c->bbegin, c->bpos,
+                           d.N, d.q, d.K, seed_fill, c->t.JK, j0);
+        LSHMF_LAUNCHED("k_topk");
+    }
+    // neighbour codes of every training rating
+    if (nnz > 0) {
+        hipLaunchKernelGGL(k_nbr_codes, dim3(grid_for(nnz * kWave, 256, 65536)), dim3(256), 0, s, c->pk, c->sj,
+                           nnz, c->t.JK, d.K, c->row_ptr, c->csr_col, c->csr_rc, c->nib, c->nstride);
+        LSHMF_LAUNCHED("k_nbr_codes");
+    }
+    return LSHMF_OK;
+}
+
+}  // namespace lshmf

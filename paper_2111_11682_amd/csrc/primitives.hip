@@ -1,0 +1,275 @@
+// Device-wide building blocks: exclusive scan, stable LSD radix sort, bin
+// counting and fills.  Used by the layout (ingest) and by the banding step of
+// the neighbour search; not on the per-rating SGD path.
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+
+#include "common.hpp"
+
+namespace lshmf {
+
+static thread_local char g_err[512] = "";
+
+void set_error(const char* fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+}
+
+int hip_fail(hipError_t e, const char* what)
+{
+    set_error("%s: %s", what, hipGetErrorString(e));
+    return LSHMF_EDEVICE;
+}
+
+const char* last_error() { return g_err; }
+
+// ------------------------------------------------------------------ fills
+template <typename T>
+__global__ void k_fill(T* p, int64_t n, T v)
+{
+    for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < n;
+         x += (int64_t)gridDim.x * blockDim.x)
+        p[x] = v;
+}
+
+template <typename T>
+static int fill(T* p, int64_t n, T v, hipStream_t s)
+{
+    if (n <= 0) return LSHMF_OK;
+    int64_t blocks = ceil_div(n, 256);
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL(k_fill<T>, dim3((unsigned)blocks), dim3(256), 0, s, p, n, v);
+    LSHMF_LAUNCHED("k_fill");
+    return LSHMF_OK;
+}
+
+int fill_i64(int64_t* p, int64_t n, int64_t v, hipStream_t s) { return fill(p, n, v, s); }
+int fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s) { return fill(p, n, v, s); }
+int fill_f32(float* p, int64_t n, float v, hipStream_t s) { return fill(p, n, v, s); }
+
+// ------------------------------------------------------------------- scan
+// One workgroup of 256 threads scans a tile of 1024 values (4 per thread).
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 4;
+constexpr int kScanTile = kScanThreads * kScanItems;
+
+__device__ inline int64_t wave_incl_scan(int64_t v)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        int64_t y = __shfl_up(v, o, kWave);
+        if (lane >= o) v += y;
+    }
+    return v;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_tile(const int64_t* in, int64_t* out,
+                                                            int64_t n, int64_t* sums)
+{
+    __shared__ int64_t wsum[kScanThreads / kWave];
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    int64_t v[kScanItems];
+    int64_t local = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        v[k] = (base + k < n) ? in[base + k] : 0;
+        local += v[k];
+    }
+    int64_t incl = wave_incl_scan(local);
+    const int wave = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
+    if (lane == kWave - 1) wsum[wave] = incl;
+    __syncthreads();
+    int64_t wprefix = 0;
+    for (int w = 0; w < wave; ++w) wprefix += wsum[w];
+    int64_t run = wprefix + incl - local;   // exclusive prefix of this thread
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        if (base + k < n) out[base + k] = run;
+        run += v[k];
+    }
+    if (threadIdx.x == kScanThreads - 1) {
+        int64_t tot = 0;
+        for (int w = 0; w < kScanThreads / kWave; ++w) tot += wsum[w];
+        sums[blockIdx.x] = tot;
+    }
+}
+
+__global__ void k_scan_add(int64_t* out, int64_t n, const int64_t* offs)
+{
+    const int64_t x = (int64_t)blockIdx.x * kScanTile + threadIdx.x;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        const int64_t y = x + (int64_t)k * kScanThreads;
+        if (y < n) out[y] += offs[blockIdx.x];
+    }
+}
+
+__global__ void k_set_total(int64_t* out, int64_t n, const int64_t* sums_scanned, int64_t nb)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) out[n] = sums_scanned[nb];
+}
+
+size_t scan_tmp_elems(int64_t n)
+{
+    size_t tot = 0;
+    while (n > 1) {
+        const int64_t nb = ceil_div(n, kScanTile);
+        tot += (size_t)nb + 1;
+        n = nb;
+    }
+    return tot + 2;
+}
+
+int scan_excl(const int64_t* in, int64_t* out, int64_t n, int64_t* tmp, hipStream_t s)
+{
+    if (n <= 0) {
+        hipLaunchKernelGGL(k_fill<int64_t>, dim3(1), dim3(1), 0, s, out, (int64_t)1, (int64_t)0);
+        LSHMF_LAUNCHED("k_fill(scan total)");
+        return LSHMF_OK;
+    }
+    const int64_t nb = ceil_div(n, kScanTile);
+    int64_t* sums = tmp;            // nb + 1 entries, scanned recursively in place
+    hipLaunchKernelGGL(k_scan_tile, dim3((unsigned)nb), dim3(kScanThreads), 0, s, in, out, n, sums);
+    LSHMF_LAUNCHED("k_scan_tile");
+    if (nb == 1) {  // sums[0] is the total
+        hipLaunchKernelGGL(k_set_total, dim3(1), dim3(1), 0, s, out, n, sums, (int64_t)0);
+        LSHMF_LAUNCHED("k_set_total");
+        return LSHMF_OK;
+    }
+    LSHMF_TRY(scan_excl(sums, sums, nb, tmp + nb + 1, s));
+    hipLaunchKernelGGL(k_scan_add, dim3((unsigned)nb), dim3(kScanThreads), 0, s, out, n, sums);
+    LSHMF_LAUNCHED("k_scan_add");
+    hipLaunchKernelGGL(k_set_total, dim3(1), dim3(1), 0, s, out, n, sums, nb);
+    LSHMF_LAUNCHED("k_set_total");
+    return LSHMF_OK;
+}
+
+// ------------------------------------------------------------- radix sort
+// 8-bit digits; a tile of 4096 keys per 256-thread workgroup.
+constexpr int kRsThreads = 256;
+constexpr int kRsItems = 16;
+constexpr int kRsTile = kRsThreads * kRsItems;
+constexpr int kRsBins = 256;
+
+size_t radix_hist_elems(int64_t n) { return (size_t)ceil_div(n, kRsTile) * kRsBins + 1; }
+
+__global__ __launch_bounds__(kRsThreads) void k_rs_hist(const uint64_t* keys, int64_t n, int shift,
+                                                        int64_t* hist, int64_t ntiles)
+{
+    __shared__ int cnt[kRsBins];
+    cnt[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kRsTile;
+    for (int k = 0; k < kRsItems; ++k) {
+        const int64_t x = base + (int64_t)k * kRsThreads + threadIdx.x;
+        if (x < n) atomicAdd(&cnt[(keys[x] >> shift) & (kRsBins - 1)], 1);
+    }
+    __syncthreads();
+    hist[(int64_t)threadIdx.x * ntiles + blockIdx.x] = cnt[threadIdx.x];
+}
+
+// Stable scatter: keys of a tile are ranked in their original order.  Each
+// round handles 256 consecutive keys (thread t takes the t-th); the rank of a
+// key among equal digits is (keys of earlier rounds) + (earlier waves of this
+// round) + (lower lanes of its own wave).
+__global__ __launch_bounds__(kRsThreads) void k_rs_scatter(const uint64_t* kin, const uint32_t* vin,
+                                                           uint64_t* kout, uint32_t* vout, int64_t n,
+                                                           int shift, const int64_t* offs,
+                                                           int64_t ntiles)
+{
+    constexpr int kWaves = kRsThreads / kWave;
+    __shared__ int64_t base[kRsBins];
+    __shared__ int wcnt[kWaves][kRsBins];
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+    base[tid] = offs[(int64_t)tid * ntiles + blockIdx.x];
+    for (int w = 0; w < kWaves; ++w) wcnt[w][tid] = 0;
+    __syncthreads();
+    const int64_t tile0 = (int64_t)blockIdx.x * kRsTile;
+    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
+    for (int r = 0; r < kRsItems; ++r) {
+        const int64_t x = tile0 + (int64_t)r * kRsThreads + tid;
+        const bool valid = x < n;
+        uint64_t key = 0;
+        uint32_t val = 0;
+        int d = 0;
+        if (valid) {
+            key = kin[x];
+            val = vin[x];
+            d = (int)((key >> shift) & (kRsBins - 1));
+        }
+        // lanes of this wave with the same digit
+        uint64_t same = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const uint64_t bal = __ballot(valid && ((d >> b) & 1));
+            same &= ((d >> b) & 1) ? bal : ~bal;
+        }
+        const int rank_w = __popcll(same & lt_mask);
+        const bool leader = valid && rank_w == 0;
+        if (leader) wcnt[wave][d] = __popcll(same);
+        __syncthreads();
+        if (valid) {
+            int64_t pos = base[d] + rank_w;
+            for (int w = 0; w < wave; ++w) pos += wcnt[w][d];
+            kout[pos] = key;
+            vout[pos] = val;
+        }
+        __syncthreads();
+        int add = 0;
+        for (int w = 0; w < kWaves; ++w) {
+            add += wcnt[w][tid];
+            wcnt[w][tid] = 0;
+        }
+        base[tid] += add;
+        __syncthreads();
+    }
+}
+
+int radix_sort(uint64_t* keys[2], uint32_t* vals[2], int64_t n, int bits, int64_t* hist,
+               int64_t* scan_tmp, hipStream_t s, int* result_index)
+{
+    int cur = 0;
+    if (n > 1) {
+        const int64_t ntiles = ceil_div(n, kRsTile);
+        for (int shift = 0; shift < bits; shift += 8) {
+            hipLaunchKernelGGL(k_rs_hist, dim3((unsigned)ntiles), dim3(kRsThreads), 0, s, keys[cur],
+                               n, shift, hist, ntiles);
+            LSHMF_LAUNCHED("k_rs_hist");
+            LSHMF_TRY(scan_excl(hist, hist, ntiles * kRsBins, scan_tmp, s));
+            hipLaunchKernelGGL(k_rs_scatter, dim3((unsigned)ntiles), dim3(kRsThreads), 0, s,
+                               keys[cur], vals[cur], keys[cur ^ 1], vals[cur ^ 1], n, shift, hist,
+                               ntiles);
+            LSHMF_LAUNCHED("k_rs_scatter");
+            cur ^= 1;
+        }
+    }
+    *result_index = cur;
+    return LSHMF_OK;
+}
+
+// --------------------------------------------------------------- counting
+__global__ void k_count(const int32_t* idx, int64_t n, unsigned long long* cnt)
+{
+    for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < n;
+         x += (int64_t)gridDim.x * blockDim.x)
+        atomicAdd(&cnt[idx[x]], 1ull);
+}
+
+int count_bins(const int32_t* idx, int64_t n, int64_t* cnt, int64_t nbins, hipStream_t s)
+{
+    LSHMF_TRY(fill_i64(cnt, nbins, 0, s));
+    if (n <= 0) return LSHMF_OK;
+    int64_t blocks = ceil_div(n, 256);
+    if (blocks > 16384) blocks = 16384;
+    hipLaunchKernelGGL(k_count, dim3((unsigned)blocks), dim3(256), 0, s, idx, n,
+                       (unsigned long long*)cnt);
+    LSHMF_LAUNCHED("k_count");
+    return LSHMF_OK;
+}
+
+}  // namespace lshmf

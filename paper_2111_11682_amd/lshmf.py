@@ -1,0 +1,211 @@
+"""Python binding of liblshmf (ctypes): argument marshalling only.
+
+Every step of the method runs in the HIP library; this module allocates the
+caller-owned device tables with PyTorch, passes raw device pointers and the
+current HIP stream, and turns non-zero statuses into exceptions.  There is no
+CPU fallback: if the library is not built the import-time loader raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import threading
+from typing import Optional, Sequence
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblshmf.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "lshmf.h")
+
+LSHMF_OK = 0
+STATUS = {0: "LSHMF_OK", -1: "LSHMF_EINVAL", -2: "LSHMF_ESTATE", -3: "LSHMF_ECAPACITY",
+          -4: "LSHMF_EDEVICE"}
+
+
+class LshmfError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__("%s: %s" % (STATUS.get(status, status), msg))
+        self.status = status
+
+
+class Dims(C.Structure):
+    _fields_ = [("M", C.c_int32), ("N", C.c_int32), ("F", C.c_int32), ("K", C.c_int32),
+                ("G", C.c_int32), ("p", C.c_int32), ("q", C.c_int32), ("rscale", C.c_int32),
+                ("psi_exp", C.c_int32), ("n_strata", C.c_int32), ("storage", C.c_int32),
+                ("reserved", C.c_int32), ("nnz", C.c_int64)]
+
+
+class HParams(C.Structure):
+    _fields_ = [("alpha", C.c_float * 6), ("lambda_", C.c_float * 6), ("beta", C.c_float),
+                ("reserved", C.c_int32)]
+
+
+class Tables(C.Structure):
+    _fields_ = [(n, C.c_void_p) for n in
+                ("U", "V", "bu", "bv", "W", "C", "JK", "acc", "sig", "b0", "bh0", "mu")]
+
+
+class Layout(C.Structure):
+    _fields_ = [(n, C.c_void_p) for n in
+                ("pk", "sj", "dep", "nib", "blk_ptr", "blk_seg", "seg_col", "seg_start",
+                 "row_ptr", "csr_col", "csr_rc", "col_ptr", "csc_row", "csc_rc", "err")] + \
+               [("nstride", C.c_int32), ("P", C.c_int32)]
+
+
+_lock = threading.Lock()
+_lib = None
+
+
+def lib():
+    """Loads liblshmf.so; raises if it has not been built."""
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(LIB_PATH):
+                raise ImportError("liblshmf.so is not built (run __graft_entry__.build()); "
+                                  "there is no CPU fallback")
+            L = C.CDLL(LIB_PATH)
+            vp, i32, i64, u64 = C.c_void_p, C.c_int32, C.c_int64, C.c_uint64
+            L.lshmf_create.argtypes = [C.POINTER(Dims), C.POINTER(vp)]
+            L.lshmf_destroy.argtypes = [vp]
+            L.lshmf_destroy.restype = None
+            L.lshmf_arena_bytes.argtypes = [vp, C.POINTER(C.c_size_t)]
+            L.lshmf_bind.argtypes = [vp, C.POINTER(Tables), vp, C.c_size_t]
+            L.lshmf_ingest.argtypes = [vp, vp, vp, vp, i64, vp]
+            L.build_lsh_neighbours.argtypes = [vp, vp, u64, vp]
+            L.sgd_epoch.argtypes = [vp, C.POINTER(HParams), i32, vp]
+            L.predict.argtypes = [vp, vp, vp, i64, vp, vp]
+            L.lshmf_rmse.argtypes = [vp, vp, vp, i64, vp, vp]
+            L.lshmf_export_layout.argtypes = [vp, C.POINTER(Layout)]
+            L.lshmf_last_error.restype = C.c_char_p
+            L.lshmf_last_error.argtypes = []
+            _lib = L
+    return _lib
+
+
+def _check(status: int):
+    if status != LSHMF_OK:
+        raise LshmfError(status, lib().lshmf_last_error().decode())
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return C.c_void_p(t.data_ptr()) if t is not None else C.c_void_p(0)
+
+
+def _stream(device) -> C.c_void_p:
+    return C.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def header_functions() -> Sequence[str]:
+    """Names of the functions declared in include/lshmf.h."""
+    import re
+    src = open(HEADER).read()
+    return re.findall(r"^\s*(?:int|void|const char\*)\s+([a-z_][a-z0-9_]*)\s*\(", src, re.M)
+
+
+class LshMF:
+    """Device-resident LSH-MF model driven through the C ABI."""
+
+    def __init__(self, M: int, N: int, F: int, K: int, G: int, p: int, q: int, rscale: int,
+                 nnz: int, psi_exp: int = 2, n_strata: int = 256, device="cuda"):
+        self.device = torch.device(device)
+        self.dims = Dims(M, N, F, K, G, p, q, rscale, psi_exp, n_strata, 0, 0, nnz)
+        self.B = G * p * q
+        self.words = (self.B + 31) // 32
+        h = C.c_void_p()
+        _check(lib().lshmf_create(C.byref(self.dims), C.byref(h)))
+        self._h = h
+        nbytes = C.c_size_t()
+        _check(lib().lshmf_arena_bytes(h, C.byref(nbytes)))
+        dev = self.device
+        f32 = dict(dtype=torch.float32, device=dev)
+        self.U = torch.zeros(M, F, **f32)
+        self.V = torch.zeros(N, F, **f32)
+        self.bu = torch.zeros(M, **f32)
+        self.bv = torch.zeros(N, **f32)
+        self.W = torch.zeros(N, K, **f32)
+        self.C = torch.zeros(N, K, **f32)
+        self.JK = torch.zeros(N, K, dtype=torch.int32, device=dev)
+        self.acc = torch.zeros(N, self.B, dtype=torch.int32, device=dev)
+        self.sig = torch.zeros(N, self.words, dtype=torch.int32, device=dev)
+        self.b0 = torch.zeros(M, **f32)
+        self.bh0 = torch.zeros(N, **f32)
+        self.mu = torch.zeros(1, dtype=torch.float64, device=dev)
+        self.arena = torch.empty(int(nbytes.value) + 256, dtype=torch.uint8, device=dev)
+        off = (-self.arena.data_ptr()) % 256
+        self._arena_ptr = self.arena.data_ptr() + off
+        self.tables = Tables(*[t.data_ptr() for t in (self.U, self.V, self.bu, self.bv, self.W,
+                                                       self.C, self.JK, self.acc, self.sig,
+                                                       self.b0, self.bh0, self.mu)])
+        _check(lib().lshmf_bind(h, C.byref(self.tables), C.c_void_p(self._arena_ptr),
+                                C.c_size_t(int(nbytes.value))))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().lshmf_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- tables
+    def set_factors(self, U0: torch.Tensor, V0: torch.Tensor):
+        """Initial U, V (copied); b, bh, W, C start at zero."""
+        self.U.copy_(U0)
+        self.V.copy_(V0)
+        for t in (self.bu, self.bv, self.W, self.C):
+            t.zero_()
+
+    # -- C ABI entry points
+    def ingest(self, u: torch.Tensor, i: torch.Tensor, rc: torch.Tensor):
+        assert u.dtype == torch.int32 and i.dtype == torch.int32 and rc.dtype == torch.uint8
+        assert u.is_contiguous() and i.is_contiguous() and rc.is_contiguous()
+        self._keep = (u, i, rc)
+        _check(lib().lshmf_ingest(self._h, _ptr(u), _ptr(i), _ptr(rc), u.numel(),
+                                  _stream(self.device)))
+
+    def build_lsh_neighbours(self, H: torch.Tensor, seed_fill: int):
+        assert H.dtype in (torch.int32,) and H.is_contiguous()
+        assert tuple(H.shape) == (self.dims.M, self.words)
+        _check(lib().build_lsh_neighbours(self._h, _ptr(H), C.c_uint64(seed_fill & (2**64 - 1)),
+                                          _stream(self.device)))
+
+    def sgd_epoch(self, alpha, lam, beta: float, epoch: int):
+        hp = HParams((C.c_float * 6)(*alpha), (C.c_float * 6)(*lam), beta, 0)
+        _check(lib().sgd_epoch(self._h, C.byref(hp), epoch, _stream(self.device)))
+
+    def predict(self, u: torch.Tensor, i: torch.Tensor, out: Optional[torch.Tensor] = None):
+        assert u.dtype == torch.int32 and i.dtype == torch.int32
+        if out is None:
+            out = torch.empty(u.numel(), dtype=torch.float32, device=self.device)
+        _check(lib().predict(self._h, _ptr(u), _ptr(i), u.numel(), _ptr(out), _stream(self.device)))
+        return out
+
+    def rmse(self, pred: torch.Tensor, rc: torch.Tensor, out: Optional[torch.Tensor] = None):
+        if out is None:
+            out = torch.empty(1, dtype=torch.float64, device=self.device)
+        _check(lib().lshmf_rmse(self._h, _ptr(pred), _ptr(rc), pred.numel(), _ptr(out),
+                                _stream(self.device)))
+        return out
+
+    def layout(self) -> Layout:
+        lay = Layout()
+        _check(lib().lshmf_export_layout(self._h, C.byref(lay)))
+        return lay
+
+    def device_status(self) -> int:
+        """The library's device status word (0 while healthy); synchronises."""
+        lay = self.layout()
+        torch.cuda.synchronize(self.device)
+        return int(self.arena_view(lay.err, 1, torch.int32).item())
+
+    def arena_view(self, ptr: int, n: int, dtype: torch.dtype) -> torch.Tensor:
+        """A tensor view of n elements of the library's arena starting at ptr."""
+        off = ptr - self.arena.data_ptr()
+        esz = torch.empty(0, dtype=dtype).element_size()
+        assert off >= 0 and off % esz == 0 and off + n * esz <= self.arena.numel()
+        return self.arena[off: off + n * esz].view(dtype)

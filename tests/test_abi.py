@@ -1,0 +1,63 @@
+"""The C-ABI library loads and exports every declared symbol; host-side checks.
+
+No GPU needed: only host code of the library runs here (validation and the
+arena size computation).
+"""
+import ctypes as C
+import os
+
+import pytest
+
+from paper_2111_11682_amd import lshmf
+
+
+def test_library_exports_every_header_function():
+    L = lshmf.lib()
+    names = lshmf.header_functions()
+    assert {"build_lsh_neighbours", "sgd_epoch", "predict", "lshmf_ingest",
+            "lshmf_rmse"} <= set(names)
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def _create(**kw):
+    base = dict(M=943, N=1682, F=32, K=10, G=8, p=1, q=8, rscale=1, psi_exp=2, n_strata=16,
+                storage=0, reserved=0, nnz=90000)
+    base.update(kw)
+    d = lshmf.Dims(*[base[f] for f, _ in lshmf.Dims._fields_])
+    h = C.c_void_p()
+    st = lshmf.lib().lshmf_create(C.byref(d), C.byref(h))
+    return st, h
+
+
+@pytest.mark.parametrize("bad", [dict(K=0), dict(K=1682), dict(K=129), dict(F=0), dict(F=257),
+                                 dict(G=8, p=5, q=1), dict(G=8, p=1, q=33), dict(rscale=3),
+                                 dict(psi_exp=0), dict(n_strata=0), dict(storage=1),
+                                 dict(nnz=-1), dict(M=0), dict(N=1)])
+def test_create_rejects_bad_dims(bad):
+    st, h = _create(**bad)
+    assert st == -1
+    assert lshmf.lib().lshmf_last_error()
+
+
+def test_arena_size_and_bind_checks():
+    st, h = _create()
+    assert st == 0
+    n = C.c_size_t()
+    assert lshmf.lib().lshmf_arena_bytes(h, C.byref(n)) == 0
+    assert n.value > 90000 * 20
+    t = lshmf.Tables(*([0] * 12))
+    assert lshmf.lib().lshmf_bind(h, C.byref(t), C.c_void_p(256), n.value) == -1   # NULL tables
+    t = lshmf.Tables(*([4096] * 12))
+    assert lshmf.lib().lshmf_bind(h, C.byref(t), C.c_void_p(4096 + 16), n.value) == -1  # unaligned
+    assert lshmf.lib().lshmf_bind(h, C.byref(t), C.c_void_p(4096), n.value - 1) == -3  # too small
+    # calls out of order report ESTATE without touching the device
+    assert lshmf.lib().sgd_epoch(h, None, 0, None) == -2
+    lshmf.lib().lshmf_destroy(h)
+
+
+def test_binding_has_no_cpu_fallback(monkeypatch):
+    monkeypatch.setattr(lshmf, "_lib", None)
+    monkeypatch.setattr(lshmf, "LIB_PATH", os.path.join(os.path.dirname(lshmf.LIB_PATH), "missing.so"))
+    with pytest.raises(ImportError):
+        lshmf.lib()
