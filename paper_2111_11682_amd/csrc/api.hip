@@ -41,13 +41,17 @@ size_t carve(lshmf_ctx* c, char* base)
     c->col_ptr = k.take<int64_t>(d.N + 1);
     c->csc_row = k.take<int32_t>(nnz);
     c->csc_rc = k.take<uint8_t>(nnz);
-    c->pk = k.take<uint32_t>(nnz);
+    c->pk = k.take<uint32_t>(nnz + kStreamPad);
     c->sj = k.take<int32_t>(nnz);
     c->dep = k.take<int32_t>(nnz);
-    c->nib = k.take<uint8_t>((size_t)nnz * c->nstride);
+    c->link = k.take<uint32_t>(nnz + kStreamPad);
+    c->nib = k.take<uint8_t>((size_t)(nnz + kStreamPad) * c->nstride);
     c->blk_ptr = k.take<int64_t>(P * P + 1);
     c->blk_seg = k.take<int64_t>(P * P + 1);
     c->seg_col = k.take<int32_t>(nnz);
+    c->blk_slots = k.take<int32_t>(P * P);
+    c->irank = k.take<int32_t>(d.N);
+    c->trash = k.take<float>(512);
     c->seg_start = k.take<int64_t>(nnz + 1);
     c->csr_spos = k.take<int32_t>(nnz);
     int64_t cn = nnz;
@@ -68,6 +72,7 @@ size_t carve(lshmf_ctx* c, char* base)
     if (scan_n2 > scan_n) scan_n = scan_n2;
     c->scan_tmp = k.take<int64_t>(scan_n);
     c->red = k.take<double>(1024);
+    c->nbr_b0 = k.take<float>((size_t)d.N * d.K);
     c->bitem = k.take<int32_t>(nq);
     c->bbegin = k.take<int32_t>(nq + 1);
     c->bpos = k.take<int32_t>(nq);

@@ -11,6 +11,7 @@
 namespace lshmf {
 
 constexpr int kWave = 64;
+constexpr int kStreamPad = 64;  // zeroed records after the stream arrays (read-ahead of the SGD)
 
 // ---------------------------------------------------------------- errors
 void set_error(const char* fmt, ...);
@@ -88,10 +89,14 @@ struct lshmf_ctx {
     uint32_t* pk;        // nnz   block stream: (i << 4) | rc
     int32_t* sj;         // nnz   item of each stream rating
     int32_t* dep;        // nnz   previous rating of the same user inside the block (local), -1
+    uint32_t* link;      // nnz   hand-over word of the SGD kernel (successor, predecessor, chain pos, slot)
     uint8_t* nib;        // nnz*nstride  4-bit codes of r_{i, JK[j][k]} (0: not rated)
     int64_t* blk_ptr;    // P*P+1 block b of stratum s = entry s*P + b
     int64_t* blk_seg;    // P*P+1 first segment of each block
     int32_t* seg_col;    // nnz   item of each segment (a run of one item inside a block)
+    int32_t* blk_slots;  // P*P   mailbox slots (users with several ratings) per block
+    int32_t* irank;      // N     item order inside blocks: degree desc, id asc
+    float* trash;        // 512   sink for the stores of read-ahead slots past a segment
     int64_t* seg_start;  // nnz+1
     int32_t* csr_spos;   // nnz   stream position of each CSR rating
     int64_t* cnt;        // max(M,N,P*P,nnz)+1 counters / flags
@@ -100,9 +105,12 @@ struct lshmf_ctx {
     int64_t* hist;       // radix histogram
     int64_t* scan_tmp;
     double* red;         // FP64 reduction partials
+    float* nbr_b0;       // N*K   fixed baseline bh0 of each neighbour slot
     int32_t* bitem;      // q*N  items sorted by (band, key)
     int32_t* bbegin;     // q*N+1 bucket starts (by bucket id)
     int32_t* bpos;       // q*N  bucket id of (band t, item j) at t*N + j
     int32_t* err;        // device error flag
-    int64_t max_block_nnz;  // host copy after ingest
+    int64_t max_block_nnz;  // host copies after ingest
+    int64_t max_block_slots;
+    int64_t nseg;
 };

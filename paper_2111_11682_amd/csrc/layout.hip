@@ -35,13 +35,14 @@ __global__ void k_keys_pair(const int32_t* major, const int32_t* minor, int64_t 
 }
 
 struct StratKey {
-    int64_t P, MP, NP;  // strata, ceil(M/P), ceil(N/P)
+    int64_t P, MP, N;  // strata, ceil(M/P), items
 };
 
-// Stream order: (stratum s, block b, item j, user i).  Users i = b mod P and
-// items j = (b+s) mod P inside a block, so (s, b, j/P, i/P) orders the same.
-__global__ void k_keys_stream(const int32_t* u, const int32_t* it, int64_t n, StratKey sk,
-                              uint64_t* keys, uint32_t* vals)
+// Stream order: (stratum s, block b, item rank, user i), where an item's rank
+// orders items by decreasing training degree, then id.  Users inside a block
+// are i = b mod P, so i/P orders them like i.
+__global__ void k_keys_stream(const int32_t* u, const int32_t* it, const int32_t* rank, int64_t n,
+                              StratKey sk, uint64_t* keys, uint32_t* vals)
 {
     for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < n;
          x += (int64_t)gridDim.x * blockDim.x) {
@@ -49,9 +50,28 @@ __global__ void k_keys_stream(const int32_t* u, const int32_t* it, int64_t n, St
         const int64_t rb = i % sk.P, cb = j % sk.P;
         const int64_t s = (cb - rb + sk.P) % sk.P;
         const uint64_t blk = (uint64_t)(s * sk.P + rb);
-        keys[x] = ((blk * (uint64_t)sk.NP + (uint64_t)(j / sk.P)) * (uint64_t)sk.MP) + (uint64_t)(i / sk.P);
+        keys[x] = ((blk * (uint64_t)sk.N + (uint64_t)rank[j]) * (uint64_t)sk.MP) + (uint64_t)(i / sk.P);
         vals[x] = (uint32_t)x;
     }
+}
+
+// Items by (training degree desc, id asc): key = (nnz - deg) * 2^idbits + j.
+__global__ void k_keys_rank(const int64_t* col_ptr, int32_t N, int64_t nnz, int idbits, uint64_t* keys,
+                            uint32_t* vals)
+{
+    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < N;
+         j += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t deg = col_ptr[j + 1] - col_ptr[j];
+        keys[j] = ((uint64_t)(nnz - deg) << idbits) | (uint64_t)j;
+        vals[j] = (uint32_t)j;
+    }
+}
+
+__global__ void k_rank_fill(const uint32_t* order, int32_t N, int32_t* rank)
+{
+    for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < N;
+         x += (int64_t)gridDim.x * blockDim.x)
+        rank[order[x]] = (int32_t)x;
 }
 
 __device__ inline int64_t block_of(int64_t i, int64_t j, int64_t P)
@@ -108,30 +128,69 @@ __global__ void k_blk_seg(const int64_t* blk_ptr, const int64_t* ex, int64_t nbl
     }
 }
 
-// Dependency order: (s, b, user i, item j); value = stream position.
-__global__ void k_keys_dep(const int32_t* u, const int32_t* it, const int32_t* e2s, int64_t n,
-                           StratKey sk, uint64_t* keys, uint32_t* vals)
+// Dependency order: (s, b, user i, item rank); value = stream position.
+__global__ void k_keys_dep(const int32_t* u, const int32_t* it, const int32_t* rank, const int32_t* e2s,
+                           int64_t n, StratKey sk, uint64_t* keys, uint32_t* vals)
 {
     for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < n;
          x += (int64_t)gridDim.x * blockDim.x) {
         const int64_t i = u[x], j = it[x];
         const uint64_t blk = (uint64_t)block_of(i, j, sk.P);
-        keys[x] = ((blk * (uint64_t)sk.MP + (uint64_t)(i / sk.P)) * (uint64_t)sk.NP) + (uint64_t)(j / sk.P);
+        keys[x] = ((blk * (uint64_t)sk.MP + (uint64_t)(i / sk.P)) * (uint64_t)sk.N) + (uint64_t)rank[j];
         vals[x] = (uint32_t)e2s[x];
     }
 }
 
-__global__ void k_dep_fill(const uint64_t* keys, const uint32_t* pos, int64_t n, int64_t NP,
-                           const int32_t* blk_of_pos, const int64_t* blk_ptr, int32_t* dep)
+__device__ inline bool same_user_block(const uint64_t* keys, int64_t a, int64_t b, int64_t N)
+{
+    return keys[a] / (uint64_t)N == keys[b] / (uint64_t)N;
+}
+
+// A user with several ratings in a block gets a mailbox slot in that block:
+// flag the first rating of each such chain (in (block, user, item rank) order).
+__global__ void k_chain_flags(const uint64_t* keys, int64_t n, int64_t N, int64_t* flag)
+{
+    for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < n;
+         x += (int64_t)gridDim.x * blockDim.x) {
+        const bool pred = x > 0 && same_user_block(keys, x, x - 1, N);
+        const bool succ = x + 1 < n && same_user_block(keys, x, x + 1, N);
+        flag[x] = (!pred && succ) ? 1 : 0;
+    }
+}
+
+// dep[p]: local index (inside the block) of the previous rating of the same
+// user, or -1.  link[p] drives the SGD kernel's hand-over of user rows
+// between waves: bit 31 = a later rating of the user follows in the block,
+// bit 30 = an earlier one precedes, bits 16..29 = position in the user's
+// chain, bits 0..15 = the chain's mailbox slot in the block.
+__global__ void k_dep_fill(const uint64_t* keys, const uint32_t* pos, int64_t n, int64_t N,
+                           const int32_t* blk_of_pos, const int64_t* blk_ptr, const int64_t* ex, int32_t* dep,
+                           uint32_t* link)
 {
     for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < n;
          x += (int64_t)gridDim.x * blockDim.x) {
         const uint32_t p = pos[x];
-        int32_t d = -1;
-        if (x > 0 && keys[x] / (uint64_t)NP == keys[x - 1] / (uint64_t)NP)
-            d = (int32_t)((int64_t)pos[x - 1] - blk_ptr[blk_of_pos[p]]);
-        dep[p] = d;
+        const int64_t blk = blk_of_pos[p];
+        const bool pred = x > 0 && same_user_block(keys, x, x - 1, N);
+        const bool succ = x + 1 < n && same_user_block(keys, x, x + 1, N);
+        int64_t q = 0;
+        while (x - q > 0 && same_user_block(keys, x - q, x - q - 1, N)) ++q;
+        dep[p] = pred ? (int32_t)((int64_t)pos[x - 1] - blk_ptr[blk]) : -1;
+        uint32_t lk = 0;
+        if (pred || succ) {
+            const int64_t slot = ex[x - q] - ex[blk_ptr[blk]];
+            lk = (succ ? 0x80000000u : 0u) | (pred ? 0x40000000u : 0u) | ((uint32_t)q << 16) | (uint32_t)slot;
+        }
+        link[p] = lk;
     }
+}
+
+// mailbox slots used by each block
+__global__ void k_block_slots(const int64_t* blk_ptr, const int64_t* ex, int64_t nblk, int32_t* out)
+{
+    for (int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; b < nblk;
+         b += (int64_t)gridDim.x * blockDim.x)
+        out[b] = (int32_t)(ex[blk_ptr[b + 1]] - ex[blk_ptr[b]]);
 }
 
 // CSR / CSC payloads after their sorts.
@@ -193,7 +252,7 @@ int ingest(lshmf_ctx* c, const int32_t* u, const int32_t* it, const uint8_t* rc,
 {
     const lshmf_dims& d = c->d;
     const int64_t P = c->P;
-    const StratKey sk{P, ceil_div(d.M, P), ceil_div(d.N, P)};
+    const StratKey sk{P, ceil_div(d.M, P), d.N};
     int ri = 0;
 
     LSHMF_TRY(fill_i32(c->err, 2, 0, s));
@@ -208,24 +267,39 @@ int ingest(lshmf_ctx* c, const int32_t* u, const int32_t* it, const uint8_t* rc,
         return LSHMF_EINVAL;
     }
 
+    // -- CSC by item (item degrees order the items inside a block)
+    hipLaunchKernelGGL(k_keys_pair, dim3(grid_for(n)), dim3(256), 0, s, it, u, n, (int64_t)d.M, c->sk[0], c->sv[0]);
+    LSHMF_LAUNCHED("k_keys_pair(csc)");
+    LSHMF_TRY(radix_sort(c->sk, c->sv, n, bits_for((uint64_t)d.M * (uint64_t)d.N), c->hist, c->scan_tmp, s, &ri));
+    hipLaunchKernelGGL(k_gather_pair, dim3(grid_for(n)), dim3(256), 0, s, c->sv[ri], u, rc, n, c->csc_row,
+                       c->csc_rc, nullptr, nullptr);
+    LSHMF_LAUNCHED("k_gather_pair(csc)");
+    LSHMF_TRY(count_bins(it, n, c->cnt, d.N, s));
+    LSHMF_TRY(scan_excl(c->cnt, c->col_ptr, d.N, c->scan_tmp, s));
+
+    // -- item rank: training degree descending, id ascending
+    const int idbits = bits_for((uint64_t)d.N);
+    hipLaunchKernelGGL(k_keys_rank, dim3(grid_for(d.N)), dim3(256), 0, s, c->col_ptr, d.N, n, idbits, c->sk[0],
+                       c->sv[0]);
+    LSHMF_LAUNCHED("k_keys_rank");
+    LSHMF_TRY(radix_sort(c->sk, c->sv, d.N, idbits + bits_for((uint64_t)n + 1), c->hist, c->scan_tmp, s, &ri));
+    hipLaunchKernelGGL(k_rank_fill, dim3(grid_for(d.N)), dim3(256), 0, s, c->sv[ri], d.N, c->irank);
+    LSHMF_LAUNCHED("k_rank_fill");
+
     // -- stratified block stream
-    int32_t* e2s = c->csr_spos;       // reused: edge -> stream position (nnz int32)
-    int32_t* blk_of_pos = c->seg_col; // reused until segments are written
-    hipLaunchKernelGGL(k_keys_stream, dim3(grid_for(n)), dim3(256), 0, s, u, it, n, sk, c->sk[0], c->sv[0]);
+    int32_t* e2s = c->csr_spos;                              // edge -> stream position until the CSR step
+    int32_t* bop = reinterpret_cast<int32_t*>(c->cnt);       // block of each stream position
+    hipLaunchKernelGGL(k_keys_stream, dim3(grid_for(n)), dim3(256), 0, s, u, it, c->irank, n, sk, c->sk[0],
+                       c->sv[0]);
     LSHMF_LAUNCHED("k_keys_stream");
-    const int sbits = bits_for((uint64_t)(P * P) * (uint64_t)sk.NP * (uint64_t)sk.MP);
+    const int sbits = bits_for((uint64_t)(P * P) * (uint64_t)sk.N * (uint64_t)sk.MP);
     LSHMF_TRY(radix_sort(c->sk, c->sv, n, sbits, c->hist, c->scan_tmp, s, &ri));
-    // the dependency arrays below need e2s, and blk_of_pos lives in seg_col:
-    // keep blk_of_pos in the cnt region instead (int64 sized, cast to int32)
-    int32_t* bop = reinterpret_cast<int32_t*>(c->cnt);
-    (void)blk_of_pos;
     hipLaunchKernelGGL(k_stream_fill, dim3(grid_for(n)), dim3(256), 0, s, c->sv[ri], u, it, rc, n, P,
                        c->pk, c->sj, bop, e2s);
     LSHMF_LAUNCHED("k_stream_fill");
-    // block pointers
     LSHMF_TRY(count_bins(bop, n, c->blk_seg, P * P, s));       // blk_seg as a temporary
     LSHMF_TRY(scan_excl(c->blk_seg, c->blk_ptr, P * P, c->scan_tmp, s));
-    // segments: flags in seg_start (int64, nnz+1 entries), scanned in place
+    // segments: a run of one item inside a block
     hipLaunchKernelGGL(k_seg_flags, dim3(grid_for(n)), dim3(256), 0, s, c->sj, bop, n, c->seg_start);
     LSHMF_LAUNCHED("k_seg_flags");
     int64_t* ex = reinterpret_cast<int64_t*>(c->sk[ri ^ 1]);  // free sort buffer, n+1 int64
@@ -237,12 +311,22 @@ int ingest(lshmf_ctx* c, const int32_t* u, const int32_t* it, const uint8_t* rc,
                        c->blk_seg);
     LSHMF_LAUNCHED("k_blk_seg");
     // dependencies: previous rating of the same user inside the block
-    hipLaunchKernelGGL(k_keys_dep, dim3(grid_for(n)), dim3(256), 0, s, u, it, e2s, n, sk, c->sk[0], c->sv[0]);
+    hipLaunchKernelGGL(k_keys_dep, dim3(grid_for(n)), dim3(256), 0, s, u, it, c->irank, e2s, n, sk, c->sk[0],
+                       c->sv[0]);
     LSHMF_LAUNCHED("k_keys_dep");
     LSHMF_TRY(radix_sort(c->sk, c->sv, n, sbits, c->hist, c->scan_tmp, s, &ri));
-    hipLaunchKernelGGL(k_dep_fill, dim3(grid_for(n)), dim3(256), 0, s, c->sk[ri], c->sv[ri], n, sk.NP,
-                       bop, c->blk_ptr, c->dep);
+    int64_t* chain = reinterpret_cast<int64_t*>(c->sk[ri ^ 1]);  // n+1 int64, scanned in place
+    hipLaunchKernelGGL(k_chain_flags, dim3(grid_for(n)), dim3(256), 0, s, c->sk[ri], n, sk.N, chain);
+    LSHMF_LAUNCHED("k_chain_flags");
+    LSHMF_TRY(scan_excl(chain, chain, n, c->scan_tmp, s));
+    hipLaunchKernelGGL(k_dep_fill, dim3(grid_for(n)), dim3(256), 0, s, c->sk[ri], c->sv[ri], n, sk.N, bop,
+                       c->blk_ptr, chain, c->dep, c->link);
     LSHMF_LAUNCHED("k_dep_fill");
+    hipLaunchKernelGGL(k_block_slots, dim3(grid_for(P * P)), dim3(256), 0, s, c->blk_ptr, chain, P * P, c->blk_slots);
+    LSHMF_LAUNCHED("k_block_slots");
+    // zero tails: the SGD kernel reads a few records past a segment's end
+    LSHMF_TRY(fill_i32(reinterpret_cast<int32_t*>(c->pk) + n, kStreamPad, 0, s));
+    LSHMF_TRY(fill_i32(reinterpret_cast<int32_t*>(c->link) + n, kStreamPad, 0, s));
 
     // -- CSR by user, with the stream position of each rating
     hipLaunchKernelGGL(k_keys_pair, dim3(grid_for(n)), dim3(256), 0, s, u, it, n, (int64_t)d.N, c->sk[0], c->sv[0]);
@@ -256,16 +340,6 @@ int ingest(lshmf_ctx* c, const int32_t* u, const int32_t* it, const uint8_t* rc,
     LSHMF_LAUNCHED("k_gather_pair(csr)");
     LSHMF_TRY(count_bins(u, n, c->cnt, d.M, s));
     LSHMF_TRY(scan_excl(c->cnt, c->row_ptr, d.M, c->scan_tmp, s));
-
-    // -- CSC by item
-    hipLaunchKernelGGL(k_keys_pair, dim3(grid_for(n)), dim3(256), 0, s, it, u, n, (int64_t)d.M, c->sk[0], c->sv[0]);
-    LSHMF_LAUNCHED("k_keys_pair(csc)");
-    LSHMF_TRY(radix_sort(c->sk, c->sv, n, bits_for((uint64_t)d.M * (uint64_t)d.N), c->hist, c->scan_tmp, s, &ri));
-    hipLaunchKernelGGL(k_gather_pair, dim3(grid_for(n)), dim3(256), 0, s, c->sv[ri], u, rc, n, c->csc_row,
-                       c->csc_rc, nullptr, nullptr);
-    LSHMF_LAUNCHED("k_gather_pair(csc)");
-    LSHMF_TRY(count_bins(it, n, c->cnt, d.N, s));
-    LSHMF_TRY(scan_excl(c->cnt, c->col_ptr, d.N, c->scan_tmp, s));
 
     // -- baselines (Sec. 3.2, simple case), FP64
     unsigned long long* total = reinterpret_cast<unsigned long long*>(c->cnt);
@@ -281,18 +355,29 @@ int ingest(lshmf_ctx* c, const int32_t* u, const int32_t* it, const uint8_t* rc,
                        c->csc_rc, (int64_t)d.N, d.rscale, c->t.mu, c->t.bh0);
     LSHMF_LAUNCHED("k_row_means(items)");
 
-    // largest block, for the LDS capacity check of the SGD kernel
-    int64_t* hptr = new int64_t[P * P + 1];
-    hipError_t e = hipMemcpyAsync(hptr, c->blk_ptr, sizeof(int64_t) * (P * P + 1), hipMemcpyDeviceToHost, s);
+    // largest block and most mailbox slots in a block, for the SGD kernel's limits
+    const int64_t nb = P * P + 1;
+    int64_t* hptr = new int64_t[2 * nb];
+    int32_t* hslots = new int32_t[nb];
+    hipError_t e = hipMemcpyAsync(hptr, c->blk_ptr, sizeof(int64_t) * nb, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(hptr + nb, c->blk_seg, sizeof(int64_t) * nb, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(hslots, c->blk_slots, sizeof(int32_t) * (nb - 1), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
         delete[] hptr;
+        delete[] hslots;
         return hip_fail(e, "ingest: block pointers");
     }
-    int64_t mx = 0;
-    for (int64_t b = 0; b < P * P; ++b) mx = hptr[b + 1] - hptr[b] > mx ? hptr[b + 1] - hptr[b] : mx;
+    int64_t mx = 0, msl = 0;
+    for (int64_t b = 0; b < P * P; ++b) {
+        mx = hptr[b + 1] - hptr[b] > mx ? hptr[b + 1] - hptr[b] : mx;
+        msl = hslots[b] > msl ? hslots[b] : msl;
+    }
+    c->nseg = hptr[nb + P * P];
     delete[] hptr;
+    delete[] hslots;
     c->max_block_nnz = mx;
+    c->max_block_slots = msl;
     return LSHMF_OK;
 }
 

@@ -339,6 +339,13 @@ __global__ __launch_bounds__(256) void k_nbr_codes(const uint32_t* pk, const int
     }
 }
 
+__global__ void k_nbr_b0(const int32_t* JK, const float* bh0, int64_t n, float* out)
+{
+    for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < n;
+         x += (int64_t)gridDim.x * blockDim.x)
+        out[x] = bh0[JK[x]];
+}
+
 static unsigned grid_for(int64_t n, int threads = 256, int64_t cap = 16384)
 {
     int64_t b = ceil_div(n > 0 ? n : 1, threads);
@@ -382,6 +389,10 @@ int build_neighbours(lshmf_ctx* c, const uint32_t* H, uint64_t seed_fill, hipStr
                            d.N, d.q, d.K, seed_fill, c->t.JK, j0);
         LSHMF_LAUNCHED("k_topk");
     }
+    // fixed baselines of the neighbour slots (read once per item segment by the SGD)
+    hipLaunchKernelGGL(k_nbr_b0, dim3(grid_for((int64_t)d.N * d.K)), dim3(256), 0, s, c->t.JK, c->t.bh0,
+                       (int64_t)d.N * d.K, c->nbr_b0);
+    LSHMF_LAUNCHED("k_nbr_b0");
     // neighbour codes of every training rating
     if (nnz > 0) {
         hipLaunchKernelGGL(k_nbr_codes, dim3(grid_for(nnz * kWave, 256, 65536)), dim3(256), 0, s, c->pk, c->sj,

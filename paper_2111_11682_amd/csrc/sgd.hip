@@ -18,20 +18,20 @@
 namespace lshmf {
 
 constexpr int kSgdWaves = 8;
-constexpr int kMaxBlockNnz = 1 << 16;   // LDS done-flags: 8 KB
-constexpr int kSpinLimit = 1 << 24;     // bounded wait: a broken dependency ends the kernel
+constexpr int kGroup = 8;                        // ratings per pipeline stage
+constexpr int kSpinLimit = 1 << 24;              // bounded wait: a broken hand-over ends the kernel
+constexpr int kMaxMailboxBytes = 150 * 1024;     // dynamic LDS of one block
+constexpr int kMaxChainPos = (1 << 14) - 1;      // link encoding limits
+constexpr int kMaxSlots = (1 << 16) - 2;
 
 struct SgdArgs {
-    const uint32_t* pk;
-    const int32_t* dep;
     const uint8_t* nib;
     const int64_t* blk_ptr;
     const int64_t* blk_seg;
     const int32_t* seg_col;
     const int64_t* seg_start;
-    const int32_t* JK;
+    const float* nbr_b0;
     const float* b0;
-    const float* bh0;
     const double* mu;
     float* U;
     float* V;
@@ -39,43 +39,80 @@ struct SgdArgs {
     float* bv;
     float* W;
     float* C;
+    float* trash;
     int32_t* err;
-    int F, K, P, nstride, s;
+    int F, K, P, nstride, s, slots;
     float inv_s;
     float g[6], l[6];
 };
 
-__device__ inline float wave_sum(float v)
+template <int CTRL, int ROW_MASK, bool BOUND_ZERO>
+__device__ inline float dpp_f32(float x)
 {
-#pragma unroll
-    for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
-    return v;
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), CTRL, ROW_MASK,
+                                                                 0xF, BOUND_ZERO));
 }
 
-template <int FP, int KP>
-__global__ __launch_bounds__(kSgdWaves* kWave) void k_sgd_stratum(SgdArgs a)
+// Full 64-lane sum with DPP row operations; the total ends in lane 63 and is
+// broadcast through a scalar register.  Fixed association order.
+__device__ inline float wave_sum(float v)
 {
-    __shared__ uint32_t done[kMaxBlockNnz / 32];
+    v += dpp_f32<0xB1, 0xF, true>(v);    // quad_perm [1,0,3,2]
+    v += dpp_f32<0x4E, 0xF, true>(v);    // quad_perm [2,3,0,1]
+    v += dpp_f32<0x141, 0xF, true>(v);   // row_half_mirror
+    v += dpp_f32<0x140, 0xF, true>(v);   // row_mirror: every lane holds its row's sum
+    v += dpp_f32<0x142, 0xA, false>(v);  // row_bcast:15 into rows 1 and 3
+    v += dpp_f32<0x143, 0xC, false>(v);  // row_bcast:31 into rows 2 and 3
+    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 63));
+}
+
+// User-side inputs of one group of ratings, loaded a group ahead of use.  A
+// user rated earlier in the same block is read from the block's LDS mailbox
+// (m*), otherwise from HBM (g*); both loads are always issued so that every
+// group issues the same memory operations.
+template <int FP, int KP>
+struct Stage {
+    float gu[kGroup][FP];
+    float mu[kGroup][FP];
+    float gbi[kGroup], mbi[kGroup], b0[kGroup];
+    uint32_t nb[kGroup][KP];  // raw neighbour-code bytes of this lane's slots
+    uint32_t pk[kGroup];      // (user << 4) | code
+    uint32_t lk[kGroup];      // hand-over word
+};
+
+template <int FP, int KP>
+__global__ __launch_bounds__(kSgdWaves* kWave) void k_sgd_stratum(SgdArgs a, const uint32_t* __restrict__ pk,
+                                                                   const uint32_t* __restrict__ link)
+{
+    // mailbox: slots + 1 rows (the last is a write sink) of F floats, b_i, sequence
+    extern __shared__ float smem[];
     __shared__ int next_seg;
+    const int F = a.F, K = a.K;
+    const int dummy = a.slots;
+    float* mb_u = smem;
+    float* mb_b = smem + (size_t)(dummy + 1) * F;
+    int* mb_seq = reinterpret_cast<int*>(mb_b + dummy + 1);
     const int lane = threadIdx.x & (kWave - 1);
     const int64_t blk = (int64_t)a.s * a.P + blockIdx.x;
-    const int64_t e0 = a.blk_ptr[blk], e1 = a.blk_ptr[blk + 1];
     const int64_t g0 = a.blk_seg[blk], g1 = a.blk_seg[blk + 1];
-    const int nwords = (int)((e1 - e0 + 31) / 32);
-    for (int x = threadIdx.x; x < nwords; x += blockDim.x) done[x] = 0;
+    const int nsegs = (int)(g1 - g0);
+    for (int x = threadIdx.x; x <= dummy; x += blockDim.x) mb_seq[x] = 0;
     if (threadIdx.x == 0) next_seg = 0;
     __syncthreads();
     const float mu = (float)(*a.mu);
-    const int F = a.F, K = a.K;
+    const float inv_s = a.inv_s;
+
     while (true) {
         int g = 0;
         if (lane == 0) g = atomicAdd(&next_seg, 1);
-        g = __shfl(g, 0, kWave);
-        if (g >= g1 - g0) break;
+        g = __builtin_amdgcn_readfirstlane(g);
+        if (g >= nsegs) break;
         const int64_t seg = g0 + g;
         const int64_t j = a.seg_col[seg];
         const int64_t ea = a.seg_start[seg], ez = a.seg_start[seg + 1];
+        if (ez - ea > 4 * kGroup) __builtin_amdgcn_s_setprio(2);
 
+        // item state, register resident for the whole segment
         float v[FP], w[KP], c[KP], bhn[KP];
 #pragma unroll
         for (int x = 0; x < FP; ++x) {
@@ -90,87 +127,167 @@ __global__ __launch_bounds__(kSgdWaves* kWave) void k_sgd_stratum(SgdArgs a)
             if (k < K) {
                 w[y] = a.W[j * K + k];
                 c[y] = a.C[j * K + k];
-                bhn[y] = a.bh0[a.JK[j * K + k]];
+                bhn[y] = a.nbr_b0[j * K + k];
             }
         }
 
-        for (int64_t e = ea; e < ez; ++e) {
-            const int d = a.dep[e];
-            if (d >= 0) {
-                int spins = 0;
-                while (!((__hip_atomic_load(&done[d >> 5], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) >>
-                          (d & 31)) & 1u)) {
-                    if (++spins > kSpinLimit) {
-                        if (lane == 0) atomicOr(a.err, 2);
-                        break;
+        // (user, code) and hand-over words of a group: one vector load each
+        auto words = [&](uint32_t& px, uint32_t& lx, int64_t gb) {
+            px = lane < kGroup ? pk[gb + lane] : 0u;
+            lx = lane < kGroup ? link[gb + lane] : 0u;
+        };
+        // wait for an earlier rating of the same user, then load the inputs
+        auto stage = [&](Stage<FP, KP>& S, uint32_t px, uint32_t lx, int64_t gb) {
+#pragma unroll
+            for (int sl = 0; sl < kGroup; ++sl) {
+                const uint32_t pw = (uint32_t)__builtin_amdgcn_readlane((int)px, sl);
+                const uint32_t lw = (uint32_t)__builtin_amdgcn_readlane((int)lx, sl);
+                const bool has_pred = gb + sl < ez && ((lw >> 30) & 1u);
+                const int slot = (int)(lw & 0xFFFFu);
+                if (has_pred) {
+                    const int want = (int)((lw >> 16) & 0x3FFFu);
+                    int spins = 0;
+                    while (__hip_atomic_load(&mb_seq[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) != want) {
+                        if (++spins > kSpinLimit) {
+                            if (lane == 0) atomicOr(a.err, 2);
+                            break;
+                        }
+                        __builtin_amdgcn_s_sleep(1);
                     }
-                    __builtin_amdgcn_s_sleep(1);
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
                 }
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-            }
-            const uint32_t pk = a.pk[e];
-            const int64_t i = pk >> 4;
-            const float r = (float)(pk & 15u) * a.inv_s;
-            float u[FP];
+                S.pk[sl] = pw;
+                S.lk[sl] = lw;
+                const int64_t i = pw >> 4;
+                const float* urow = has_pred ? a.trash : a.U + i * F;
+                const int rs = has_pred ? slot : dummy;
 #pragma unroll
-            for (int x = 0; x < FP; ++x) {
-                const int f = lane + x * kWave;
-                u[x] = f < F ? a.U[i * F + f] : 0.0f;
-            }
-            const float bi = a.bu[i];
-            const float base_i = mu + a.b0[i];
-            const uint8_t* nb = a.nib + e * a.nstride;
-            int code[KP];
-            int nR = 0;
+                for (int x = 0; x < FP; ++x) {
+                    const int f = lane + x * kWave;
+                    S.gu[sl][x] = f < F ? urow[f] : 0.0f;
+                    S.mu[sl][x] = f < F ? mb_u[rs * F + f] : 0.0f;
+                }
+                S.gbi[sl] = has_pred ? a.trash[F] : a.bu[i];
+                S.mbi[sl] = mb_b[rs];
+                S.b0[sl] = a.b0[i];
+                const uint8_t* nbp = a.nib + (gb + sl) * a.nstride;
 #pragma unroll
-            for (int y = 0; y < KP; ++y) {
-                const int k = lane + y * kWave;
-                code[y] = k < K ? (nb[k >> 1] >> ((k & 1) * 4)) & 15 : 0;
-                nR += __popcll(__ballot(code[y] != 0));
-            }
-            const int nN = K - nR;
-            const float sR = nR > 0 ? 1.0f / sqrtf((float)nR) : 0.0f;
-            const float sN = nN > 0 ? 1.0f / sqrtf((float)nN) : 0.0f;
-
-            float part = 0.0f;
-#pragma unroll
-            for (int x = 0; x < FP; ++x) part += u[x] * v[x];
-            float resid[KP];
-#pragma unroll
-            for (int y = 0; y < KP; ++y) {
-                const int k = lane + y * kWave;
-                resid[y] = (float)code[y] * a.inv_s - base_i - bhn[y];
-                if (k < K) part += code[y] ? resid[y] * w[y] * sR : c[y] * sN;
-            }
-            const float rhat = mu + bi + bh + wave_sum(part);
-            const float err = r - rhat;
-
-            if (lane == 0) a.bu[i] = bi + a.g[0] * (err - a.l[0] * bi);
-            bh = bh + a.g[1] * (err - a.l[1] * bh);
-#pragma unroll
-            for (int x = 0; x < FP; ++x) {
-                const int f = lane + x * kWave;
-                if (f < F) {
-                    a.U[i * F + f] = u[x] + a.g[2] * (err * v[x] - a.l[2] * u[x]);
-                    v[x] = v[x] + a.g[3] * (err * u[x] - a.l[3] * v[x]);
+                for (int y = 0; y < KP; ++y) {
+                    const int byte = (lane >> 1) + y * (kWave / 2);
+                    S.nb[sl][y] = byte < a.nstride ? nbp[byte] : 0u;
                 }
             }
+        };
+        // Eq. (rr) and Eq. (sgd_update) for the ratings of one group, in order;
+        // then hand the updated user rows to later ratings of the same users
+        auto compute = [&](Stage<FP, KP>& S, int64_t gb) {
 #pragma unroll
-            for (int y = 0; y < KP; ++y) {
-                const int k = lane + y * kWave;
-                if (k < K) {
-                    if (code[y]) w[y] += a.g[4] * (sR * err * resid[y] - a.l[4] * w[y]);
-                    else c[y] += a.g[5] * (sN * err - a.l[5] * c[y]);
+            for (int sl = 0; sl < kGroup; ++sl) {
+                const bool valid = gb + sl < ez;
+                const uint32_t lw = S.lk[sl];
+                const bool has_pred = valid && ((lw >> 30) & 1u);
+                const bool has_succ = valid && (lw >> 31);
+                const int slot = (int)(lw & 0xFFFFu);
+                const int64_t i = S.pk[sl] >> 4;
+                const float r = (float)(S.pk[sl] & 15u) * inv_s;
+                const float base_i = mu + S.b0[sl];
+                int code[KP];
+                float resid[KP];
+                int nR = 0;
+#pragma unroll
+                for (int y = 0; y < KP; ++y) {
+                    const int k = lane + y * kWave;
+                    code[y] = k < K ? (int)((S.nb[sl][y] >> ((lane & 1) * 4)) & 15u) : 0;
+                    resid[y] = (float)code[y] * inv_s - base_i - bhn[y];
+                    nR += __popcll(__ballot(code[y] != 0));
+                }
+                const float sR = nR > 0 ? __builtin_amdgcn_rsqf((float)nR) : 0.0f;
+                const float sN = K - nR > 0 ? __builtin_amdgcn_rsqf((float)(K - nR)) : 0.0f;
+                float u[FP];
+#pragma unroll
+                for (int x = 0; x < FP; ++x) u[x] = has_pred ? S.mu[sl][x] : S.gu[sl][x];
+                const float bi = has_pred ? S.mbi[sl] : S.gbi[sl];
+                // u.v + |R^K|^-1/2 sum resid*w + |N^K|^-1/2 sum c: one reduction
+                float part = 0.0f;
+#pragma unroll
+                for (int x = 0; x < FP; ++x) part += u[x] * v[x];
+#pragma unroll
+                for (int y = 0; y < KP; ++y)
+                    if (lane + y * kWave < K) part += code[y] ? resid[y] * w[y] * sR : c[y] * sN;
+                const float err = r - (mu + bi + bh + wave_sum(part));
+                // all right-hand sides from the pre-step state.  The last rating
+                // of a user in the block writes HBM; earlier ones only the mailbox.
+                // Slots past the segment end write to sinks.
+                const bool to_hbm = valid && !has_succ;
+                float* bu_dst = to_hbm ? a.bu + i : a.trash + F;
+                float* u_dst = to_hbm ? a.U + i * F : a.trash;
+                const int ws = has_succ ? slot : dummy;
+                const float bnew = bi + a.g[0] * (err - a.l[0] * bi);
+                if (lane == 0) {
+                    *bu_dst = bnew;
+                    mb_b[ws] = bnew;
+                }
+                const float bh_new = bh + a.g[1] * (err - a.l[1] * bh);
+                bh = valid ? bh_new : bh;
+#pragma unroll
+                for (int x = 0; x < FP; ++x) {
+                    const int f = lane + x * kWave;
+                    const float unew = u[x] + a.g[2] * (err * v[x] - a.l[2] * u[x]);
+                    if (f < F) {
+                        u_dst[f] = unew;
+                        mb_u[ws * F + f] = unew;
+                    }
+                    const float vn = v[x] + a.g[3] * (err * u[x] - a.l[3] * v[x]);
+                    v[x] = valid ? vn : v[x];
+                }
+#pragma unroll
+                for (int y = 0; y < KP; ++y) {
+                    if (lane + y * kWave < K) {
+                        const float wn = w[y] + a.g[4] * (sR * err * resid[y] - a.l[4] * w[y]);
+                        const float cn = c[y] + a.g[5] * (sN * err - a.l[5] * c[y]);
+                        w[y] = (valid && code[y]) ? wn : w[y];
+                        c[y] = (valid && !code[y]) ? cn : c[y];
+                    }
                 }
             }
-            // publish this rating's user-side writes to the other waves of the block
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+            // the mailbox rows are written: publish their sequence numbers
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
             if (lane == 0) {
-                const int64_t le = e - e0;
-                __hip_atomic_fetch_or(&done[le >> 5], 1u << (le & 31), __ATOMIC_RELAXED,
-                                      __HIP_MEMORY_SCOPE_WORKGROUP);
+#pragma unroll
+                for (int sl = 0; sl < kGroup; ++sl) {
+                    const uint32_t lw = S.lk[sl];
+                    const bool has_succ = gb + sl < ez && (lw >> 31);
+                    const int ws = has_succ ? (int)(lw & 0xFFFFu) : dummy;
+                    __hip_atomic_store(&mb_seq[ws], (int)((lw >> 16) & 0x3FFFu) + 1, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_WORKGROUP);
+                }
+            }
+        };
+
+        Stage<FP, KP> SA, SB;
+        uint32_t pkA, lkA, pkB, lkB;
+        if (ez - ea <= kGroup) {
+            words(pkA, lkA, ea);
+            stage(SA, pkA, lkA, ea);
+            compute(SA, ea);
+        } else {
+            // inputs of group g+1 in flight while group g computes
+            words(pkA, lkA, ea);
+            words(pkB, lkB, ea + kGroup);
+            stage(SA, pkA, lkA, ea);
+            words(pkA, lkA, ea + 2 * kGroup);
+            for (int64_t gb = ea;; gb += 2 * kGroup) {
+                stage(SB, pkB, lkB, gb + kGroup);
+                words(pkB, lkB, gb + 3 * kGroup);
+                compute(SA, gb);
+                if (gb + kGroup >= ez) break;
+                stage(SA, pkA, lkA, gb + 2 * kGroup);
+                words(pkA, lkA, gb + 4 * kGroup);
+                compute(SB, gb + kGroup);
+                if (gb + 2 * kGroup >= ez) break;
             }
         }
+        __builtin_amdgcn_s_setprio(0);
 #pragma unroll
         for (int x = 0; x < FP; ++x) {
             const int f = lane + x * kWave;
@@ -189,38 +306,44 @@ __global__ __launch_bounds__(kSgdWaves* kWave) void k_sgd_stratum(SgdArgs a)
 }
 
 template <int FP, int KP>
-static int launch_sgd(const SgdArgs& args, hipStream_t s)
+static int launch_sgd(const SgdArgs& args, const uint32_t* pk, const uint32_t* link, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_sgd_stratum<FP, KP>), dim3((unsigned)args.P), dim3(kSgdWaves * kWave), 0, s, args);
+    const size_t lds = (size_t)(args.slots + 1) * (args.F + 2) * sizeof(float);
+    if (lds > 64 * 1024) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sgd_stratum<FP, KP>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return hip_fail(e, "hipFuncSetAttribute(k_sgd_stratum)");
+    }
+    hipLaunchKernelGGL((k_sgd_stratum<FP, KP>), dim3((unsigned)args.P), dim3(kSgdWaves * kWave), lds, s, args, pk,
+                       link);
     LSHMF_LAUNCHED("k_sgd_stratum");
     return LSHMF_OK;
 }
 
 template <int FP>
-static int launch_sgd_k(const SgdArgs& args, hipStream_t s)
+static int launch_sgd_k(const SgdArgs& args, const uint32_t* pk, const uint32_t* link, hipStream_t s)
 {
-    return args.K <= kWave ? launch_sgd<FP, 1>(args, s) : launch_sgd<FP, 2>(args, s);
+    return args.K <= kWave ? launch_sgd<FP, 1>(args, pk, link, s) : launch_sgd<FP, 2>(args, pk, link, s);
 }
 
 int run_sgd_epoch(lshmf_ctx* c, const lshmf_hparams* hp, int epoch, hipStream_t s)
 {
     const lshmf_dims& d = c->d;
-    if (c->max_block_nnz > kMaxBlockNnz) {
-        set_error("sgd_epoch: a block holds %lld ratings, more than %d; raise n_strata",
-                  (long long)c->max_block_nnz, kMaxBlockNnz);
+    const size_t lds = (size_t)(c->max_block_slots + 1) * (d.F + 2) * sizeof(float);
+    if (c->max_block_slots > kMaxSlots || lds > (size_t)kMaxMailboxBytes || c->max_block_nnz > kMaxChainPos) {
+        set_error("sgd_epoch: a block needs %lld mailbox slots (%zu bytes of LDS, limit %d) or holds %lld "
+                  "ratings (limit %d); raise n_strata",
+                  (long long)c->max_block_slots, lds, kMaxMailboxBytes, (long long)c->max_block_nnz, kMaxChainPos);
         return LSHMF_ECAPACITY;
     }
     SgdArgs a;
-    a.pk = c->pk;
-    a.dep = c->dep;
     a.nib = c->nib;
     a.blk_ptr = c->blk_ptr;
     a.blk_seg = c->blk_seg;
     a.seg_col = c->seg_col;
     a.seg_start = c->seg_start;
-    a.JK = c->t.JK;
+    a.nbr_b0 = c->nbr_b0;
     a.b0 = c->t.b0;
-    a.bh0 = c->t.bh0;
     a.mu = c->t.mu;
     a.U = c->t.U;
     a.V = c->t.V;
@@ -228,11 +351,13 @@ int run_sgd_epoch(lshmf_ctx* c, const lshmf_hparams* hp, int epoch, hipStream_t 
     a.bv = c->t.bv;
     a.W = c->t.W;
     a.C = c->t.C;
+    a.trash = c->trash;
     a.err = c->err;
     a.F = d.F;
     a.K = d.K;
     a.P = c->P;
     a.nstride = c->nstride;
+    a.slots = (int)c->max_block_slots;
     a.inv_s = 1.0f / (float)d.rscale;
     // Eq. (learn_rate): gamma_t = alpha / (1 + beta * t^1.5)
     const double den = 1.0 + (double)hp->beta * std::pow((double)epoch, 1.5);
@@ -244,10 +369,10 @@ int run_sgd_epoch(lshmf_ctx* c, const lshmf_hparams* hp, int epoch, hipStream_t 
     for (int st = 0; st < c->P; ++st) {
         a.s = st;
         switch (fp) {
-            case 1: LSHMF_TRY(launch_sgd_k<1>(a, s)); break;
-            case 2: LSHMF_TRY(launch_sgd_k<2>(a, s)); break;
-            case 3: LSHMF_TRY(launch_sgd_k<3>(a, s)); break;
-            default: LSHMF_TRY(launch_sgd_k<4>(a, s)); break;
+            case 1: LSHMF_TRY(launch_sgd_k<1>(a, c->pk, c->link, s)); break;
+            case 2: LSHMF_TRY(launch_sgd_k<2>(a, c->pk, c->link, s)); break;
+            case 3: LSHMF_TRY(launch_sgd_k<3>(a, c->pk, c->link, s)); break;
+            default: LSHMF_TRY(launch_sgd_k<4>(a, c->pk, c->link, s)); break;
         }
     }
     return LSHMF_OK;

@@ -15,7 +15,7 @@ from typing import Optional, Sequence
 import torch
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "liblshmf.so")
+LIB_PATH = os.environ.get("LSHMF_LIB") or os.path.join(HERE, "liblshmf.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "lshmf.h")
 
 LSHMF_OK = 0

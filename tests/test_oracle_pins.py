@@ -391,8 +391,11 @@ def test_schedule_blocks_are_conflict_free():
             items |= bi
             assert all(x % P == b for x in bu)
             assert all(x % P == (b + s) % P for x in bi)
-            jj = d["train_i"][sl].astype(np.int64) * w.M + d["train_u"][sl]
-            assert np.all(np.diff(jj) > 0)            # (j asc, i asc) inside a block
+            # inside a block: items by (degree desc, id asc), users ascending
+            deg = np.bincount(d["train_i"], minlength=w.N)
+            jj = d["train_i"][sl].astype(np.int64)
+            key = (-deg[jj]) * (1 << 40) + jj * (1 << 20) + d["train_u"][sl]
+            assert np.all(np.diff(key) > 0)
 
 
 def test_block_order_invariance_bit_exact():
