@@ -69,6 +69,8 @@ def main():
     ap.add_argument("--workload", default="ml10m")
     ap.add_argument("--epochs", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also run one plain 1 GiB device copy, the reference for HBM byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -113,6 +115,13 @@ def main():
         m.predict(g["test_u"], g["test_i"], out=pred)
         m.rmse(pred, g["test_rc"], out=rmse)
 
+    if args.calib_copy:
+        src = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        log("calibration copy: 1 GiB read + 1 GiB written")
     for _ in range(args.warmup):
         step(False)
     torch.cuda.synchronize()

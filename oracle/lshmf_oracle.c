@@ -66,13 +66,12 @@ static int hbit(const uint32_t* H, int words, int64_t i, int b)
     return (int)((H[i * words + b / 32] >> (b % 32)) & 1u);
 }
 
-int orc_simlsh(int M, int N, int B, int64_t nnz, const int32_t* u, const int32_t* it,
-               const uint8_t* rc, const uint32_t* H, int psi_exp,
-               int64_t* acc /* N*B */, uint32_t* sig /* N*ceil(B/32) */)
+/* acc[j][b] += Psi(r_ij) * Phi(H_i,b) over the given ratings (no reset). */
+int orc_simlsh_add(int M, int N, int B, int64_t nnz, const int32_t* u, const int32_t* it,
+                   const uint8_t* rc, const uint32_t* H, int psi_exp, int64_t* acc /* N*B */)
 {
     if (M <= 0 || N <= 0 || B <= 0 || nnz < 0) return ORC_EINVAL;
     const int words = (B + 31) / 32;
-    memset(acc, 0, sizeof(int64_t) * (size_t)N * B);
     for (int64_t e = 0; e < nnz; ++e) {
         const int i = u[e], j = it[e];
         if (i < 0 || i >= M || j < 0 || j >= N) return ORC_EINVAL;
@@ -80,11 +79,28 @@ int orc_simlsh(int M, int N, int B, int64_t nnz, const int32_t* u, const int32_t
         for (int b = 0; b < B; ++b)
             acc[(int64_t)j * B + b] += w * (2 * hbit(H, words, i, b) - 1);
     }
+    return ORC_OK;
+}
+
+/* Upsilon: signature bit b of item j is 1 iff acc[j][b] >= 0. */
+void orc_signs(int N, int B, const int64_t* acc, uint32_t* sig)
+{
+    const int words = (B + 31) / 32;
     memset(sig, 0, sizeof(uint32_t) * (size_t)N * words);
     for (int j = 0; j < N; ++j)
         for (int b = 0; b < B; ++b)
             if (acc[(int64_t)j * B + b] >= 0)
                 sig[(int64_t)j * words + b / 32] |= 1u << (b % 32);
+}
+
+int orc_simlsh(int M, int N, int B, int64_t nnz, const int32_t* u, const int32_t* it,
+               const uint8_t* rc, const uint32_t* H, int psi_exp,
+               int64_t* acc /* N*B */, uint32_t* sig /* N*ceil(B/32) */)
+{
+    memset(acc, 0, sizeof(int64_t) * (size_t)(N > 0 ? N : 0) * (B > 0 ? B : 0));
+    const int st = orc_simlsh_add(M, N, B, nnz, u, it, rc, H, psi_exp, acc);
+    if (st != ORC_OK) return st;
+    orc_signs(N, B, acc, sig);
     return ORC_OK;
 }
 

@@ -64,6 +64,9 @@ def lib():
             L.orc_splitmix64.restype = u64
             L.orc_splitmix64.argtypes = [u64, u64]
             L.orc_simlsh.argtypes = [i32, i32, i32, i64, vp, vp, vp, vp, i32, vp, vp]
+            L.orc_simlsh_add.argtypes = [i32, i32, i32, i64, vp, vp, vp, vp, i32, vp]
+            L.orc_signs.argtypes = [i32, i32, vp, vp]
+            L.orc_signs.restype = None
             L.orc_band_key.restype = u64
             L.orc_band_key.argtypes = [vp, i32, i32, i32]
             L.orc_band_keys.argtypes = [i32, i32, i32, i32, i32, vp, vp]
@@ -114,6 +117,28 @@ def simlsh(M: int, N: int, B: int, u, it, rc, H, psi_exp: int = 2):
     _chk(lib().orc_simlsh(M, N, B, u.size, _p(u), _p(it), _p(rc), _p(H), psi_exp,
                           _p(acc), _p(sig)), "simlsh")
     return acc, sig
+
+
+def simlsh_add(acc, B: int, u, it, rc, H, psi_exp: int = 2):
+    """acc += Psi(r)(2H - 1) over the given ratings (the online update of the
+    saved pre-sign sums, Sec. 4.3)."""
+    u = np.ascontiguousarray(u, np.int32)
+    it = np.ascontiguousarray(it, np.int32)
+    rc = np.ascontiguousarray(rc, np.uint8)
+    H = np.ascontiguousarray(H, np.uint32)
+    assert acc.dtype == np.int64 and acc.flags.c_contiguous
+    N = acc.shape[0]
+    _chk(lib().orc_simlsh_add(H.shape[0], N, B, u.size, _p(u), _p(it), _p(rc), _p(H), psi_exp,
+                              _p(acc)), "simlsh_add")
+    return acc
+
+
+def signs(acc, B: int) -> np.ndarray:
+    acc = np.ascontiguousarray(acc, np.int64)
+    N = acc.shape[0]
+    sig = np.zeros((N, (B + 31) // 32), np.uint32)
+    lib().orc_signs(N, B, _p(acc), _p(sig))
+    return sig
 
 
 def band_keys(sig, B: int, G: int, p: int, q: int) -> np.ndarray:
@@ -201,12 +226,18 @@ class Model:
     """FP64 LSH-MF model state driven by the oracle's SGD (Alg. CULSH-MF)."""
 
     def __init__(self, M: int, N: int, F: int, K: int, rscale: int, train_u, train_i, train_rc,
-                 JK, U0, V0, W0=None, C0=None, bu0=None, bv0=None):
+                 JK, U0, V0, W0=None, C0=None, bu0=None, bv0=None, fixed_baselines=None):
         self.M, self.N, self.F, self.K, self.rscale = M, N, F, K, rscale
         self.u = np.ascontiguousarray(train_u, np.int32)
         self.i = np.ascontiguousarray(train_i, np.int32)
         self.rc = np.ascontiguousarray(train_rc, np.uint8)
-        self.mu, self.b0, self.bh0 = baselines(M, N, self.u, self.i, self.rc, rscale)
+        if fixed_baselines is None:
+            self.mu, self.b0, self.bh0 = baselines(M, N, self.u, self.i, self.rc, rscale)
+        else:
+            mu, b0, bh0 = fixed_baselines
+            self.mu = float(mu)
+            self.b0 = np.ascontiguousarray(b0, np.float64).copy()
+            self.bh0 = np.ascontiguousarray(bh0, np.float64).copy()
         self.R = Csr(M, self.u, self.i, self.rc)
         self.JK = np.ascontiguousarray(JK, np.int32).reshape(N, K) if K else np.zeros((N, 1), np.int32)
         self.U = np.array(U0, np.float64).reshape(M, F).copy()
@@ -235,17 +266,32 @@ class Model:
 
     def sgd_epoch(self, P: int, alpha, lam, beta: float, t: int, reverse_blocks: bool = False,
                   upd: int = 3):
+        """One pass over the model's own ratings in the stratified order."""
         if P not in self._sched:
             self._sched[P] = schedule(P, self.u, self.i)
-        order, blk = self._sched[P]
+        self._pass(self.u, self.i, self.rc, self._sched[P], P, alpha, lam, beta, t,
+                   reverse_blocks, upd)
+
+    def sgd_pass(self, u, it, rc, P: int, alpha, lam, beta: float, t: int, upd: int = 3):
+        """One pass over a given subset of ratings, in the stratified order of
+        that subset; R(i) is the model's full rating set."""
+        u = np.ascontiguousarray(u, np.int32)
+        it = np.ascontiguousarray(it, np.int32)
+        rc = np.ascontiguousarray(rc, np.uint8)
+        if u.size == 0:
+            return
+        self._pass(u, it, rc, schedule(P, u, it), P, alpha, lam, beta, t, False, upd)
+
+    def _pass(self, u, it, rc, sched, P, alpha, lam, beta, t, reverse_blocks, upd):
+        order, blk = sched
         r = _Rates()
         a = np.ascontiguousarray(alpha, np.float64)
         l = np.ascontiguousarray(lam, np.float64)
         lib().orc_rates_for_epoch(_p(a), _p(l), beta, t, C.byref(r))
         m = self._c()
-        _chk(lib().orc_sgd_epoch(C.byref(m), C.byref(self.R.c), self.u.size, _p(self.u),
-                                 _p(self.i), _p(self.rc), _p(order), _p(blk), P, C.byref(r),
-                                 int(reverse_blocks), upd), "sgd_epoch")
+        _chk(lib().orc_sgd_epoch(C.byref(m), C.byref(self.R.c), u.size, _p(u), _p(it), _p(rc),
+                                 _p(order), _p(blk), P, C.byref(r), int(reverse_blocks), upd),
+             "sgd_epoch")
 
     def sgd_one(self, i: int, j: int, code: int, g, lam, upd: int = 3):
         """One update (Eq. sgd_update) with explicit rates g and regularisers lam."""
@@ -264,6 +310,83 @@ class Model:
 
     def rmse(self, qu, qi, rc) -> float:
         return rmse(self.predict(qu, qi), rc, self.rscale)
+
+
+def online_update(m: "Model", acc, sig, B: int, G: int, p: int, q: int, seed_fill: int,
+                  new_u, new_i, new_rc, H, U0_new, V0_new, P: int, alpha, lam, beta: float,
+                  t: int, passes: int = 1, psi_exp: int = 2):
+    """Online learning, Sec. 4.3 and Alg. "Online Learning".
+
+    The batch may bring new users (ids >= m.M) and new items (ids >= m.N).
+      1. the saved pre-sign sums of the items the batch touches are increased
+         by the batch's terms (new items start from zero) and signs recomputed;
+      2. existing items keep their neighbour lists; every new item gets its
+         top-K over all items from the updated signatures;
+      3. mu stays; a new user's / item's fixed baseline is the mean of its
+         batch ratings minus mu; existing baselines stay;
+      4. `passes` times: (A) ratings of new users on existing items update only
+         b_i, u_i; (B) ratings of new items update only bh_j, v_j, w_j, c_j;
+         (C) the remaining ratings update both sides.  Each phase runs in the
+         stratified order of its own ratings; R(i) includes the batch.
+    Returns (new Model, acc, sig).
+    """
+    new_u = np.ascontiguousarray(new_u, np.int32)
+    new_i = np.ascontiguousarray(new_i, np.int32)
+    new_rc = np.ascontiguousarray(new_rc, np.uint8)
+    M2 = max(m.M, int(new_u.max()) + 1 if new_u.size else 0)
+    N2 = max(m.N, int(new_i.max()) + 1 if new_i.size else 0)
+    # 1. sums and signs
+    acc2 = np.zeros((N2, B), np.int64)
+    acc2[: m.N] = acc
+    simlsh_add(acc2, B, new_u, new_i, new_rc, H, psi_exp)
+    sig2 = signs(acc2, B)
+    # 2. neighbour lists
+    K = m.K
+    JK2 = np.zeros((N2, K), np.int32)
+    JK2[: m.N] = m.JK
+    if N2 > m.N:
+        JK2[m.N:] = topk(sig2, B, G, p, q, K, seed_fill, items=np.arange(m.N, N2, dtype=np.int32))
+    # 3. baselines
+    b02 = np.zeros(M2)
+    b02[: m.M] = m.b0
+    bh02 = np.zeros(N2)
+    bh02[: m.N] = m.bh0
+    for ids, vals, out, base in ((new_u, new_rc, b02, m.M), (new_i, new_rc, bh02, m.N)):
+        sel = ids >= base
+        if sel.any():
+            cnt = np.bincount(ids[sel], minlength=out.size)
+            tot = np.bincount(ids[sel], weights=vals[sel].astype(np.float64) / m.rscale,
+                              minlength=out.size)
+            nz = cnt > 0
+            out[nz] = tot[nz] / cnt[nz] - m.mu
+    # the grown model
+    U2 = np.zeros((M2, m.F))
+    U2[: m.M] = m.U
+    U2[m.M:] = np.asarray(U0_new, np.float64).reshape(M2 - m.M, m.F)
+    V2 = np.zeros((N2, m.F))
+    V2[: m.N] = m.V
+    V2[m.N:] = np.asarray(V0_new, np.float64).reshape(N2 - m.N, m.F)
+    W2 = np.zeros((N2, max(K, 1)))
+    W2[: m.N] = m.W
+    C2 = np.zeros((N2, max(K, 1)))
+    C2[: m.N] = m.C
+    bu2 = np.zeros(M2)
+    bu2[: m.M] = m.bu
+    bv2 = np.zeros(N2)
+    bv2[: m.N] = m.bv
+    u_all = np.concatenate([m.u, new_u])
+    i_all = np.concatenate([m.i, new_i])
+    rc_all = np.concatenate([m.rc, new_rc])
+    m2 = Model(M2, N2, m.F, K, m.rscale, u_all, i_all, rc_all, JK2, U2, V2, W2, C2, bu2, bv2,
+               fixed_baselines=(m.mu, b02, bh02))
+    # 4. frozen-side passes over the batch
+    phaseA = (new_u >= m.M) & (new_i < m.N)
+    phaseB = new_i >= m.N
+    phaseC = ~(phaseA | phaseB)
+    for _ in range(passes):
+        for sel, upd in ((phaseA, 1), (phaseB, 2), (phaseC, 3)):
+            m2.sgd_pass(new_u[sel], new_i[sel], new_rc[sel], P, alpha, lam, beta, t, upd)
+    return m2, acc2, sig2
 
 
 # --------------------------------------------------------------------------

@@ -51,7 +51,7 @@ size_t carve(lshmf_ctx* c, char* base)
     c->seg_col = k.take<int32_t>(nnz);
     c->blk_slots = k.take<int32_t>(P * P);
     c->irank = k.take<int32_t>(d.N);
-    c->trash = k.take<float>(512);
+    c->trash = k.take<float>(1024);
     c->seg_start = k.take<int64_t>(nnz + 1);
     c->csr_spos = k.take<int32_t>(nnz);
     int64_t cn = nnz;

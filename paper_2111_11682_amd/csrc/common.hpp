@@ -96,7 +96,7 @@ struct lshmf_ctx {
     int32_t* seg_col;    // nnz   item of each segment (a run of one item inside a block)
     int32_t* blk_slots;  // P*P   mailbox slots (users with several ratings) per block
     int32_t* irank;      // N     item order inside blocks: degree desc, id asc
-    float* trash;        // 512   sink for the stores of read-ahead slots past a segment
+    float* trash;        // 1024  sink for loads/stores that must not touch a table
     int64_t* seg_start;  // nnz+1
     int32_t* csr_spos;   // nnz   stream position of each CSR rating
     int64_t* cnt;        // max(M,N,P*P,nnz)+1 counters / flags

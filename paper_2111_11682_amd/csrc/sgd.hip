@@ -161,11 +161,14 @@ __global__ __launch_bounds__(kSgdWaves* kWave) void k_sgd_stratum(SgdArgs a, con
                 const int64_t i = pw >> 4;
                 const float* urow = has_pred ? a.trash : a.U + i * F;
                 const int rs = has_pred ? slot : dummy;
+                // lanes past F read the sink row: every load is issued by all lanes
 #pragma unroll
                 for (int x = 0; x < FP; ++x) {
                     const int f = lane + x * kWave;
-                    S.gu[sl][x] = f < F ? urow[f] : 0.0f;
-                    S.mu[sl][x] = f < F ? mb_u[rs * F + f] : 0.0f;
+                    const float gv = *(f < F ? urow + f : a.trash + lane);
+                    const float mv = mb_u[(f < F ? rs * F + f : dummy * F)];
+                    S.gu[sl][x] = f < F ? gv : 0.0f;   // lanes past F keep u = 0 (and so v = 0)
+                    S.mu[sl][x] = f < F ? mv : 0.0f;
                 }
                 S.gbi[sl] = has_pred ? a.trash[F] : a.bu[i];
                 S.mbi[sl] = mb_b[rs];
@@ -174,7 +177,7 @@ __global__ __launch_bounds__(kSgdWaves* kWave) void k_sgd_stratum(SgdArgs a, con
 #pragma unroll
                 for (int y = 0; y < KP; ++y) {
                     const int byte = (lane >> 1) + y * (kWave / 2);
-                    S.nb[sl][y] = byte < a.nstride ? nbp[byte] : 0u;
+                    S.nb[sl][y] = nbp[byte < a.nstride ? byte : 0];
                 }
             }
         };
@@ -212,42 +215,39 @@ __global__ __launch_bounds__(kSgdWaves* kWave) void k_sgd_stratum(SgdArgs a, con
 #pragma unroll
                 for (int x = 0; x < FP; ++x) part += u[x] * v[x];
 #pragma unroll
-                for (int y = 0; y < KP; ++y)
-                    if (lane + y * kWave < K) part += code[y] ? resid[y] * w[y] * sR : c[y] * sN;
+                for (int y = 0; y < KP; ++y) {
+                    const float t = code[y] ? resid[y] * w[y] * sR : c[y] * sN;
+                    part += lane + y * kWave < K ? t : 0.0f;
+                }
                 const float err = r - (mu + bi + bh + wave_sum(part));
                 // all right-hand sides from the pre-step state.  The last rating
-                // of a user in the block writes HBM; earlier ones only the mailbox.
-                // Slots past the segment end write to sinks.
+                // of a user in the block writes HBM; earlier ones only the
+                // mailbox.  Stores that must not happen go to sinks instead, so
+                // every lane issues the same stores without branches.
                 const bool to_hbm = valid && !has_succ;
-                float* bu_dst = to_hbm ? a.bu + i : a.trash + F;
-                float* u_dst = to_hbm ? a.U + i * F : a.trash;
                 const int ws = has_succ ? slot : dummy;
                 const float bnew = bi + a.g[0] * (err - a.l[0] * bi);
-                if (lane == 0) {
-                    *bu_dst = bnew;
-                    mb_b[ws] = bnew;
-                }
+                float* bsink = a.trash + 2 * kWave * FP;
+                *((lane == 0 && to_hbm) ? a.bu + i : bsink + lane) = bnew;
+                mb_b[lane == 0 ? ws : dummy] = bnew;
                 const float bh_new = bh + a.g[1] * (err - a.l[1] * bh);
                 bh = valid ? bh_new : bh;
 #pragma unroll
                 for (int x = 0; x < FP; ++x) {
                     const int f = lane + x * kWave;
                     const float unew = u[x] + a.g[2] * (err * v[x] - a.l[2] * u[x]);
-                    if (f < F) {
-                        u_dst[f] = unew;
-                        mb_u[ws * F + f] = unew;
-                    }
+                    *((to_hbm && f < F) ? a.U + i * F + f : a.trash + kWave * FP + f) = unew;
+                    mb_u[f < F ? ws * F + f : dummy * F] = unew;
                     const float vn = v[x] + a.g[3] * (err * u[x] - a.l[3] * v[x]);
                     v[x] = valid ? vn : v[x];
                 }
 #pragma unroll
                 for (int y = 0; y < KP; ++y) {
-                    if (lane + y * kWave < K) {
-                        const float wn = w[y] + a.g[4] * (sR * err * resid[y] - a.l[4] * w[y]);
-                        const float cn = c[y] + a.g[5] * (sN * err - a.l[5] * c[y]);
-                        w[y] = (valid && code[y]) ? wn : w[y];
-                        c[y] = (valid && !code[y]) ? cn : c[y];
-                    }
+                    const bool in_k = lane + y * kWave < K;
+                    const float wn = w[y] + a.g[4] * (sR * err * resid[y] - a.l[4] * w[y]);
+                    const float cn = c[y] + a.g[5] * (sN * err - a.l[5] * c[y]);
+                    w[y] = (valid && in_k && code[y]) ? wn : w[y];
+                    c[y] = (valid && in_k && !code[y]) ? cn : c[y];
                 }
             }
             // the mailbox rows are written: publish their sequence numbers

@@ -283,6 +283,35 @@ def generate(w: Workload, seed: int = MASTER_SEED, with_tables: bool = True) -> 
     return out
 
 
+def online_split(w: Workload, d: Dict[str, np.ndarray], frac_new: float = 0.01,
+                 stream_frac: float = 0.2, seed: int = MASTER_SEED) -> Dict[str, np.ndarray]:
+    """Pre-train / stream split of the training ratings for online learning.
+
+    The users with the top `frac_new` of ids and the items with the top
+    `frac_new` of ids are "new": all their ratings go to the stream.  Random
+    existing x existing ratings fill the stream up to `stream_frac` of the
+    ratings.  Ids are random permutations of popularity, so the new sets are
+    random samples.  Returns pretrain_{u,i,rc}, stream_{u,i,rc} (stream in a
+    random order), M_old, N_old.
+    """
+    rng = _rng(seed, 21)
+    M_old = w.M - max(1, int(round(frac_new * w.M)))
+    N_old = w.N - max(1, int(round(frac_new * w.N)))
+    u, i, rc = d["train_u"], d["train_i"], d["train_rc"]
+    new = (u >= M_old) | (i >= N_old)
+    old_idx = np.nonzero(~new)[0]
+    n_fill = max(0, int(round(stream_frac * u.size)) - int(new.sum()))
+    fill = rng.choice(old_idx, size=min(n_fill, old_idx.size), replace=False)
+    in_stream = new.copy()
+    in_stream[fill] = True
+    s_idx = np.nonzero(in_stream)[0]
+    s_idx = s_idx[rng.permutation(s_idx.size)]
+    p_idx = np.nonzero(~in_stream)[0]
+    return {"pretrain_u": u[p_idx], "pretrain_i": i[p_idx], "pretrain_rc": rc[p_idx],
+            "stream_u": u[s_idx], "stream_i": i[s_idx], "stream_rc": rc[s_idx],
+            "M_old": np.int64(M_old), "N_old": np.int64(N_old)}
+
+
 def random_queries(M: int, N: int, n: int, seed: int) -> Tuple[np.ndarray, np.ndarray]:
     """Uniform (user, item) query pairs for predict."""
     rng = _rng(seed, 11)

@@ -437,3 +437,92 @@ def test_lsh_neighbours_not_worse_than_random():
             m.sgd_epoch(w.n_strata, w.alpha, w.lam, w.beta, t)
         res[name] = m.rmse(d["test_u"], d["test_i"], d["test_rc"])
     assert res["lsh"] <= res["rand"] + 1e-3, res
+
+
+# --------------------------------------------------------------------------
+# Online learning, Sec. 4.3 / Alg. "Online Learning"
+# --------------------------------------------------------------------------
+def _online_setup(name="small", batch_frac=0.5):
+    w = synth.WORKLOADS[name]
+    d = synth.generate(w)
+    sp = synth.online_split(w, d, frac_new=0.05, stream_frac=0.2)
+    M0, N0 = int(sp["M_old"]), int(sp["N_old"])
+    pu, pi, prc = sp["pretrain_u"], sp["pretrain_i"], sp["pretrain_rc"]
+    H0 = d["H"][:M0]
+    acc, sig = orc.simlsh(M0, N0, w.B, pu, pi, prc, H0)
+    JK = orc.topk(sig, w.B, w.G, w.p, w.q, w.K, 9)
+    m = orc.Model(M0, N0, w.F, w.K, w.rscale, pu, pi, prc, JK, d["U0"][:M0], d["V0"][:N0])
+    m.sgd_epoch(w.n_strata, w.alpha, w.lam, w.beta, 0)
+    n = int(batch_frac * sp["stream_u"].size)
+    batch = (sp["stream_u"][:n], sp["stream_i"][:n], sp["stream_rc"][:n])
+    return w, d, sp, m, acc, sig, batch
+
+
+def test_online_sums_equal_full_recompute():
+    w, d, sp, m, acc, sig, (bu_, bi_, brc) = _online_setup()
+    m2, acc2, sig2 = orc.online_update(m, acc, sig, w.B, w.G, w.p, w.q, 9, bu_, bi_, brc, d["H"],
+                                       d["U0"][m.M:], d["V0"][m.N:], w.n_strata, w.alpha, w.lam,
+                                       w.beta, 1)
+    u_all = np.concatenate([m.u, bu_])
+    i_all = np.concatenate([m.i, bi_])
+    rc_all = np.concatenate([m.rc, brc])
+    full_acc, full_sig = orc.simlsh(m2.M, m2.N, w.B, u_all, i_all, rc_all, d["H"][: m2.M])
+    assert np.array_equal(acc2, full_acc)
+    assert np.array_equal(sig2, full_sig)
+    # existing items keep their lists; new items search all items
+    assert np.array_equal(m2.JK[: m.N], m.JK)
+    new_items = np.arange(m.N, m2.N, dtype=np.int32)
+    assert np.array_equal(m2.JK[m.N:], orc.topk(full_sig, w.B, w.G, w.p, w.q, w.K, 9, items=new_items))
+
+
+def test_online_phases_freeze_sides():
+    w, d, sp, m, acc, sig, (bu_, bi_, brc) = _online_setup()
+    # phase A only: new users on existing items -> item side untouched
+    a = (bu_ >= m.M) & (bi_ < m.N)
+    m2, _, _ = orc.online_update(m, acc, sig, w.B, w.G, w.p, w.q, 9, bu_[a], bi_[a], brc[a], d["H"],
+                                 d["U0"][m.M:m.M + 0] if False else d["U0"][m.M:int(bu_[a].max()) + 1],
+                                 d["V0"][m.N:m.N], w.n_strata, w.alpha, w.lam, w.beta, 1)
+    assert m2.N == m.N
+    for k in ("V", "bv", "W", "C"):
+        assert np.array_equal(getattr(m2, k), getattr(m, k)), k
+    assert np.array_equal(m2.U[: m.M], m.U) and np.array_equal(m2.bu[: m.M], m.bu)
+    touched = np.unique(bu_[a])
+    assert not np.array_equal(m2.U[touched], np.asarray(d["U0"][touched], np.float64))
+    # phase B only: ratings of new items -> user side untouched
+    b = bi_ >= m.N
+    M2 = max(m.M, int(bu_[b].max()) + 1)
+    m3, _, _ = orc.online_update(m, acc, sig, w.B, w.G, w.p, w.q, 9, bu_[b], bi_[b], brc[b], d["H"],
+                                 d["U0"][m.M:M2], d["V0"][m.N:int(bi_[b].max()) + 1], w.n_strata,
+                                 w.alpha, w.lam, w.beta, 1)
+    assert np.array_equal(m3.U[: m.M], m.U) and np.array_equal(m3.bu[: m.M], m.bu)
+    assert np.array_equal(m3.U[m.M:], np.asarray(d["U0"][m.M:M2], np.float64))
+    for k in ("V", "bv", "W", "C"):
+        assert np.array_equal(getattr(m3, k)[: m.N], getattr(m, k)), k
+
+
+def test_online_empty_batch_is_identity():
+    w, d, sp, m, acc, sig, _ = _online_setup()
+    e = np.zeros(0, np.int32)
+    m2, acc2, sig2 = orc.online_update(m, acc, sig, w.B, w.G, w.p, w.q, 9, e, e, e.astype(np.uint8),
+                                       d["H"], np.zeros((0, w.F)), np.zeros((0, w.F)), w.n_strata,
+                                       w.alpha, w.lam, w.beta, 1)
+    for k in ("U", "V", "bu", "bv", "W", "C", "JK"):
+        assert np.array_equal(getattr(m2, k), getattr(m, k)), k
+    assert np.array_equal(acc2, acc) and np.array_equal(sig2, sig)
+
+
+def test_online_learns_new_users():
+    # new users' held-back ratings are predicted better after the update
+    w, d, sp, m, acc, sig, _ = _online_setup(batch_frac=1.0)
+    su, si, src = sp["stream_u"], sp["stream_i"], sp["stream_rc"]
+    newu = (su >= m.M) & (si < m.N)
+    idx = np.nonzero(newu)[0]
+    test = idx[::4]
+    keep = np.ones(su.size, bool)
+    keep[test] = False
+    m2, _, _ = orc.online_update(m, acc, sig, w.B, w.G, w.p, w.q, 9, su[keep], si[keep], src[keep],
+                                 d["H"], d["U0"][m.M:], d["V0"][m.N:], w.n_strata, w.alpha, w.lam,
+                                 w.beta, 1, passes=3)
+    before = np.sqrt(np.mean((src[test] / w.rscale - m2.mu) ** 2))
+    after = m2.rmse(su[test], si[test], src[test])
+    assert after < before
