@@ -28,6 +28,9 @@
 extern "C" {
 #endif
 
+/* The library is built with hidden visibility; only these names are exported. */
+#pragma GCC visibility push(default)
+
 typedef struct ihipStream_t* lshmf_stream_t; /* hipStream_t; NULL = default stream */
 
 enum {
@@ -52,7 +55,12 @@ typedef struct lshmf_dims {
     int32_t n_strata;  /* P: users and items split into P blocks by id mod P */
     int32_t storage;   /* LSHMF_FP32 (BF16 reserved)                         */
     int32_t reserved;
-    int64_t nnz;       /* training ratings                                   */
+    int64_t nnz;       /* ratings of the initial training set                */
+    /* Capacities for online learning (0: the initial size; batch_cap 0: no
+     * online batches).  Tables and the arena are sized for them.            */
+    int32_t M_cap, N_cap;
+    int64_t nnz_cap;   /* ratings the store holds, training set + batches    */
+    int64_t batch_cap; /* most ratings one online_update call takes          */
 } lshmf_dims;
 
 /* Learning rates alpha and regularisers lambda, in the order
@@ -65,7 +73,8 @@ typedef struct lshmf_hparams {
     int32_t reserved;
 } lshmf_hparams;
 
-/* Model tables: caller-owned device buffers, FP32, row-major.
+/* Model tables: caller-owned device buffers, FP32, row-major, sized for the
+ * capacities M_cap and N_cap (M, N below):
  *   U  [M*F]   V  [N*F]          factor rows u_i, v_j              (Eq. rr, part 4)
  *   bu [M]     bv [N]            learned deviations b_i, bh_j       (Eq. rr, part 1)
  *   W  [N*K]   C  [N*K]          explicit / implicit influence w_j, c_j, slot k
@@ -106,7 +115,8 @@ int lshmf_arena_bytes(const lshmf_ctx* ctx, size_t* bytes);
 int lshmf_bind(lshmf_ctx* ctx, const lshmf_tables* tables, void* d_arena, size_t arena_bytes);
 
 /* Ingest and layout of the training ratings (COO, d_u[n], d_i[n], d_rc[n],
- * n = dims.nnz, each (u, i) pair at most once): CSR by user, CSC by item,
+ * n <= dims.nnz_cap, each (u, i) pair at most once; resets the model to
+ * dims.M x dims.N): CSR by user, CSC by item,
  * the stratified block stream and the fixed baselines mu, b0, bh0 (Sec. 3.2,
  * the "simple case" means, reduced in FP64).  Ids outside [0,M) x [0,N) give
  * LSHMF_EINVAL after a stream synchronisation. */
@@ -127,13 +137,38 @@ int build_lsh_neighbours(lshmf_ctx* ctx, const uint32_t* d_H, uint64_t seed_fill
 
 /* One SGD epoch t (0-based) over all training ratings in the stratified
  * order: stratum s = 0..P-1 runs the P blocks (b, (b+s) mod P) of users
- * i mod P = b and items j mod P = (b+s) mod P; inside a block, items
- * ascending and users ascending within an item.  Each rating applies Eq.
+ * i mod P = b and items j mod P = (b+s) mod P; inside a block, runs of one
+ * item by decreasing item degree (ties by smaller id), users ascending within
+ * a run.  Each rating applies Eq.
  * (sgd_update) with the prediction of Eq. (rr), N(i) the complement of R(i)
  * (the CULSH-MF adjustment), and the residual baseline of the w-term fixed to
  * the simple-case means.  Results do not depend on how blocks are scheduled.
  * Requires build_lsh_neighbours. */
 int sgd_epoch(lshmf_ctx* ctx, const lshmf_hparams* hp, int32_t epoch, lshmf_stream_t stream);
+
+/* Online learning (Sec. 4.3, Alg. "Online Learning") of a batch of n new
+ * ratings (d_u, d_i, d_rc as for lshmf_ingest, pairs not already in the
+ * store) that may bring new users [M, M_new) and new items [N, N_new):
+ *   - the saved pre-sign sums acc grow by the batch's terms (rows of new items
+ *     start at zero) and every signature is re-signed (Eq. item_hash);
+ *   - existing items keep JK; each new item gets its top-K from the band
+ *     collisions over all N_new items, exactly as build_lsh_neighbours;
+ *   - mu and the existing b0, bh0 stay; a new id's fixed baseline is the mean
+ *     of its batch ratings minus mu;
+ *   - `passes` rounds of three SGD phases at the rate of epoch `epoch`, each
+ *     phase over its own ratings in the stratified order of sgd_epoch: (A) new
+ *     users on existing items update only b_i, u_i; (B) ratings on new items
+ *     update only bh_j, v_j, w_j, c_j; (C) the rest update both sides; R(i)
+ *     includes the batch.
+ * The caller writes U rows [M, M_new) and V rows [N, N_new) before the call;
+ * the library zeroes bu, bv, W, C of the new ids.  d_H holds M_new rows.
+ * The batch joins the training set of later sgd_epoch calls.  Exceeding a
+ * capacity gives LSHMF_ECAPACITY, ids outside [0,M_new) x [0,N_new)
+ * LSHMF_EINVAL, both before any table is touched.  Requires
+ * build_lsh_neighbours. */
+int online_update(lshmf_ctx* ctx, const int32_t* d_u, const int32_t* d_i, const uint8_t* d_rc, int64_t n,
+                  int32_t M_new, int32_t N_new, const uint32_t* d_H, uint64_t seed_fill,
+                  const lshmf_hparams* hp, int32_t epoch, int32_t passes, lshmf_stream_t stream);
 
 /* Eq. (rr) for n query pairs (d_u[x], d_i[x]) -> d_out[x] (FP32), with R(i)
  * the user's training items.  Ids out of range give NaN for that query. */
@@ -150,7 +185,9 @@ int lshmf_rmse(lshmf_ctx* ctx, const float* d_pred, const uint8_t* d_rc, int64_t
  * of the same user in the block or -1, nib = K 4-bit neighbour codes per
  * rating, nstride bytes each), block and segment ranges, and the CSR / CSC
  * copies of the training set.  Valid after lshmf_ingest (nib after
- * build_lsh_neighbours) until the next lshmf_bind. */
+ * build_lsh_neighbours) until the next lshmf_bind; after online_update the
+ * stream describes the previous training set until the next sgd_epoch lays
+ * out the grown one. */
 typedef struct lshmf_layout {
     const uint32_t* pk;
     const int32_t* sj;
@@ -170,12 +207,16 @@ typedef struct lshmf_layout {
                                  an SGD dependency wait hit its spin limit */
     int32_t nstride;
     int32_t P;
+    int32_t M, N;             /* current users and items                     */
+    int64_t nnz;              /* ratings in the store                        */
 } lshmf_layout;
 
 int lshmf_export_layout(const lshmf_ctx* ctx, lshmf_layout* out);
 
 /* Thread-local message describing the last non-OK status. */
 const char* lshmf_last_error(void);
+
+#pragma GCC visibility pop
 
 #ifdef __cplusplus
 }

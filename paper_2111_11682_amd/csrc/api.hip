@@ -9,7 +9,13 @@ namespace lshmf {
 const char* last_error();
 int ingest(lshmf_ctx* c, const int32_t* u, const int32_t* it, const uint8_t* rc, int64_t n, hipStream_t s);
 int build_neighbours(lshmf_ctx* c, const uint32_t* H, uint64_t seed_fill, hipStream_t s);
-int run_sgd_epoch(lshmf_ctx* c, const lshmf_hparams* hp, int epoch, hipStream_t s);
+int build_stream(lshmf_ctx* c, Stream& st, const int32_t* u, const int32_t* it, const uint8_t* rc, int64_t n,
+                 hipStream_t s);
+int stream_codes(lshmf_ctx* c, Stream& st, hipStream_t s);
+int run_sgd(lshmf_ctx* c, Stream& st, const lshmf_hparams* hp, int epoch, int upd, hipStream_t s);
+int run_online(lshmf_ctx* c, const int32_t* u, const int32_t* it, const uint8_t* rc, int64_t n, int32_t M_new,
+               int32_t N_new, const uint32_t* H, uint64_t seed_fill, const lshmf_hparams* hp, int epoch,
+               int passes, hipStream_t s);
 int run_predict(lshmf_ctx* c, const int32_t* qu, const int32_t* qi, int64_t n, float* out, hipStream_t s);
 int run_rmse(lshmf_ctx* c, const float* pred, const uint8_t* rc, int64_t n, double* out, hipStream_t s);
 
@@ -28,39 +34,58 @@ struct Carver {
     }
 };
 
+void carve_stream(Carver& k, Stream& st, int64_t cap, int64_t P, int nstride)
+{
+    st.cap = cap;
+    st.pk = k.take<uint32_t>(cap + kStreamPad);
+    st.sj = k.take<int32_t>(cap);
+    st.dep = k.take<int32_t>(cap);
+    st.link = k.take<uint32_t>(cap + kStreamPad);
+    st.nib = k.take<uint8_t>((size_t)(cap + kStreamPad) * nstride);
+    st.blk_ptr = k.take<int64_t>(P * P + 1);
+    st.blk_seg = k.take<int64_t>(P * P + 1);
+    st.seg_col = k.take<int32_t>(cap);
+    st.seg_start = k.take<int64_t>(cap + 1);
+    st.blk_slots = k.take<int32_t>(P * P);
+}
+
+int64_t max3(int64_t a, int64_t b, int64_t c)
+{
+    const int64_t m = a > b ? a : b;
+    return m > c ? m : c;
+}
+
 // One walk over the arena, used both to size it (base == nullptr) and to
-// assign the regions.
+// assign the regions.  Everything is sized for the capacities in c->d.
 size_t carve(lshmf_ctx* c, char* base)
 {
     const lshmf_dims& d = c->d;
-    const int64_t nnz = d.nnz, P = c->P, nq = (int64_t)d.q * d.N;
+    const int64_t nz = d.nnz_cap, bc = d.batch_cap, Mc = d.M_cap, Nc = d.N_cap, P = c->P;
+    const int64_t nq = (int64_t)d.q * Nc;
     Carver k{base};
-    c->row_ptr = k.take<int64_t>(d.M + 1);
-    c->csr_col = k.take<int32_t>(nnz);
-    c->csr_rc = k.take<uint8_t>(nnz);
-    c->col_ptr = k.take<int64_t>(d.N + 1);
-    c->csc_row = k.take<int32_t>(nnz);
-    c->csc_rc = k.take<uint8_t>(nnz);
-    c->pk = k.take<uint32_t>(nnz + kStreamPad);
-    c->sj = k.take<int32_t>(nnz);
-    c->dep = k.take<int32_t>(nnz);
-    c->link = k.take<uint32_t>(nnz + kStreamPad);
-    c->nib = k.take<uint8_t>((size_t)(nnz + kStreamPad) * c->nstride);
-    c->blk_ptr = k.take<int64_t>(P * P + 1);
-    c->blk_seg = k.take<int64_t>(P * P + 1);
-    c->seg_col = k.take<int32_t>(nnz);
-    c->blk_slots = k.take<int32_t>(P * P);
-    c->irank = k.take<int32_t>(d.N);
+    c->coo_u = k.take<int32_t>(nz);
+    c->coo_i = k.take<int32_t>(nz);
+    c->coo_rc = k.take<uint8_t>(nz);
+    c->row_ptr = k.take<int64_t>(Mc + 1);
+    c->csr_col = k.take<int32_t>(nz);
+    c->csr_rc = k.take<uint8_t>(nz);
+    c->col_ptr = k.take<int64_t>(Nc + 1);
+    c->csc_row = k.take<int32_t>(nz);
+    c->csc_rc = k.take<uint8_t>(nz);
+    carve_stream(k, c->train, nz, P, c->nstride);
+    for (Stream& st : c->phase) carve_stream(k, st, bc, P, c->nstride);
+    c->bat_u = k.take<int32_t>(bc);
+    c->bat_i = k.take<int32_t>(bc);
+    c->bat_rc = k.take<uint8_t>(bc);
+    c->bcol_ptr = k.take<int64_t>(Nc + 1);
+    c->bcsc_row = k.take<int32_t>(bc);
+    c->bcsc_rc = k.take<uint8_t>(bc);
+    c->irank = k.take<int32_t>(Nc);
+    c->e2s = k.take<int32_t>(nz > bc ? nz : bc);
     c->trash = k.take<float>(1024);
-    c->seg_start = k.take<int64_t>(nnz + 1);
-    c->csr_spos = k.take<int32_t>(nnz);
-    int64_t cn = nnz;
-    if (d.M > cn) cn = d.M;
-    if (d.N > cn) cn = d.N;
-    if (P * P > cn) cn = P * P;
-    if (nq > cn) cn = nq;
+    const int64_t cn = max3(max3(2 * Mc, 2 * Nc, P * P), max3(nz, nq, bc), 4);
     c->cnt = k.take<int64_t>(cn + 2);
-    c->sort_n = (nnz > nq ? nnz : nq) + 2;
+    c->sort_n = max3(nz, nq, bc > Nc ? bc : Nc) + 2;
     c->sk[0] = k.take<uint64_t>(c->sort_n);
     c->sk[1] = k.take<uint64_t>(c->sort_n);
     c->sv[0] = k.take<uint32_t>(c->sort_n);
@@ -72,7 +97,7 @@ size_t carve(lshmf_ctx* c, char* base)
     if (scan_n2 > scan_n) scan_n = scan_n2;
     c->scan_tmp = k.take<int64_t>(scan_n);
     c->red = k.take<double>(1024);
-    c->nbr_b0 = k.take<float>((size_t)d.N * d.K);
+    c->nbr_b0 = k.take<float>((size_t)Nc * d.K);
     c->bitem = k.take<int32_t>(nq);
     c->bbegin = k.take<int32_t>(nq + 1);
     c->bpos = k.take<int32_t>(nq);
@@ -112,7 +137,7 @@ int validate(const lshmf_dims* d)
         return LSHMF_EINVAL;
     }
     // |acc| <= M * 15^psi_exp must fit int32
-    double bound = (double)d->M;
+    double bound = (double)(d->M_cap > d->M ? d->M_cap : d->M);
     for (int e = 0; e < d->psi_exp; ++e) bound *= 15.0;
     if (bound >= 2147483647.0) {
         set_error("M * 15^psi_exp overflows the int32 hash sums");
@@ -128,6 +153,19 @@ int validate(const lshmf_dims* d)
     }
     if (d->nnz < 0 || d->nnz >= ((int64_t)1 << 31)) {
         set_error("nnz=%lld outside [0, 2^31)", (long long)d->nnz);
+        return LSHMF_EINVAL;
+    }
+    if (d->M_cap < 0 || d->N_cap < 0 || d->nnz_cap < 0 || d->batch_cap < 0) {
+        set_error("negative capacity");
+        return LSHMF_EINVAL;
+    }
+    if (d->M_cap >= (1 << 28) || d->nnz_cap >= ((int64_t)1 << 31) || d->batch_cap >= ((int64_t)1 << 31)) {
+        set_error("capacities must stay below M_cap 2^28, nnz_cap and batch_cap 2^31");
+        return LSHMF_EINVAL;
+    }
+    if ((d->M_cap && d->M_cap < d->M) || (d->N_cap && d->N_cap < d->N) || (d->nnz_cap && d->nnz_cap < d->nnz)) {
+        set_error("a capacity is below its initial size (M_cap=%d M=%d N_cap=%d N=%d nnz_cap=%lld nnz=%lld)",
+                  d->M_cap, d->M, d->N_cap, d->N, (long long)d->nnz_cap, (long long)d->nnz);
         return LSHMF_EINVAL;
     }
     return LSHMF_OK;
@@ -154,6 +192,12 @@ int lshmf_create(const lshmf_dims* dims, lshmf_ctx** out)
         return LSHMF_EINVAL;
     }
     c->d = *dims;
+    if (c->d.M_cap == 0) c->d.M_cap = dims->M;
+    if (c->d.N_cap == 0) c->d.N_cap = dims->N;
+    if (c->d.nnz_cap == 0) c->d.nnz_cap = dims->nnz;
+    c->M = dims->M;
+    c->N = dims->N;
+    c->nnz = 0;
     c->B = dims->G * dims->p * dims->q;
     c->words = (c->B + 31) / 32;
     c->pG = dims->G * dims->p;
@@ -211,8 +255,8 @@ int lshmf_ingest(lshmf_ctx* ctx, const int32_t* d_u, const int32_t* d_i, const u
         set_error("context not bound");
         return LSHMF_ESTATE;
     }
-    if (n != ctx->d.nnz) {
-        set_error("ingest: n=%lld differs from dims.nnz=%lld", (long long)n, (long long)ctx->d.nnz);
+    if (n < 0 || n > ctx->d.nnz_cap) {
+        set_error("ingest: n=%lld outside [0, nnz_cap=%lld]", (long long)n, (long long)ctx->d.nnz_cap);
         return LSHMF_EINVAL;
     }
     if (n > 0 && (!d_u || !d_i || !d_rc)) {
@@ -220,6 +264,8 @@ int lshmf_ingest(lshmf_ctx* ctx, const int32_t* d_u, const int32_t* d_i, const u
         return LSHMF_EINVAL;
     }
     ctx->ingested = ctx->neighbours = false;
+    ctx->M = ctx->d.M;
+    ctx->N = ctx->d.N;
     LSHMF_TRY(ingest(ctx, d_u, d_i, d_rc, n, reinterpret_cast<hipStream_t>(stream)));
     ctx->ingested = true;
     return LSHMF_OK;
@@ -250,7 +296,39 @@ int sgd_epoch(lshmf_ctx* ctx, const lshmf_hparams* hp, int32_t epoch, lshmf_stre
         set_error("sgd_epoch: bad hyper-parameters or epoch");
         return LSHMF_EINVAL;
     }
-    return run_sgd_epoch(ctx, hp, epoch, reinterpret_cast<hipStream_t>(stream));
+    const hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    if (ctx->train_stale) {  // the store grew by online batches since the stream was laid out
+        LSHMF_TRY(build_stream(ctx, ctx->train, ctx->coo_u, ctx->coo_i, ctx->coo_rc, ctx->nnz, s));
+        ctx->train_stale = false;
+    }
+    if (!ctx->train.codes) LSHMF_TRY(stream_codes(ctx, ctx->train, s));
+    return run_sgd(ctx, ctx->train, hp, epoch, 3, s);
+}
+
+int online_update(lshmf_ctx* ctx, const int32_t* d_u, const int32_t* d_i, const uint8_t* d_rc, int64_t n,
+                  int32_t M_new, int32_t N_new, const uint32_t* d_H, uint64_t seed_fill, const lshmf_hparams* hp,
+                  int32_t epoch, int32_t passes, lshmf_stream_t stream)
+{
+    if (!ctx || !ctx->neighbours) {
+        set_error("online_update: neighbours not built");
+        return LSHMF_ESTATE;
+    }
+    if (!hp || epoch < 0 || passes < 0 || !d_H || n < 0 || (n > 0 && (!d_u || !d_i || !d_rc))) {
+        set_error("online_update: bad arguments");
+        return LSHMF_EINVAL;
+    }
+    if (M_new < ctx->M || N_new < ctx->N) {
+        set_error("online_update: M_new=%d, N_new=%d below the current %d x %d", M_new, N_new, ctx->M, ctx->N);
+        return LSHMF_EINVAL;
+    }
+    if (M_new > ctx->d.M_cap || N_new > ctx->d.N_cap || n > ctx->d.batch_cap || ctx->nnz + n > ctx->d.nnz_cap) {
+        set_error("online_update: %d x %d with %lld + %lld ratings exceeds the capacities %d x %d, batch %lld, "
+                  "store %lld", M_new, N_new, (long long)ctx->nnz, (long long)n, ctx->d.M_cap, ctx->d.N_cap,
+                  (long long)ctx->d.batch_cap, (long long)ctx->d.nnz_cap);
+        return LSHMF_ECAPACITY;
+    }
+    return run_online(ctx, d_u, d_i, d_rc, n, M_new, N_new, d_H, seed_fill, hp, epoch, passes,
+                      reinterpret_cast<hipStream_t>(stream));
 }
 
 int predict(lshmf_ctx* ctx, const int32_t* d_u, const int32_t* d_i, int64_t n, float* d_out,
@@ -287,14 +365,15 @@ int lshmf_export_layout(const lshmf_ctx* ctx, lshmf_layout* out)
         set_error("lshmf_export_layout: context not bound");
         return LSHMF_ESTATE;
     }
-    out->pk = ctx->pk;
-    out->sj = ctx->sj;
-    out->dep = ctx->dep;
-    out->nib = ctx->nib;
-    out->blk_ptr = ctx->blk_ptr;
-    out->blk_seg = ctx->blk_seg;
-    out->seg_col = ctx->seg_col;
-    out->seg_start = ctx->seg_start;
+    const Stream& st = ctx->train;
+    out->pk = st.pk;
+    out->sj = st.sj;
+    out->dep = st.dep;
+    out->nib = st.nib;
+    out->blk_ptr = st.blk_ptr;
+    out->blk_seg = st.blk_seg;
+    out->seg_col = st.seg_col;
+    out->seg_start = st.seg_start;
     out->row_ptr = ctx->row_ptr;
     out->csr_col = ctx->csr_col;
     out->csr_rc = ctx->csr_rc;
@@ -304,6 +383,9 @@ int lshmf_export_layout(const lshmf_ctx* ctx, lshmf_layout* out)
     out->err = ctx->err;
     out->nstride = ctx->nstride;
     out->P = ctx->P;
+    out->M = ctx->M;
+    out->N = ctx->N;
+    out->nnz = ctx->nnz;
     return LSHMF_OK;
 }
 

@@ -67,50 +67,83 @@ int fill_f32(float* p, int64_t n, float v, hipStream_t s);
 }  // namespace lshmf
 
 // ------------------------------------------------------------ the context
+namespace lshmf {
+
+// One stratified stream of ratings: the order an SGD pass visits them in.
+// Stratum s runs blocks (b, (b+s) mod P) of users i mod P = b and items
+// j mod P = (b+s) mod P; inside a block item runs go by decreasing degree
+// (within the stream's own ratings, ties by id), users ascending in a run.
+struct Stream {
+    int64_t cap = 0;           // ratings it can hold
+    uint32_t* pk;              // cap + kStreamPad  (user << 4) | code
+    int32_t* sj;               // cap               item
+    int32_t* dep;              // cap               previous rating of the user in the block (local) or -1
+    uint32_t* link;            // cap + kStreamPad  hand-over word (successor, predecessor, chain pos, slot)
+    uint8_t* nib;              // (cap + kStreamPad) * nstride   neighbour codes
+    int64_t* blk_ptr;          // P*P + 1
+    int64_t* blk_seg;          // P*P + 1
+    int32_t* seg_col;          // cap               item of each run
+    int64_t* seg_start;        // cap + 1
+    int32_t* blk_slots;        // P*P               mailbox slots per block
+    int64_t n = 0;             // host copies after a build
+    int64_t max_block_nnz = 0;
+    int64_t max_block_slots = 0;
+    int64_t nseg = 0;
+    bool codes = false;        // nib valid for the current neighbour lists
+};
+
+}  // namespace lshmf
+
 struct lshmf_ctx {
-    lshmf_dims d;
-    int B;         // hash bits G*p*q
-    int words;     // uint32 words per signature
-    int pG;        // band width in bits
-    int P;         // strata
-    int nstride;   // bytes of neighbour codes per rating (K nibbles, padded)
-    int64_t sort_n;  // capacity of the sort buffers
+    lshmf_dims d;              // as created; M_cap, N_cap, nnz_cap resolved
+    int32_t M, N;              // current users and items
+    int64_t nnz;               // current ratings in the store
+    int B;                     // hash bits G*p*q
+    int words;                 // uint32 words per signature
+    int pG;                    // band width in bits
+    int P;                     // strata
+    int nstride;               // bytes of neighbour codes per rating (K nibbles, padded)
+    int64_t sort_n;            // capacity of the sort buffers
 
     lshmf_tables t;
     bool bound = false, ingested = false, neighbours = false;
 
-    // arena regions (device)
-    int64_t* row_ptr;    // M+1   CSR by user
-    int32_t* csr_col;    // nnz   items, ascending per user
-    uint8_t* csr_rc;     // nnz
-    int64_t* col_ptr;    // N+1   CSC by item
-    int32_t* csc_row;    // nnz   users, ascending per item
-    uint8_t* csc_rc;     // nnz
-    uint32_t* pk;        // nnz   block stream: (i << 4) | rc
-    int32_t* sj;         // nnz   item of each stream rating
-    int32_t* dep;        // nnz   previous rating of the same user inside the block (local), -1
-    uint32_t* link;      // nnz   hand-over word of the SGD kernel (successor, predecessor, chain pos, slot)
-    uint8_t* nib;        // nnz*nstride  4-bit codes of r_{i, JK[j][k]} (0: not rated)
-    int64_t* blk_ptr;    // P*P+1 block b of stratum s = entry s*P + b
-    int64_t* blk_seg;    // P*P+1 first segment of each block
-    int32_t* seg_col;    // nnz   item of each segment (a run of one item inside a block)
-    int32_t* blk_slots;  // P*P   mailbox slots (users with several ratings) per block
-    int32_t* irank;      // N     item order inside blocks: degree desc, id asc
-    float* trash;        // 1024  sink for loads/stores that must not touch a table
-    int64_t* seg_start;  // nnz+1
-    int32_t* csr_spos;   // nnz   stream position of each CSR rating
-    int64_t* cnt;        // max(M,N,P*P,nnz)+1 counters / flags
-    uint64_t* sk[2];     // sort keys
-    uint32_t* sv[2];     // sort values
-    int64_t* hist;       // radix histogram
+    // rating store and its compressed copies (device)
+    int32_t* coo_u;            // nnz_cap
+    int32_t* coo_i;            // nnz_cap
+    uint8_t* coo_rc;           // nnz_cap
+    int64_t* row_ptr;          // M_cap+1   CSR by user
+    int32_t* csr_col;          // nnz_cap   items, ascending per user
+    uint8_t* csr_rc;           // nnz_cap
+    int64_t* col_ptr;          // N_cap+1   CSC by item
+    int32_t* csc_row;          // nnz_cap   users, ascending per item
+    uint8_t* csc_rc;           // nnz_cap
+
+    lshmf::Stream train;       // all ratings of the store
+    lshmf::Stream phase[3];    // online batch: new users / new items / the rest
+    bool train_stale = false;  // the store grew since `train` was built
+
+    // online batch scratch
+    int32_t* bat_u;            // batch_cap  batch ratings grouped by phase
+    int32_t* bat_i;
+    uint8_t* bat_rc;
+    int64_t* bcol_ptr;         // N_cap+1    CSC of the batch (hash sums)
+    int32_t* bcsc_row;         // batch_cap
+    uint8_t* bcsc_rc;
+
+    // shared scratch
+    int32_t* irank;            // N_cap   item order of the stream being built
+    int32_t* e2s;              // max(nnz_cap, batch_cap) rating -> stream position
+    int64_t* cnt;              // counters / flags
+    uint64_t* sk[2];           // sort keys
+    uint32_t* sv[2];           // sort values
+    int64_t* hist;             // radix histogram
     int64_t* scan_tmp;
-    double* red;         // FP64 reduction partials
-    float* nbr_b0;       // N*K   fixed baseline bh0 of each neighbour slot
-    int32_t* bitem;      // q*N  items sorted by (band, key)
-    int32_t* bbegin;     // q*N+1 bucket starts (by bucket id)
-    int32_t* bpos;       // q*N  bucket id of (band t, item j) at t*N + j
-    int32_t* err;        // device error flag
-    int64_t max_block_nnz;  // host copies after ingest
-    int64_t max_block_slots;
-    int64_t nseg;
+    double* red;               // FP64 reduction partials
+    float* trash;              // sink for loads/stores that must not touch a table
+    float* nbr_b0;             // N_cap*K fixed baseline bh0 of each neighbour slot
+    int32_t* bitem;            // q*N_cap  items sorted by (band, key)
+    int32_t* bbegin;           // q*N_cap+1 bucket starts (by bucket id)
+    int32_t* bpos;             // q*N_cap  bucket id of (band t, item j) at t*N + j
+    int32_t* err;              // device status word
 };

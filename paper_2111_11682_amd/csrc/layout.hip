@@ -1,12 +1,13 @@
-// Ingest and layout of the training ratings.
+// Ingest and layout of the ratings.
 //
-// From the COO triplets this builds, all on the device:
+// All on the device:
+//   * the rating store (COO), which online updates append to;
 //   * CSR by user (items ascending)   -- R(i) membership for Eq. (rr)
 //   * CSC by item (users ascending)   -- the per-item sums of Eq. (item_hash)
-//   * the stratified block stream     -- the SGD order (see sgd_epoch in lshmf.h)
-//     with per-block ranges, item segments and, for every rating, the
-//     previous rating of the same user inside its block (the only ordering
-//     constraint between the waves that share a block)
+//   * stratified streams              -- the SGD order (see sgd_epoch in lshmf.h)
+//     with per-block ranges, item runs and, for every rating, its place in
+//     the chain of the same user's ratings inside its block (the only
+//     ordering constraint between the waves that share a block);
 //   * mu, b0_i, bh0_j: the "simple case" means of Sec. 3.2, exact integer sums
 //     reduced and divided in FP64.
 #include "common.hpp"
@@ -55,14 +56,13 @@ __global__ void k_keys_stream(const int32_t* u, const int32_t* it, const int32_t
     }
 }
 
-// Items by (training degree desc, id asc): key = (nnz - deg) * 2^idbits + j.
-__global__ void k_keys_rank(const int64_t* col_ptr, int32_t N, int64_t nnz, int idbits, uint64_t* keys,
+// Items by (degree in the stream desc, id asc): key = (n - deg) * 2^idbits + j.
+__global__ void k_keys_rank(const int64_t* deg, int32_t N, int64_t n, int idbits, uint64_t* keys,
                             uint32_t* vals)
 {
     for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < N;
          j += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t deg = col_ptr[j + 1] - col_ptr[j];
-        keys[j] = ((uint64_t)(nnz - deg) << idbits) | (uint64_t)j;
+        keys[j] = ((uint64_t)(n - deg[j]) << idbits) | (uint64_t)j;
         vals[j] = (uint32_t)j;
     }
 }
@@ -195,16 +195,37 @@ __global__ void k_block_slots(const int64_t* blk_ptr, const int64_t* ex, int64_t
 
 // CSR / CSC payloads after their sorts.
 __global__ void k_gather_pair(const uint32_t* order, const int32_t* other, const uint8_t* rc,
-                              int64_t n, int32_t* out_idx, uint8_t* out_rc, const int32_t* e2s,
-                              int32_t* out_spos)
+                              int64_t n, int32_t* out_idx, uint8_t* out_rc)
 {
     for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < n;
          x += (int64_t)gridDim.x * blockDim.x) {
         const uint32_t e = order[x];
         out_idx[x] = other[e];
         out_rc[x] = rc[e];
-        if (out_spos) out_spos[x] = e2s[e];
     }
+}
+
+// Fixed baselines of users / items first seen in an online batch: the mean
+// of their batch ratings minus mu (existing ones keep theirs).
+__global__ void k_sum_by_id(const int32_t* id, const uint8_t* rc, int64_t n, int32_t first,
+                            unsigned long long* sum, unsigned long long* cnt)
+{
+    for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < n;
+         x += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t v = id[x];
+        if (v >= first) {
+            atomicAdd(&sum[v - first], (unsigned long long)rc[x]);
+            atomicAdd(&cnt[v - first], 1ull);
+        }
+    }
+}
+
+__global__ void k_new_means(const unsigned long long* sum, const unsigned long long* cnt, int32_t count,
+                            int rscale, const double* mu, float* out)
+{
+    for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < count;
+         x += (int64_t)gridDim.x * blockDim.x)
+        out[x] = cnt[x] ? (float)((double)sum[x] / ((double)rscale * (double)cnt[x]) - *mu) : 0.0f;
 }
 
 // ---------------------------------------------------------------- baselines
@@ -247,72 +268,101 @@ static unsigned grid_for(int64_t n, int threads = 256, int64_t cap = 16384)
     return (unsigned)(b > cap ? cap : b);
 }
 
-int ingest(lshmf_ctx* c, const int32_t* u, const int32_t* it, const uint8_t* rc, int64_t n,
-           hipStream_t s)
+int check_ids(lshmf_ctx* c, const int32_t* u, const int32_t* it, const uint8_t* rc, int64_t n, int32_t M,
+              int32_t N, hipStream_t s)
 {
-    const lshmf_dims& d = c->d;
-    const int64_t P = c->P;
-    const StratKey sk{P, ceil_div(d.M, P), d.N};
-    int ri = 0;
-
-    LSHMF_TRY(fill_i32(c->err, 2, 0, s));
-    hipLaunchKernelGGL(k_check_ids, dim3(grid_for(n)), dim3(256), 0, s, u, it, rc, n, d.M, d.N, c->err);
-    LSHMF_LAUNCHED("k_check_ids");
+    LSHMF_TRY(fill_i32(c->err, 1, 0, s));
+    if (n > 0) {
+        hipLaunchKernelGGL(k_check_ids, dim3(grid_for(n)), dim3(256), 0, s, u, it, rc, n, M, N, c->err);
+        LSHMF_LAUNCHED("k_check_ids");
+    }
     int32_t herr = 0;
     LSHMF_HIP(hipMemcpyAsync(&herr, c->err, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     LSHMF_HIP(hipStreamSynchronize(s));
     if (herr) {
-        set_error("ingest: a rating has a user outside [0,%d), an item outside [0,%d) or a code "
-                  "outside 1..15", d.M, d.N);
+        set_error("a rating has a user outside [0,%d), an item outside [0,%d) or a code outside 1..15", M, N);
         return LSHMF_EINVAL;
     }
+    return LSHMF_OK;
+}
 
-    // -- CSC by item (item degrees order the items inside a block)
-    hipLaunchKernelGGL(k_keys_pair, dim3(grid_for(n)), dim3(256), 0, s, it, u, n, (int64_t)d.M, c->sk[0], c->sv[0]);
-    LSHMF_LAUNCHED("k_keys_pair(csc)");
-    LSHMF_TRY(radix_sort(c->sk, c->sv, n, bits_for((uint64_t)d.M * (uint64_t)d.N), c->hist, c->scan_tmp, s, &ri));
-    hipLaunchKernelGGL(k_gather_pair, dim3(grid_for(n)), dim3(256), 0, s, c->sv[ri], u, rc, n, c->csc_row,
-                       c->csc_rc, nullptr, nullptr);
-    LSHMF_LAUNCHED("k_gather_pair(csc)");
-    LSHMF_TRY(count_bins(it, n, c->cnt, d.N, s));
-    LSHMF_TRY(scan_excl(c->cnt, c->col_ptr, d.N, c->scan_tmp, s));
+// Compressed copy of n ratings by `major` (ptr over n_major rows, minor ids
+// ascending inside a row).
+int compress(lshmf_ctx* c, const int32_t* major, const int32_t* minor, const uint8_t* rc, int64_t n,
+             int64_t n_major, int64_t n_minor, int64_t* ptr, int32_t* idx, uint8_t* rc_out, hipStream_t s)
+{
+    int ri = 0;
+    if (n > 0) {
+        hipLaunchKernelGGL(k_keys_pair, dim3(grid_for(n)), dim3(256), 0, s, major, minor, n, n_minor, c->sk[0],
+                           c->sv[0]);
+        LSHMF_LAUNCHED("k_keys_pair");
+        LSHMF_TRY(radix_sort(c->sk, c->sv, n, bits_for((uint64_t)n_major * (uint64_t)n_minor), c->hist,
+                             c->scan_tmp, s, &ri));
+        hipLaunchKernelGGL(k_gather_pair, dim3(grid_for(n)), dim3(256), 0, s, c->sv[ri], minor, rc, n, idx, rc_out);
+        LSHMF_LAUNCHED("k_gather_pair");
+    }
+    LSHMF_TRY(count_bins(major, n, c->cnt, n_major, s));
+    return scan_excl(c->cnt, ptr, n_major, c->scan_tmp, s);
+}
 
-    // -- item rank: training degree descending, id ascending
-    const int idbits = bits_for((uint64_t)d.N);
-    hipLaunchKernelGGL(k_keys_rank, dim3(grid_for(d.N)), dim3(256), 0, s, c->col_ptr, d.N, n, idbits, c->sk[0],
+// CSR and CSC of the store's c->nnz ratings over c->M users and c->N items.
+int build_compressed(lshmf_ctx* c, hipStream_t s)
+{
+    LSHMF_TRY(compress(c, c->coo_i, c->coo_u, c->coo_rc, c->nnz, c->N, c->M, c->col_ptr, c->csc_row, c->csc_rc, s));
+    return compress(c, c->coo_u, c->coo_i, c->coo_rc, c->nnz, c->M, c->N, c->row_ptr, c->csr_col, c->csr_rc, s);
+}
+
+// The stratified stream of n ratings (u, it, rc) over the current M x N.
+int build_stream(lshmf_ctx* c, Stream& st, const int32_t* u, const int32_t* it, const uint8_t* rc, int64_t n,
+                 hipStream_t s)
+{
+    if (n > st.cap) {
+        set_error("a stream of %lld ratings exceeds its capacity %lld", (long long)n, (long long)st.cap);
+        return LSHMF_ECAPACITY;
+    }
+    st.n = st.max_block_nnz = st.max_block_slots = st.nseg = 0;
+    st.codes = false;
+    if (n == 0) return LSHMF_OK;
+    const int64_t P = c->P;
+    const StratKey sk{P, ceil_div(c->M, P), c->N};
+    int ri = 0;
+
+    // item order inside blocks: degree within these ratings desc, id asc
+    const int idbits = bits_for((uint64_t)c->N);
+    LSHMF_TRY(count_bins(it, n, c->cnt, c->N, s));
+    hipLaunchKernelGGL(k_keys_rank, dim3(grid_for(c->N)), dim3(256), 0, s, c->cnt, c->N, n, idbits, c->sk[0],
                        c->sv[0]);
     LSHMF_LAUNCHED("k_keys_rank");
-    LSHMF_TRY(radix_sort(c->sk, c->sv, d.N, idbits + bits_for((uint64_t)n + 1), c->hist, c->scan_tmp, s, &ri));
-    hipLaunchKernelGGL(k_rank_fill, dim3(grid_for(d.N)), dim3(256), 0, s, c->sv[ri], d.N, c->irank);
+    LSHMF_TRY(radix_sort(c->sk, c->sv, c->N, idbits + bits_for((uint64_t)n + 1), c->hist, c->scan_tmp, s, &ri));
+    hipLaunchKernelGGL(k_rank_fill, dim3(grid_for(c->N)), dim3(256), 0, s, c->sv[ri], c->N, c->irank);
     LSHMF_LAUNCHED("k_rank_fill");
 
-    // -- stratified block stream
-    int32_t* e2s = c->csr_spos;                              // edge -> stream position until the CSR step
+    // stream order and block ranges
     int32_t* bop = reinterpret_cast<int32_t*>(c->cnt);       // block of each stream position
     hipLaunchKernelGGL(k_keys_stream, dim3(grid_for(n)), dim3(256), 0, s, u, it, c->irank, n, sk, c->sk[0],
                        c->sv[0]);
     LSHMF_LAUNCHED("k_keys_stream");
     const int sbits = bits_for((uint64_t)(P * P) * (uint64_t)sk.N * (uint64_t)sk.MP);
     LSHMF_TRY(radix_sort(c->sk, c->sv, n, sbits, c->hist, c->scan_tmp, s, &ri));
-    hipLaunchKernelGGL(k_stream_fill, dim3(grid_for(n)), dim3(256), 0, s, c->sv[ri], u, it, rc, n, P,
-                       c->pk, c->sj, bop, e2s);
+    hipLaunchKernelGGL(k_stream_fill, dim3(grid_for(n)), dim3(256), 0, s, c->sv[ri], u, it, rc, n, P, st.pk,
+                       st.sj, bop, c->e2s);
     LSHMF_LAUNCHED("k_stream_fill");
-    LSHMF_TRY(count_bins(bop, n, c->blk_seg, P * P, s));       // blk_seg as a temporary
-    LSHMF_TRY(scan_excl(c->blk_seg, c->blk_ptr, P * P, c->scan_tmp, s));
-    // segments: a run of one item inside a block
-    hipLaunchKernelGGL(k_seg_flags, dim3(grid_for(n)), dim3(256), 0, s, c->sj, bop, n, c->seg_start);
+    LSHMF_TRY(count_bins(bop, n, st.blk_seg, P * P, s));       // blk_seg as a temporary
+    LSHMF_TRY(scan_excl(st.blk_seg, st.blk_ptr, P * P, c->scan_tmp, s));
+    // item runs inside blocks
+    hipLaunchKernelGGL(k_seg_flags, dim3(grid_for(n)), dim3(256), 0, s, st.sj, bop, n, st.seg_start);
     LSHMF_LAUNCHED("k_seg_flags");
     int64_t* ex = reinterpret_cast<int64_t*>(c->sk[ri ^ 1]);  // free sort buffer, n+1 int64
-    LSHMF_TRY(scan_excl(c->seg_start, ex, n, c->scan_tmp, s));
-    hipLaunchKernelGGL(k_seg_fill, dim3(grid_for(n)), dim3(256), 0, s, c->sj, bop, ex, n, c->seg_col,
-                       c->seg_start);
+    LSHMF_TRY(scan_excl(st.seg_start, ex, n, c->scan_tmp, s));
+    hipLaunchKernelGGL(k_seg_fill, dim3(grid_for(n)), dim3(256), 0, s, st.sj, bop, ex, n, st.seg_col,
+                       st.seg_start);
     LSHMF_LAUNCHED("k_seg_fill");
-    hipLaunchKernelGGL(k_blk_seg, dim3(grid_for(P * P + 1)), dim3(256), 0, s, c->blk_ptr, ex, P * P, n,
-                       c->blk_seg);
+    hipLaunchKernelGGL(k_blk_seg, dim3(grid_for(P * P + 1)), dim3(256), 0, s, st.blk_ptr, ex, P * P, n,
+                       st.blk_seg);
     LSHMF_LAUNCHED("k_blk_seg");
-    // dependencies: previous rating of the same user inside the block
-    hipLaunchKernelGGL(k_keys_dep, dim3(grid_for(n)), dim3(256), 0, s, u, it, c->irank, e2s, n, sk, c->sk[0],
-                       c->sv[0]);
+    // each user's chain of ratings inside a block
+    hipLaunchKernelGGL(k_keys_dep, dim3(grid_for(n)), dim3(256), 0, s, u, it, c->irank, c->e2s, n, sk,
+                       c->sk[0], c->sv[0]);
     LSHMF_LAUNCHED("k_keys_dep");
     LSHMF_TRY(radix_sort(c->sk, c->sv, n, sbits, c->hist, c->scan_tmp, s, &ri));
     int64_t* chain = reinterpret_cast<int64_t*>(c->sk[ri ^ 1]);  // n+1 int64, scanned in place
@@ -320,64 +370,93 @@ int ingest(lshmf_ctx* c, const int32_t* u, const int32_t* it, const uint8_t* rc,
     LSHMF_LAUNCHED("k_chain_flags");
     LSHMF_TRY(scan_excl(chain, chain, n, c->scan_tmp, s));
     hipLaunchKernelGGL(k_dep_fill, dim3(grid_for(n)), dim3(256), 0, s, c->sk[ri], c->sv[ri], n, sk.N, bop,
-                       c->blk_ptr, chain, c->dep, c->link);
+                       st.blk_ptr, chain, st.dep, st.link);
     LSHMF_LAUNCHED("k_dep_fill");
-    hipLaunchKernelGGL(k_block_slots, dim3(grid_for(P * P)), dim3(256), 0, s, c->blk_ptr, chain, P * P, c->blk_slots);
+    hipLaunchKernelGGL(k_block_slots, dim3(grid_for(P * P)), dim3(256), 0, s, st.blk_ptr, chain, P * P,
+                       st.blk_slots);
     LSHMF_LAUNCHED("k_block_slots");
-    // zero tails: the SGD kernel reads a few records past a segment's end
-    LSHMF_TRY(fill_i32(reinterpret_cast<int32_t*>(c->pk) + n, kStreamPad, 0, s));
-    LSHMF_TRY(fill_i32(reinterpret_cast<int32_t*>(c->link) + n, kStreamPad, 0, s));
-
-    // -- CSR by user, with the stream position of each rating
-    hipLaunchKernelGGL(k_keys_pair, dim3(grid_for(n)), dim3(256), 0, s, u, it, n, (int64_t)d.N, c->sk[0], c->sv[0]);
-    LSHMF_LAUNCHED("k_keys_pair(csr)");
-    LSHMF_TRY(radix_sort(c->sk, c->sv, n, bits_for((uint64_t)d.M * (uint64_t)d.N), c->hist, c->scan_tmp, s, &ri));
-    // e2s is read while csr_spos (the same memory) is written: stage e2s first
-    int32_t* e2s_copy = reinterpret_cast<int32_t*>(c->sk[ri ^ 1]);
-    LSHMF_HIP(hipMemcpyAsync(e2s_copy, e2s, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, s));
-    hipLaunchKernelGGL(k_gather_pair, dim3(grid_for(n)), dim3(256), 0, s, c->sv[ri], it, rc, n, c->csr_col,
-                       c->csr_rc, e2s_copy, c->csr_spos);
-    LSHMF_LAUNCHED("k_gather_pair(csr)");
-    LSHMF_TRY(count_bins(u, n, c->cnt, d.M, s));
-    LSHMF_TRY(scan_excl(c->cnt, c->row_ptr, d.M, c->scan_tmp, s));
-
-    // -- baselines (Sec. 3.2, simple case), FP64
-    unsigned long long* total = reinterpret_cast<unsigned long long*>(c->cnt);
-    LSHMF_TRY(fill_i64(c->cnt, 1, 0, s));
-    hipLaunchKernelGGL(k_sum_codes, dim3(grid_for(n, 256, 1024)), dim3(256), 0, s, rc, n, total);
-    LSHMF_LAUNCHED("k_sum_codes");
-    hipLaunchKernelGGL(k_mu, dim3(1), dim3(64), 0, s, total, n, d.rscale, c->t.mu);
-    LSHMF_LAUNCHED("k_mu");
-    hipLaunchKernelGGL(k_row_means, dim3(grid_for((int64_t)d.M * kWave)), dim3(256), 0, s, c->row_ptr,
-                       c->csr_rc, (int64_t)d.M, d.rscale, c->t.mu, c->t.b0);
-    LSHMF_LAUNCHED("k_row_means(users)");
-    hipLaunchKernelGGL(k_row_means, dim3(grid_for((int64_t)d.N * kWave)), dim3(256), 0, s, c->col_ptr,
-                       c->csc_rc, (int64_t)d.N, d.rscale, c->t.mu, c->t.bh0);
-    LSHMF_LAUNCHED("k_row_means(items)");
+    // zero tails: the SGD kernel reads a few records past a run's end
+    LSHMF_TRY(fill_i32(reinterpret_cast<int32_t*>(st.pk) + n, kStreamPad, 0, s));
+    LSHMF_TRY(fill_i32(reinterpret_cast<int32_t*>(st.link) + n, kStreamPad, 0, s));
 
     // largest block and most mailbox slots in a block, for the SGD kernel's limits
     const int64_t nb = P * P + 1;
     int64_t* hptr = new int64_t[2 * nb];
     int32_t* hslots = new int32_t[nb];
-    hipError_t e = hipMemcpyAsync(hptr, c->blk_ptr, sizeof(int64_t) * nb, hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(hptr + nb, c->blk_seg, sizeof(int64_t) * nb, hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(hslots, c->blk_slots, sizeof(int32_t) * (nb - 1), hipMemcpyDeviceToHost, s);
+    hipError_t e = hipMemcpyAsync(hptr, st.blk_ptr, sizeof(int64_t) * nb, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(hptr + nb, st.blk_seg, sizeof(int64_t) * nb, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(hslots, st.blk_slots, sizeof(int32_t) * (nb - 1), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
         delete[] hptr;
         delete[] hslots;
-        return hip_fail(e, "ingest: block pointers");
+        return hip_fail(e, "stream block pointers");
     }
     int64_t mx = 0, msl = 0;
     for (int64_t b = 0; b < P * P; ++b) {
         mx = hptr[b + 1] - hptr[b] > mx ? hptr[b + 1] - hptr[b] : mx;
         msl = hslots[b] > msl ? hslots[b] : msl;
     }
-    c->nseg = hptr[nb + P * P];
+    st.nseg = hptr[nb + P * P];
     delete[] hptr;
     delete[] hslots;
-    c->max_block_nnz = mx;
-    c->max_block_slots = msl;
+    st.n = n;
+    st.max_block_nnz = mx;
+    st.max_block_slots = msl;
+    st.codes = false;
+    return LSHMF_OK;
+}
+
+// mu, b0_i, bh0_j of the simple case (Sec. 3.2) over the whole store.
+int baselines_all(lshmf_ctx* c, hipStream_t s)
+{
+    const int64_t n = c->nnz;
+    unsigned long long* total = reinterpret_cast<unsigned long long*>(c->cnt);
+    LSHMF_TRY(fill_i64(c->cnt, 1, 0, s));
+    hipLaunchKernelGGL(k_sum_codes, dim3(grid_for(n, 256, 1024)), dim3(256), 0, s, c->coo_rc, n, total);
+    LSHMF_LAUNCHED("k_sum_codes");
+    hipLaunchKernelGGL(k_mu, dim3(1), dim3(64), 0, s, total, n, c->d.rscale, c->t.mu);
+    LSHMF_LAUNCHED("k_mu");
+    hipLaunchKernelGGL(k_row_means, dim3(grid_for((int64_t)c->M * kWave)), dim3(256), 0, s, c->row_ptr,
+                       c->csr_rc, (int64_t)c->M, c->d.rscale, c->t.mu, c->t.b0);
+    LSHMF_LAUNCHED("k_row_means(users)");
+    hipLaunchKernelGGL(k_row_means, dim3(grid_for((int64_t)c->N * kWave)), dim3(256), 0, s, c->col_ptr,
+                       c->csc_rc, (int64_t)c->N, c->d.rscale, c->t.mu, c->t.bh0);
+    LSHMF_LAUNCHED("k_row_means(items)");
+    return LSHMF_OK;
+}
+
+// Baselines of ids in [first, first + count) from n batch ratings.
+int baselines_new(lshmf_ctx* c, const int32_t* id, const uint8_t* rc, int64_t n, int32_t first, int32_t count,
+                  float* out, hipStream_t s)
+{
+    if (count <= 0) return LSHMF_OK;
+    unsigned long long* sum = reinterpret_cast<unsigned long long*>(c->cnt);
+    unsigned long long* cn = sum + count;
+    LSHMF_TRY(fill_i64(c->cnt, 2 * (int64_t)count, 0, s));
+    if (n > 0) {
+        hipLaunchKernelGGL(k_sum_by_id, dim3(grid_for(n)), dim3(256), 0, s, id, rc, n, first, sum, cn);
+        LSHMF_LAUNCHED("k_sum_by_id");
+    }
+    hipLaunchKernelGGL(k_new_means, dim3(grid_for(count)), dim3(256), 0, s, sum, cn, count, c->d.rscale, c->t.mu,
+                       out + first);
+    LSHMF_LAUNCHED("k_new_means");
+    return LSHMF_OK;
+}
+
+int ingest(lshmf_ctx* c, const int32_t* u, const int32_t* it, const uint8_t* rc, int64_t n, hipStream_t s)
+{
+    LSHMF_TRY(check_ids(c, u, it, rc, n, c->M, c->N, s));
+    if (n > 0) {
+        LSHMF_HIP(hipMemcpyAsync(c->coo_u, u, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, s));
+        LSHMF_HIP(hipMemcpyAsync(c->coo_i, it, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, s));
+        LSHMF_HIP(hipMemcpyAsync(c->coo_rc, rc, n, hipMemcpyDeviceToDevice, s));
+    }
+    c->nnz = n;
+    LSHMF_TRY(build_compressed(c, s));
+    LSHMF_TRY(baselines_all(c, s));
+    LSHMF_TRY(build_stream(c, c->train, c->coo_u, c->coo_i, c->coo_rc, n, s));
+    c->train_stale = false;
     return LSHMF_OK;
 }
 

@@ -352,25 +352,34 @@ static unsigned grid_for(int64_t n, int threads = 256, int64_t cap = 16384)
     return (unsigned)(b > cap ? cap : b);
 }
 
-int build_neighbours(lshmf_ctx* c, const uint32_t* H, uint64_t seed_fill, hipStream_t s)
+// acc += Psi(r)(2H-1) over the ratings of a CSC (col_ptr over c->N items).
+int hash_add(lshmf_ctx* c, const int64_t* col_ptr, const int32_t* row, const uint8_t* rc, int64_t nnz,
+             const uint32_t* H, hipStream_t s)
 {
-    const lshmf_dims& d = c->d;
-    const int64_t nnz = d.nnz;
-    // projection and signs
-    LSHMF_TRY(fill_i32(c->t.acc, (int64_t)d.N * c->B, 0, s));
     const int64_t waves = ceil_div(nnz, kAccChunk);
     if (waves > 0) {
-        hipLaunchKernelGGL(k_simlsh_acc, dim3((unsigned)ceil_div(waves * kWave, 256)), dim3(256), 0, s,
-                           c->col_ptr, c->csc_row, c->csc_rc, nnz, d.N, H, c->words, c->B, d.psi_exp,
-                           c->t.acc);
+        hipLaunchKernelGGL(k_simlsh_acc, dim3((unsigned)ceil_div(waves * kWave, 256)), dim3(256), 0, s, col_ptr, row,
+                           rc, nnz, c->N, H, c->words, c->B, c->d.psi_exp, c->t.acc);
         LSHMF_LAUNCHED("k_simlsh_acc");
     }
-    hipLaunchKernelGGL(k_simlsh_sign, dim3(grid_for((int64_t)d.N * c->words)), dim3(256), 0, s, c->t.acc,
-                       d.N, c->B, c->words, c->t.sig);
+    return LSHMF_OK;
+}
+
+int signs(lshmf_ctx* c, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_simlsh_sign, dim3(grid_for((int64_t)c->N * c->words)), dim3(256), 0, s, c->t.acc, c->N,
+                       c->B, c->words, c->t.sig);
     LSHMF_LAUNCHED("k_simlsh_sign");
-    // band keys and buckets
-    const int64_t nq = (int64_t)d.q * d.N;
-    hipLaunchKernelGGL(k_band_keys, dim3(grid_for(nq)), dim3(256), 0, s, c->t.sig, d.N, c->words, c->pG, d.q,
+    return LSHMF_OK;
+}
+
+// Band keys and buckets over all c->N items, then the top-K lists and the
+// neighbour baselines of items [j_first, j_first + count).
+int neighbours_for(lshmf_ctx* c, int32_t j_first, int32_t count, uint64_t seed_fill, hipStream_t s)
+{
+    const lshmf_dims& d = c->d;
+    const int64_t nq = (int64_t)d.q * c->N;
+    hipLaunchKernelGGL(k_band_keys, dim3(grid_for(nq)), dim3(256), 0, s, c->t.sig, c->N, c->words, c->pG, d.q,
                        c->sk[0], c->sv[0]);
     LSHMF_LAUNCHED("k_band_keys");
     int ri = 0;
@@ -379,27 +388,44 @@ int build_neighbours(lshmf_ctx* c, const uint32_t* H, uint64_t seed_fill, hipStr
     LSHMF_LAUNCHED("k_bucket_flags");
     int64_t* ex = reinterpret_cast<int64_t*>(c->sk[ri ^ 1]);
     LSHMF_TRY(scan_excl(c->cnt, ex, nq, c->scan_tmp, s));
-    hipLaunchKernelGGL(k_bucket_fill, dim3(grid_for(nq)), dim3(256), 0, s, c->sk[ri], c->sv[ri], ex, nq, d.N,
+    hipLaunchKernelGGL(k_bucket_fill, dim3(grid_for(nq)), dim3(256), 0, s, c->sk[ri], c->sv[ri], ex, nq, c->N,
                        c->pG, c->bitem, c->bbegin, c->bpos);
     LSHMF_LAUNCHED("k_bucket_fill");
-    // top-K per item (grid chunks keep the launch size modest)
-    for (int32_t j0 = 0; j0 < d.N; j0 += 65535) {
-        const int32_t nj = d.N - j0 < 65535 ? d.N - j0 : 65535;
-        hipLaunchKernelGGL(k_topk, dim3((unsigned)nj), dim3(kTopkThreads), 0, s, c->bitem, c->bbegin, c->bpos,
-                           d.N, d.q, d.K, seed_fill, c->t.JK, j0);
+    for (int32_t j0 = 0; j0 < count; j0 += 65535) {
+        const int32_t nj = count - j0 < 65535 ? count - j0 : 65535;
+        hipLaunchKernelGGL(k_topk, dim3((unsigned)nj), dim3(kTopkThreads), 0, s, c->bitem, c->bbegin, c->bpos, c->N,
+                           d.q, d.K, seed_fill, c->t.JK, j_first + j0);
         LSHMF_LAUNCHED("k_topk");
     }
-    // fixed baselines of the neighbour slots (read once per item segment by the SGD)
-    hipLaunchKernelGGL(k_nbr_b0, dim3(grid_for((int64_t)d.N * d.K)), dim3(256), 0, s, c->t.JK, c->t.bh0,
-                       (int64_t)d.N * d.K, c->nbr_b0);
-    LSHMF_LAUNCHED("k_nbr_b0");
-    // neighbour codes of every training rating
-    if (nnz > 0) {
-        hipLaunchKernelGGL(k_nbr_codes, dim3(grid_for(nnz * kWave, 256, 65536)), dim3(256), 0, s, c->pk, c->sj,
-                           nnz, c->t.JK, d.K, c->row_ptr, c->csr_col, c->csr_rc, c->nib, c->nstride);
-        LSHMF_LAUNCHED("k_nbr_codes");
+    // fixed baselines of the neighbour slots (read once per item run by the SGD)
+    const int64_t nk = (int64_t)count * d.K;
+    if (nk > 0) {
+        hipLaunchKernelGGL(k_nbr_b0, dim3(grid_for(nk)), dim3(256), 0, s, c->t.JK + (int64_t)j_first * d.K,
+                           c->t.bh0, nk, c->nbr_b0 + (int64_t)j_first * d.K);
+        LSHMF_LAUNCHED("k_nbr_b0");
     }
     return LSHMF_OK;
+}
+
+// Neighbour codes of every rating of a stream (R^K / N^K resolution).
+int stream_codes(lshmf_ctx* c, Stream& st, hipStream_t s)
+{
+    if (st.n > 0) {
+        hipLaunchKernelGGL(k_nbr_codes, dim3(grid_for(st.n * kWave, 256, 65536)), dim3(256), 0, s, st.pk, st.sj,
+                           st.n, c->t.JK, c->d.K, c->row_ptr, c->csr_col, c->csr_rc, st.nib, c->nstride);
+        LSHMF_LAUNCHED("k_nbr_codes");
+    }
+    st.codes = true;
+    return LSHMF_OK;
+}
+
+int build_neighbours(lshmf_ctx* c, const uint32_t* H, uint64_t seed_fill, hipStream_t s)
+{
+    LSHMF_TRY(fill_i32(c->t.acc, (int64_t)c->N * c->B, 0, s));
+    LSHMF_TRY(hash_add(c, c->col_ptr, c->csc_row, c->csc_rc, c->nnz, H, s));
+    LSHMF_TRY(signs(c, s));
+    LSHMF_TRY(neighbours_for(c, 0, c->N, seed_fill, s));
+    return stream_codes(c, c->train, s);
 }
 
 }  // namespace lshmf

@@ -42,6 +42,7 @@ struct SgdArgs {
     float* trash;
     int32_t* err;
     int F, K, P, nstride, s, slots;
+    int upd;          // bit 0: update the user side {b_i, u_i}; bit 1: the item side {bh_j, v_j, w_j, c_j}
     float inv_s;
     float g[6], l[6];
 };
@@ -101,6 +102,8 @@ __global__ __launch_bounds__(kSgdWaves* kWave) void k_sgd_stratum(SgdArgs a, con
     __syncthreads();
     const float mu = (float)(*a.mu);
     const float inv_s = a.inv_s;
+    const bool usr = (a.upd & 1) != 0;
+    const bool itm = (a.upd & 2) != 0;
 
     while (true) {
         int g = 0;
@@ -226,28 +229,28 @@ __global__ __launch_bounds__(kSgdWaves* kWave) void k_sgd_stratum(SgdArgs a, con
                 // every lane issues the same stores without branches.
                 const bool to_hbm = valid && !has_succ;
                 const int ws = has_succ ? slot : dummy;
-                const float bnew = bi + a.g[0] * (err - a.l[0] * bi);
+                const float bnew = usr ? bi + a.g[0] * (err - a.l[0] * bi) : bi;
                 float* bsink = a.trash + 2 * kWave * FP;
                 *((lane == 0 && to_hbm) ? a.bu + i : bsink + lane) = bnew;
                 mb_b[lane == 0 ? ws : dummy] = bnew;
                 const float bh_new = bh + a.g[1] * (err - a.l[1] * bh);
-                bh = valid ? bh_new : bh;
+                bh = (valid && itm) ? bh_new : bh;
 #pragma unroll
                 for (int x = 0; x < FP; ++x) {
                     const int f = lane + x * kWave;
-                    const float unew = u[x] + a.g[2] * (err * v[x] - a.l[2] * u[x]);
+                    const float unew = usr ? u[x] + a.g[2] * (err * v[x] - a.l[2] * u[x]) : u[x];
                     *((to_hbm && f < F) ? a.U + i * F + f : a.trash + kWave * FP + f) = unew;
                     mb_u[f < F ? ws * F + f : dummy * F] = unew;
                     const float vn = v[x] + a.g[3] * (err * u[x] - a.l[3] * v[x]);
-                    v[x] = valid ? vn : v[x];
+                    v[x] = (valid && itm) ? vn : v[x];
                 }
 #pragma unroll
                 for (int y = 0; y < KP; ++y) {
                     const bool in_k = lane + y * kWave < K;
                     const float wn = w[y] + a.g[4] * (sR * err * resid[y] - a.l[4] * w[y]);
                     const float cn = c[y] + a.g[5] * (sN * err - a.l[5] * c[y]);
-                    w[y] = (valid && in_k && code[y]) ? wn : w[y];
-                    c[y] = (valid && in_k && !code[y]) ? cn : c[y];
+                    w[y] = (valid && itm && in_k && code[y]) ? wn : w[y];
+                    c[y] = (valid && itm && in_k && !code[y]) ? cn : c[y];
                 }
             }
             // the mailbox rows are written: publish their sequence numbers
@@ -326,22 +329,24 @@ static int launch_sgd_k(const SgdArgs& args, const uint32_t* pk, const uint32_t*
     return args.K <= kWave ? launch_sgd<FP, 1>(args, pk, link, s) : launch_sgd<FP, 2>(args, pk, link, s);
 }
 
-int run_sgd_epoch(lshmf_ctx* c, const lshmf_hparams* hp, int epoch, hipStream_t s)
+// One SGD pass over a stream; upd selects the parameter sides to update.
+int run_sgd(lshmf_ctx* c, Stream& st, const lshmf_hparams* hp, int epoch, int upd, hipStream_t s)
 {
     const lshmf_dims& d = c->d;
-    const size_t lds = (size_t)(c->max_block_slots + 1) * (d.F + 2) * sizeof(float);
-    if (c->max_block_slots > kMaxSlots || lds > (size_t)kMaxMailboxBytes || c->max_block_nnz > kMaxChainPos) {
-        set_error("sgd_epoch: a block needs %lld mailbox slots (%zu bytes of LDS, limit %d) or holds %lld "
+    if (st.n == 0) return LSHMF_OK;
+    const size_t lds = (size_t)(st.max_block_slots + 1) * (d.F + 2) * sizeof(float);
+    if (st.max_block_slots > kMaxSlots || lds > (size_t)kMaxMailboxBytes || st.max_block_nnz > kMaxChainPos) {
+        set_error("sgd: a block needs %lld mailbox slots (%zu bytes of LDS, limit %d) or holds %lld "
                   "ratings (limit %d); raise n_strata",
-                  (long long)c->max_block_slots, lds, kMaxMailboxBytes, (long long)c->max_block_nnz, kMaxChainPos);
+                  (long long)st.max_block_slots, lds, kMaxMailboxBytes, (long long)st.max_block_nnz, kMaxChainPos);
         return LSHMF_ECAPACITY;
     }
     SgdArgs a;
-    a.nib = c->nib;
-    a.blk_ptr = c->blk_ptr;
-    a.blk_seg = c->blk_seg;
-    a.seg_col = c->seg_col;
-    a.seg_start = c->seg_start;
+    a.nib = st.nib;
+    a.blk_ptr = st.blk_ptr;
+    a.blk_seg = st.blk_seg;
+    a.seg_col = st.seg_col;
+    a.seg_start = st.seg_start;
     a.nbr_b0 = c->nbr_b0;
     a.b0 = c->t.b0;
     a.mu = c->t.mu;
@@ -357,7 +362,8 @@ int run_sgd_epoch(lshmf_ctx* c, const lshmf_hparams* hp, int epoch, hipStream_t 
     a.K = d.K;
     a.P = c->P;
     a.nstride = c->nstride;
-    a.slots = (int)c->max_block_slots;
+    a.slots = (int)st.max_block_slots;
+    a.upd = upd;
     a.inv_s = 1.0f / (float)d.rscale;
     // Eq. (learn_rate): gamma_t = alpha / (1 + beta * t^1.5)
     const double den = 1.0 + (double)hp->beta * std::pow((double)epoch, 1.5);
@@ -366,13 +372,13 @@ int run_sgd_epoch(lshmf_ctx* c, const lshmf_hparams* hp, int epoch, hipStream_t 
         a.l[x] = hp->lambda[x];
     }
     const int fp = (d.F + kWave - 1) / kWave;
-    for (int st = 0; st < c->P; ++st) {
-        a.s = st;
+    for (int stratum = 0; stratum < c->P; ++stratum) {
+        a.s = stratum;
         switch (fp) {
-            case 1: LSHMF_TRY(launch_sgd_k<1>(a, c->pk, c->link, s)); break;
-            case 2: LSHMF_TRY(launch_sgd_k<2>(a, c->pk, c->link, s)); break;
-            case 3: LSHMF_TRY(launch_sgd_k<3>(a, c->pk, c->link, s)); break;
-            default: LSHMF_TRY(launch_sgd_k<4>(a, c->pk, c->link, s)); break;
+            case 1: LSHMF_TRY(launch_sgd_k<1>(a, st.pk, st.link, s)); break;
+            case 2: LSHMF_TRY(launch_sgd_k<2>(a, st.pk, st.link, s)); break;
+            case 3: LSHMF_TRY(launch_sgd_k<3>(a, st.pk, st.link, s)); break;
+            default: LSHMF_TRY(launch_sgd_k<4>(a, st.pk, st.link, s)); break;
         }
     }
     return LSHMF_OK;
@@ -473,7 +479,7 @@ int run_predict(lshmf_ctx* c, const int32_t* qu, const int32_t* qi, int64_t n, f
     if (n <= 0) return LSHMF_OK;
     const lshmf_dims& d = c->d;
     PredArgs a{c->t.JK, c->t.b0, c->t.bh0, c->t.mu, c->t.U, c->t.V, c->t.bu, c->t.bv, c->t.W, c->t.C,
-               c->row_ptr, c->csr_col, c->csr_rc, d.M, d.N, d.F, d.K, 1.0f / (float)d.rscale};
+               c->row_ptr, c->csr_col, c->csr_rc, c->M, c->N, d.F, d.K, 1.0f / (float)d.rscale};
     int64_t blocks = ceil_div(n * kWave, 256);
     if (blocks > 65536) blocks = 65536;
     const int fp = (d.F + kWave - 1) / kWave;

@@ -33,7 +33,8 @@ class Dims(C.Structure):
     _fields_ = [("M", C.c_int32), ("N", C.c_int32), ("F", C.c_int32), ("K", C.c_int32),
                 ("G", C.c_int32), ("p", C.c_int32), ("q", C.c_int32), ("rscale", C.c_int32),
                 ("psi_exp", C.c_int32), ("n_strata", C.c_int32), ("storage", C.c_int32),
-                ("reserved", C.c_int32), ("nnz", C.c_int64)]
+                ("reserved", C.c_int32), ("nnz", C.c_int64), ("M_cap", C.c_int32),
+                ("N_cap", C.c_int32), ("nnz_cap", C.c_int64), ("batch_cap", C.c_int64)]
 
 
 class HParams(C.Structure):
@@ -50,7 +51,8 @@ class Layout(C.Structure):
     _fields_ = [(n, C.c_void_p) for n in
                 ("pk", "sj", "dep", "nib", "blk_ptr", "blk_seg", "seg_col", "seg_start",
                  "row_ptr", "csr_col", "csr_rc", "col_ptr", "csc_row", "csc_rc", "err")] + \
-               [("nstride", C.c_int32), ("P", C.c_int32)]
+               [("nstride", C.c_int32), ("P", C.c_int32), ("M", C.c_int32), ("N", C.c_int32),
+                ("nnz", C.c_int64)]
 
 
 _lock = threading.Lock()
@@ -75,6 +77,8 @@ def lib():
             L.lshmf_ingest.argtypes = [vp, vp, vp, vp, i64, vp]
             L.build_lsh_neighbours.argtypes = [vp, vp, u64, vp]
             L.sgd_epoch.argtypes = [vp, C.POINTER(HParams), i32, vp]
+            L.online_update.argtypes = [vp, vp, vp, vp, i64, i32, i32, vp, u64, C.POINTER(HParams),
+                                        i32, i32, vp]
             L.predict.argtypes = [vp, vp, vp, i64, vp, vp]
             L.lshmf_rmse.argtypes = [vp, vp, vp, i64, vp, vp]
             L.lshmf_export_layout.argtypes = [vp, C.POINTER(Layout)]
@@ -108,9 +112,14 @@ class LshMF:
     """Device-resident LSH-MF model driven through the C ABI."""
 
     def __init__(self, M: int, N: int, F: int, K: int, G: int, p: int, q: int, rscale: int,
-                 nnz: int, psi_exp: int = 2, n_strata: int = 256, device="cuda"):
+                 nnz: int, psi_exp: int = 2, n_strata: int = 256, device="cuda",
+                 M_cap: int = 0, N_cap: int = 0, nnz_cap: int = 0, batch_cap: int = 0):
+        """Tables are allocated for the capacities (0: the initial M, N, nnz);
+        batch_cap > 0 enables online_update batches of up to that many ratings."""
         self.device = torch.device(device)
-        self.dims = Dims(M, N, F, K, G, p, q, rscale, psi_exp, n_strata, 0, 0, nnz)
+        self.dims = Dims(M, N, F, K, G, p, q, rscale, psi_exp, n_strata, 0, 0, nnz,
+                         M_cap, N_cap, nnz_cap, batch_cap)
+        M, N = max(M, M_cap), max(N, N_cap)
         self.B = G * p * q
         self.words = (self.B + 31) // 32
         h = C.c_void_p()
@@ -154,9 +163,9 @@ class LshMF:
 
     # -- tables
     def set_factors(self, U0: torch.Tensor, V0: torch.Tensor):
-        """Initial U, V (copied); b, bh, W, C start at zero."""
-        self.U.copy_(U0)
-        self.V.copy_(V0)
+        """Initial U, V of the first rows (copied); b, bh, W, C start at zero."""
+        self.U[: U0.shape[0]].copy_(U0)
+        self.V[: V0.shape[0]].copy_(V0)
         for t in (self.bu, self.bv, self.W, self.C):
             t.zero_()
 
@@ -170,13 +179,36 @@ class LshMF:
 
     def build_lsh_neighbours(self, H: torch.Tensor, seed_fill: int):
         assert H.dtype in (torch.int32,) and H.is_contiguous()
-        assert tuple(H.shape) == (self.dims.M, self.words)
+        assert H.dim() == 2 and H.shape[1] == self.words and H.shape[0] >= self.dims.M
         _check(lib().build_lsh_neighbours(self._h, _ptr(H), C.c_uint64(seed_fill & (2**64 - 1)),
                                           _stream(self.device)))
 
     def sgd_epoch(self, alpha, lam, beta: float, epoch: int):
         hp = HParams((C.c_float * 6)(*alpha), (C.c_float * 6)(*lam), beta, 0)
         _check(lib().sgd_epoch(self._h, C.byref(hp), epoch, _stream(self.device)))
+
+    def online_update(self, u: torch.Tensor, i: torch.Tensor, rc: torch.Tensor, M_new: int, N_new: int,
+                      H: torch.Tensor, seed_fill: int, alpha, lam, beta: float, epoch: int,
+                      passes: int = 1, U_new: Optional[torch.Tensor] = None,
+                      V_new: Optional[torch.Tensor] = None):
+        """Folds a batch of ratings into the model (Sec. 4.3); U_new / V_new
+        are the initial factor rows of the new users / items."""
+        assert u.dtype == torch.int32 and i.dtype == torch.int32 and rc.dtype == torch.uint8
+        assert u.is_contiguous() and i.is_contiguous() and rc.is_contiguous()
+        assert H.dtype == torch.int32 and H.is_contiguous() and H.shape[1] == self.words
+        assert H.shape[0] >= M_new
+        lay = self.layout()
+        # rows beyond the capacity are left to the library to reject
+        if lay.M < M_new <= self.U.shape[0]:
+            assert U_new is not None and tuple(U_new.shape) == (M_new - lay.M, self.dims.F)
+            self.U[lay.M: M_new].copy_(U_new)
+        if lay.N < N_new <= self.V.shape[0]:
+            assert V_new is not None and tuple(V_new.shape) == (N_new - lay.N, self.dims.F)
+            self.V[lay.N: N_new].copy_(V_new)
+        hp = HParams((C.c_float * 6)(*alpha), (C.c_float * 6)(*lam), beta, 0)
+        _check(lib().online_update(self._h, _ptr(u), _ptr(i), _ptr(rc), u.numel(), M_new, N_new,
+                                   _ptr(H), C.c_uint64(seed_fill & (2**64 - 1)), C.byref(hp),
+                                   epoch, passes, _stream(self.device)))
 
     def predict(self, u: torch.Tensor, i: torch.Tensor, out: Optional[torch.Tensor] = None):
         assert u.dtype == torch.int32 and i.dtype == torch.int32

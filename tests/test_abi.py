@@ -14,7 +14,7 @@ from paper_2111_11682_amd import lshmf
 def test_library_exports_every_header_function():
     L = lshmf.lib()
     names = lshmf.header_functions()
-    assert {"build_lsh_neighbours", "sgd_epoch", "predict", "lshmf_ingest",
+    assert {"build_lsh_neighbours", "sgd_epoch", "predict", "online_update", "lshmf_ingest",
             "lshmf_rmse"} <= set(names)
     for n in names:
         assert hasattr(L, n), n
@@ -22,7 +22,7 @@ def test_library_exports_every_header_function():
 
 def _create(**kw):
     base = dict(M=943, N=1682, F=32, K=10, G=8, p=1, q=8, rscale=1, psi_exp=2, n_strata=16,
-                storage=0, reserved=0, nnz=90000)
+                storage=0, reserved=0, nnz=90000, M_cap=0, N_cap=0, nnz_cap=0, batch_cap=0)
     base.update(kw)
     d = lshmf.Dims(*[base[f] for f, _ in lshmf.Dims._fields_])
     h = C.c_void_p()
@@ -33,7 +33,8 @@ def _create(**kw):
 @pytest.mark.parametrize("bad", [dict(K=0), dict(K=1682), dict(K=129), dict(F=0), dict(F=257),
                                  dict(G=8, p=5, q=1), dict(G=8, p=1, q=33), dict(rscale=3),
                                  dict(psi_exp=0), dict(n_strata=0), dict(storage=1),
-                                 dict(nnz=-1), dict(M=0), dict(N=1)])
+                                 dict(nnz=-1), dict(M=0), dict(N=1), dict(M_cap=900),
+                                 dict(N_cap=1000), dict(nnz_cap=100), dict(batch_cap=-1)])
 def test_create_rejects_bad_dims(bad):
     st, h = _create(**bad)
     assert st == -1
@@ -53,7 +54,21 @@ def test_arena_size_and_bind_checks():
     assert lshmf.lib().lshmf_bind(h, C.byref(t), C.c_void_p(4096), n.value - 1) == -3  # too small
     # calls out of order report ESTATE without touching the device
     assert lshmf.lib().sgd_epoch(h, None, 0, None) == -2
+    assert lshmf.lib().online_update(h, None, None, None, 0, 943, 1682, None, 0, None, 0, 1,
+                                     None) == -2
     lshmf.lib().lshmf_destroy(h)
+
+
+def test_arena_grows_with_capacities():
+    sizes = []
+    for kw in (dict(), dict(M_cap=2000, N_cap=3000, nnz_cap=200000), dict(batch_cap=50000)):
+        st, h = _create(**kw)
+        assert st == 0
+        n = C.c_size_t()
+        assert lshmf.lib().lshmf_arena_bytes(h, C.byref(n)) == 0
+        sizes.append(n.value)
+        lshmf.lib().lshmf_destroy(h)
+    assert sizes[1] > sizes[0] + 110000 * 20 and sizes[2] > sizes[0] + 3 * 50000 * 20
 
 
 def test_binding_has_no_cpu_fallback(monkeypatch):
