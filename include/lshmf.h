@@ -53,7 +53,8 @@ typedef struct lshmf_dims {
     int32_t rscale;    /* rating code scale, 1 or 2                          */
     int32_t psi_exp;   /* Psi(r) = rc^psi_exp in the hash sums (2: Psi = r^2) */
     int32_t n_strata;  /* P: users and items split into P blocks by id mod P */
-    int32_t storage;   /* LSHMF_FP32 (BF16 reserved)                         */
+    int32_t storage;   /* LSHMF_FP32, or LSHMF_BF16: BF16 copies of U, V, W, C
+                          for serving next to the FP32 masters              */
     int32_t reserved;
     int64_t nnz;       /* ratings of the initial training set                */
     /* Capacities for online learning (0: the initial size; batch_cap 0: no
@@ -85,7 +86,13 @@ typedef struct lshmf_hparams {
  *   b0 [M]     bh0 [N]           fixed baseline deviations of the "simple case"
  *   mu [1]     double            global mean
  * U, V, bu, bv, W, C are read and written by sgd_epoch; the caller initialises
- * them (the paper's Alg. CULSH-MF takes the initial values as input). */
+ * them (the paper's Alg. CULSH-MF takes the initial values as input).
+ *
+ * Storage mode LSHMF_BF16 adds U16 [M*F], V16 [N*F], W16 [N*K], C16 [N*K]:
+ * BF16 bit patterns (round to nearest even) of the FP32 tables above, which
+ * stay the masters that SGD reads and writes.  Every call that changes a
+ * master row also rewrites its BF16 copy; predict reads the copies.  The
+ * pointers are ignored in mode LSHMF_FP32. */
 typedef struct lshmf_tables {
     float* U;
     float* V;
@@ -99,6 +106,10 @@ typedef struct lshmf_tables {
     float* b0;
     float* bh0;
     double* mu;
+    uint16_t* U16;
+    uint16_t* V16;
+    uint16_t* W16;
+    uint16_t* C16;
 } lshmf_tables;
 
 typedef struct lshmf_ctx lshmf_ctx; /* opaque, host memory */
@@ -174,6 +185,11 @@ int online_update(lshmf_ctx* ctx, const int32_t* d_u, const int32_t* d_i, const 
  * the user's training items.  Ids out of range give NaN for that query. */
 int predict(lshmf_ctx* ctx, const int32_t* d_u, const int32_t* d_i, int64_t n, float* d_out,
             lshmf_stream_t stream);
+
+/* Storage mode LSHMF_BF16: rewrites every BF16 copy from the FP32 masters,
+ * for a caller that edited the masters itself.  build_lsh_neighbours does
+ * the same; in mode LSHMF_FP32 this does nothing. */
+int lshmf_sync_storage(lshmf_ctx* ctx, lshmf_stream_t stream);
 
 /* RMSE of predictions against rating codes (Sec. 5.1), reduced in FP64 in a
  * fixed order: d_out[0] = sqrt(sum (rc/rscale - pred)^2 / n). */

@@ -18,6 +18,7 @@ int run_online(lshmf_ctx* c, const int32_t* u, const int32_t* it, const uint8_t*
                int passes, hipStream_t s);
 int run_predict(lshmf_ctx* c, const int32_t* qu, const int32_t* qi, int64_t n, float* out, hipStream_t s);
 int run_rmse(lshmf_ctx* c, const float* pred, const uint8_t* rc, int64_t n, double* out, hipStream_t s);
+int refresh_bf16(lshmf_ctx* c, int64_t m0, int64_t m1, int64_t n0, int64_t n1, hipStream_t s);
 
 namespace {
 
@@ -147,8 +148,8 @@ int validate(const lshmf_dims* d)
         set_error("n_strata=%d outside 1..4096", d->n_strata);
         return LSHMF_EINVAL;
     }
-    if (d->storage != LSHMF_FP32) {
-        set_error("only LSHMF_FP32 storage is available");
+    if (d->storage != LSHMF_FP32 && d->storage != LSHMF_BF16) {
+        set_error("storage=%d is neither LSHMF_FP32 nor LSHMF_BF16", d->storage);
         return LSHMF_EINVAL;
     }
     if (d->nnz < 0 || d->nnz >= ((int64_t)1 << 31)) {
@@ -232,6 +233,10 @@ int lshmf_bind(lshmf_ctx* ctx, const lshmf_tables* t, void* d_arena, size_t aren
         set_error("a table pointer is NULL");
         return LSHMF_EINVAL;
     }
+    if (ctx->d.storage == LSHMF_BF16 && (!t->U16 || !t->V16 || !t->W16 || !t->C16)) {
+        set_error("storage mode BF16 needs the U16, V16, W16 and C16 tables");
+        return LSHMF_EINVAL;
+    }
     if (reinterpret_cast<uintptr_t>(d_arena) & 255) {
         set_error("arena must be 256-byte aligned");
         return LSHMF_EINVAL;
@@ -281,7 +286,9 @@ int build_lsh_neighbours(lshmf_ctx* ctx, const uint32_t* d_H, uint64_t seed_fill
         set_error("build_lsh_neighbours: H is NULL");
         return LSHMF_EINVAL;
     }
-    LSHMF_TRY(build_neighbours(ctx, d_H, seed_fill, reinterpret_cast<hipStream_t>(stream)));
+    const hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    LSHMF_TRY(build_neighbours(ctx, d_H, seed_fill, s));
+    LSHMF_TRY(refresh_bf16(ctx, 0, ctx->M, 0, ctx->N, s));
     ctx->neighbours = true;
     return LSHMF_OK;
 }
@@ -357,6 +364,15 @@ int lshmf_rmse(lshmf_ctx* ctx, const float* d_pred, const uint8_t* d_rc, int64_t
         return LSHMF_EINVAL;
     }
     return run_rmse(ctx, d_pred, d_rc, n, d_out, reinterpret_cast<hipStream_t>(stream));
+}
+
+int lshmf_sync_storage(lshmf_ctx* ctx, lshmf_stream_t stream)
+{
+    if (!ctx || !ctx->bound) {
+        set_error("lshmf_sync_storage: context not bound");
+        return LSHMF_ESTATE;
+    }
+    return refresh_bf16(ctx, 0, ctx->M, 0, ctx->N, reinterpret_cast<hipStream_t>(stream));
 }
 
 int lshmf_export_layout(const lshmf_ctx* ctx, lshmf_layout* out)

@@ -271,13 +271,14 @@ static unsigned grid_for(int64_t n, int threads = 256, int64_t cap = 16384)
 int check_ids(lshmf_ctx* c, const int32_t* u, const int32_t* it, const uint8_t* rc, int64_t n, int32_t M,
               int32_t N, hipStream_t s)
 {
-    LSHMF_TRY(fill_i32(c->err, 1, 0, s));
+    int32_t* flag = c->err + 1;  // a word of its own: c->err[0] is the SGD status word
+    LSHMF_TRY(fill_i32(flag, 1, 0, s));
     if (n > 0) {
-        hipLaunchKernelGGL(k_check_ids, dim3(grid_for(n)), dim3(256), 0, s, u, it, rc, n, M, N, c->err);
+        hipLaunchKernelGGL(k_check_ids, dim3(grid_for(n)), dim3(256), 0, s, u, it, rc, n, M, N, flag);
         LSHMF_LAUNCHED("k_check_ids");
     }
     int32_t herr = 0;
-    LSHMF_HIP(hipMemcpyAsync(&herr, c->err, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    LSHMF_HIP(hipMemcpyAsync(&herr, flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     LSHMF_HIP(hipStreamSynchronize(s));
     if (herr) {
         set_error("a rating has a user outside [0,%d), an item outside [0,%d) or a code outside 1..15", M, N);
@@ -446,6 +447,7 @@ int baselines_new(lshmf_ctx* c, const int32_t* id, const uint8_t* rc, int64_t n,
 
 int ingest(lshmf_ctx* c, const int32_t* u, const int32_t* it, const uint8_t* rc, int64_t n, hipStream_t s)
 {
+    LSHMF_TRY(fill_i32(c->err, 1, 0, s));  // the device status word starts healthy
     LSHMF_TRY(check_ids(c, u, it, rc, n, c->M, c->N, s));
     if (n > 0) {
         LSHMF_HIP(hipMemcpyAsync(c->coo_u, u, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, s));

@@ -34,6 +34,7 @@ int signs(lshmf_ctx* c, hipStream_t s);
 int neighbours_for(lshmf_ctx* c, int32_t j_first, int32_t count, uint64_t seed_fill, hipStream_t s);
 int stream_codes(lshmf_ctx* c, Stream& st, hipStream_t s);
 int run_sgd(lshmf_ctx* c, Stream& st, const lshmf_hparams* hp, int epoch, int upd, hipStream_t s);
+int refresh_bf16(lshmf_ctx* c, int64_t m0, int64_t m1, int64_t n0, int64_t n1, hipStream_t s);
 
 namespace {
 
@@ -104,6 +105,7 @@ int run_online(lshmf_ctx* c, const int32_t* u, const int32_t* it, const uint8_t*
     LSHMF_TRY(fill_f32(c->t.bv + N_old, N_new - N_old, 0.0f, s));
     LSHMF_TRY(fill_f32(c->t.W + (int64_t)N_old * K, (int64_t)(N_new - N_old) * K, 0.0f, s));
     LSHMF_TRY(fill_f32(c->t.C + (int64_t)N_old * K, (int64_t)(N_new - N_old) * K, 0.0f, s));
+    LSHMF_TRY(refresh_bf16(c, M_old, M_new, N_old, N_new, s));
 
     // 3. fixed baselines of the new ids (before the neighbour baselines read them)
     LSHMF_TRY(baselines_new(c, u, rc, n, M_old, M_new - M_old, c->t.b0, s));

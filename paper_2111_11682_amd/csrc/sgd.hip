@@ -39,6 +39,10 @@ struct SgdArgs {
     float* bv;
     float* W;
     float* C;
+    uint16_t* U16;    // BF16 serving copies (storage mode BF16 only)
+    uint16_t* V16;
+    uint16_t* W16;
+    uint16_t* C16;
     float* trash;
     int32_t* err;
     int F, K, P, nstride, s, slots;
@@ -53,6 +57,17 @@ __device__ inline float dpp_f32(float x)
     return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), CTRL, ROW_MASK,
                                                                  0xF, BOUND_ZERO));
 }
+
+// FP32 -> BF16 with round-to-nearest-even on the dropped 16 bits (NaN stays
+// a quiet NaN).
+__device__ inline uint16_t to_bf16(float x)
+{
+    const uint32_t u = __float_as_uint(x);
+    if ((u & 0x7FFFFFFFu) > 0x7F800000u) return (uint16_t)0x7FC0u;
+    return (uint16_t)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+}
+
+__device__ inline float from_bf16(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
 // Full 64-lane sum with DPP row operations; the total ends in lane 63 and is
 // broadcast through a scalar register.  Fixed association order.
@@ -81,7 +96,8 @@ struct Stage {
     uint32_t lk[kGroup];      // hand-over word
 };
 
-template <int FP, int KP>
+// BF: also keep the BF16 copies of the rows the kernel writes.
+template <int FP, int KP, bool BF>
 __global__ __launch_bounds__(kSgdWaves* kWave) void k_sgd_stratum(SgdArgs a, const uint32_t* __restrict__ pk,
                                                                    const uint32_t* __restrict__ link)
 {
@@ -240,6 +256,10 @@ __global__ __launch_bounds__(kSgdWaves* kWave) void k_sgd_stratum(SgdArgs a, con
                     const int f = lane + x * kWave;
                     const float unew = usr ? u[x] + a.g[2] * (err * v[x] - a.l[2] * u[x]) : u[x];
                     *((to_hbm && f < F) ? a.U + i * F + f : a.trash + kWave * FP + f) = unew;
+                    if constexpr (BF) {
+                        uint16_t* sink = reinterpret_cast<uint16_t*>(a.trash + 3 * kWave * FP) + f;
+                        *((to_hbm && f < F) ? a.U16 + i * F + f : sink) = to_bf16(unew);
+                    }
                     mb_u[f < F ? ws * F + f : dummy * F] = unew;
                     const float vn = v[x] + a.g[3] * (err * u[x] - a.l[3] * v[x]);
                     v[x] = (valid && itm) ? vn : v[x];
@@ -294,7 +314,10 @@ __global__ __launch_bounds__(kSgdWaves* kWave) void k_sgd_stratum(SgdArgs a, con
 #pragma unroll
         for (int x = 0; x < FP; ++x) {
             const int f = lane + x * kWave;
-            if (f < F) a.V[j * F + f] = v[x];
+            if (f < F) {
+                a.V[j * F + f] = v[x];
+                if constexpr (BF) a.V16[j * F + f] = to_bf16(v[x]);
+            }
         }
         if (lane == 0) a.bv[j] = bh;
 #pragma unroll
@@ -303,30 +326,65 @@ __global__ __launch_bounds__(kSgdWaves* kWave) void k_sgd_stratum(SgdArgs a, con
             if (k < K) {
                 a.W[j * K + k] = w[y];
                 a.C[j * K + k] = c[y];
+                if constexpr (BF) {
+                    a.W16[j * K + k] = to_bf16(w[y]);
+                    a.C16[j * K + k] = to_bf16(c[y]);
+                }
             }
         }
     }
 }
 
-template <int FP, int KP>
+// BF16 copies of n FP32 values.
+__global__ void k_to_bf16(const float* src, uint16_t* dst, int64_t n)
+{
+    for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < n;
+         x += (int64_t)gridDim.x * blockDim.x)
+        dst[x] = to_bf16(src[x]);
+}
+
+int to_bf16_rows(const float* src, uint16_t* dst, int64_t n, hipStream_t s)
+{
+    if (n <= 0) return LSHMF_OK;
+    int64_t b = ceil_div(n, 256);
+    if (b > 16384) b = 16384;
+    hipLaunchKernelGGL(k_to_bf16, dim3((unsigned)b), dim3(256), 0, s, src, dst, n);
+    LSHMF_LAUNCHED("k_to_bf16");
+    return LSHMF_OK;
+}
+
+// BF16 copies of the rows [m0, m1) of U and [n0, n1) of V, W, C.
+int refresh_bf16(lshmf_ctx* c, int64_t m0, int64_t m1, int64_t n0, int64_t n1, hipStream_t s)
+{
+    if (c->d.storage != LSHMF_BF16) return LSHMF_OK;
+    const int64_t F = c->d.F, K = c->d.K;
+    LSHMF_TRY(to_bf16_rows(c->t.U + m0 * F, c->t.U16 + m0 * F, (m1 - m0) * F, s));
+    LSHMF_TRY(to_bf16_rows(c->t.V + n0 * F, c->t.V16 + n0 * F, (n1 - n0) * F, s));
+    LSHMF_TRY(to_bf16_rows(c->t.W + n0 * K, c->t.W16 + n0 * K, (n1 - n0) * K, s));
+    return to_bf16_rows(c->t.C + n0 * K, c->t.C16 + n0 * K, (n1 - n0) * K, s);
+}
+
+template <int FP, int KP, bool BF>
 static int launch_sgd(const SgdArgs& args, const uint32_t* pk, const uint32_t* link, hipStream_t s)
 {
     const size_t lds = (size_t)(args.slots + 1) * (args.F + 2) * sizeof(float);
     if (lds > 64 * 1024) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sgd_stratum<FP, KP>),
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sgd_stratum<FP, KP, BF>),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return hip_fail(e, "hipFuncSetAttribute(k_sgd_stratum)");
     }
-    hipLaunchKernelGGL((k_sgd_stratum<FP, KP>), dim3((unsigned)args.P), dim3(kSgdWaves * kWave), lds, s, args, pk,
-                       link);
+    hipLaunchKernelGGL((k_sgd_stratum<FP, KP, BF>), dim3((unsigned)args.P), dim3(kSgdWaves * kWave), lds, s, args,
+                       pk, link);
     LSHMF_LAUNCHED("k_sgd_stratum");
     return LSHMF_OK;
 }
 
 template <int FP>
-static int launch_sgd_k(const SgdArgs& args, const uint32_t* pk, const uint32_t* link, hipStream_t s)
+static int launch_sgd_k(const SgdArgs& args, bool bf, const uint32_t* pk, const uint32_t* link, hipStream_t s)
 {
-    return args.K <= kWave ? launch_sgd<FP, 1>(args, pk, link, s) : launch_sgd<FP, 2>(args, pk, link, s);
+    if (bf)
+        return args.K <= kWave ? launch_sgd<FP, 1, true>(args, pk, link, s) : launch_sgd<FP, 2, true>(args, pk, link, s);
+    return args.K <= kWave ? launch_sgd<FP, 1, false>(args, pk, link, s) : launch_sgd<FP, 2, false>(args, pk, link, s);
 }
 
 // One SGD pass over a stream; upd selects the parameter sides to update.
@@ -356,6 +414,10 @@ int run_sgd(lshmf_ctx* c, Stream& st, const lshmf_hparams* hp, int epoch, int up
     a.bv = c->t.bv;
     a.W = c->t.W;
     a.C = c->t.C;
+    a.U16 = c->t.U16;
+    a.V16 = c->t.V16;
+    a.W16 = c->t.W16;
+    a.C16 = c->t.C16;
     a.trash = c->trash;
     a.err = c->err;
     a.F = d.F;
@@ -372,13 +434,14 @@ int run_sgd(lshmf_ctx* c, Stream& st, const lshmf_hparams* hp, int epoch, int up
         a.l[x] = hp->lambda[x];
     }
     const int fp = (d.F + kWave - 1) / kWave;
+    const bool bf = d.storage == LSHMF_BF16;
     for (int stratum = 0; stratum < c->P; ++stratum) {
         a.s = stratum;
         switch (fp) {
-            case 1: LSHMF_TRY(launch_sgd_k<1>(a, st.pk, st.link, s)); break;
-            case 2: LSHMF_TRY(launch_sgd_k<2>(a, st.pk, st.link, s)); break;
-            case 3: LSHMF_TRY(launch_sgd_k<3>(a, st.pk, st.link, s)); break;
-            default: LSHMF_TRY(launch_sgd_k<4>(a, st.pk, st.link, s)); break;
+            case 1: LSHMF_TRY(launch_sgd_k<1>(a, bf, st.pk, st.link, s)); break;
+            case 2: LSHMF_TRY(launch_sgd_k<2>(a, bf, st.pk, st.link, s)); break;
+            case 3: LSHMF_TRY(launch_sgd_k<3>(a, bf, st.pk, st.link, s)); break;
+            default: LSHMF_TRY(launch_sgd_k<4>(a, bf, st.pk, st.link, s)); break;
         }
     }
     return LSHMF_OK;
@@ -390,12 +453,12 @@ struct PredArgs {
     const float* b0;
     const float* bh0;
     const double* mu;
-    const float* U;
-    const float* V;
+    const void* U;    // float, or BF16 bits in storage mode BF16
+    const void* V;
     const float* bu;
     const float* bv;
-    const float* W;
-    const float* C;
+    const void* W;
+    const void* C;
     const int64_t* row_ptr;
     const int32_t* csr_col;
     const uint8_t* csr_rc;
@@ -403,12 +466,19 @@ struct PredArgs {
     float inv_s;
 };
 
+__device__ inline float ld_tab(const float* p, int64_t x) { return p[x]; }
+__device__ inline float ld_tab(const uint16_t* p, int64_t x) { return from_bf16(p[x]); }
+
 // One wave per query: Eq. (rr) with R^K / N^K resolved by binary search of
-// each neighbour in the user's training row.
-template <int FP, int KP>
+// each neighbour in the user's training row.  T: storage type of U, V, W, C.
+template <int FP, int KP, typename T>
 __global__ __launch_bounds__(256) void k_predict(PredArgs a, const int32_t* qu, const int32_t* qi, int64_t n,
                                                  float* out)
 {
+    const T* U = static_cast<const T*>(a.U);
+    const T* V = static_cast<const T*>(a.V);
+    const T* W = static_cast<const T*>(a.W);
+    const T* C = static_cast<const T*>(a.C);
     const int lane = threadIdx.x & (kWave - 1);
     const int64_t w0 = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kWave;
     const int64_t nw = (int64_t)gridDim.x * blockDim.x / kWave;
@@ -425,7 +495,7 @@ __global__ __launch_bounds__(256) void k_predict(PredArgs a, const int32_t* qu, 
 #pragma unroll
         for (int y = 0; y < FP; ++y) {
             const int f = lane + y * kWave;
-            if (f < F) part += a.U[i * F + f] * a.V[j * F + f];
+            if (f < F) part += ld_tab(U, i * F + f) * ld_tab(V, j * F + f);
         }
         int code[KP];
         int nb[KP];
@@ -455,8 +525,8 @@ __global__ __launch_bounds__(256) void k_predict(PredArgs a, const int32_t* qu, 
         for (int y = 0; y < KP; ++y) {
             const int k = lane + y * kWave;
             if (k < K) {
-                if (code[y]) part += ((float)code[y] * a.inv_s - base_i - a.bh0[nb[y]]) * a.W[j * K + k] * sR;
-                else part += a.C[j * K + k] * sN;
+                if (code[y]) part += ((float)code[y] * a.inv_s - base_i - a.bh0[nb[y]]) * ld_tab(W, j * K + k) * sR;
+                else part += ld_tab(C, j * K + k) * sN;
             }
         }
         const float tot = wave_sum(part);
@@ -464,30 +534,42 @@ __global__ __launch_bounds__(256) void k_predict(PredArgs a, const int32_t* qu, 
     }
 }
 
-template <int FP>
-static void launch_predict_k(const PredArgs& a, const int32_t* qu, const int32_t* qi, int64_t n, float* out,
+template <int FP, typename T>
+static void launch_predict_t(const PredArgs& a, const int32_t* qu, const int32_t* qi, int64_t n, float* out,
                              unsigned grid, hipStream_t s)
 {
     if (a.K <= kWave)
-        hipLaunchKernelGGL((k_predict<FP, 1>), dim3(grid), dim3(256), 0, s, a, qu, qi, n, out);
+        hipLaunchKernelGGL((k_predict<FP, 1, T>), dim3(grid), dim3(256), 0, s, a, qu, qi, n, out);
     else
-        hipLaunchKernelGGL((k_predict<FP, 2>), dim3(grid), dim3(256), 0, s, a, qu, qi, n, out);
+        hipLaunchKernelGGL((k_predict<FP, 2, T>), dim3(grid), dim3(256), 0, s, a, qu, qi, n, out);
+}
+
+template <int FP>
+static void launch_predict_k(const PredArgs& a, bool bf, const int32_t* qu, const int32_t* qi, int64_t n,
+                             float* out, unsigned grid, hipStream_t s)
+{
+    if (bf) launch_predict_t<FP, uint16_t>(a, qu, qi, n, out, grid, s);
+    else launch_predict_t<FP, float>(a, qu, qi, n, out, grid, s);
 }
 
 int run_predict(lshmf_ctx* c, const int32_t* qu, const int32_t* qi, int64_t n, float* out, hipStream_t s)
 {
     if (n <= 0) return LSHMF_OK;
     const lshmf_dims& d = c->d;
-    PredArgs a{c->t.JK, c->t.b0, c->t.bh0, c->t.mu, c->t.U, c->t.V, c->t.bu, c->t.bv, c->t.W, c->t.C,
+    const bool bf = d.storage == LSHMF_BF16;
+    PredArgs a{c->t.JK, c->t.b0, c->t.bh0, c->t.mu,
+               bf ? (const void*)c->t.U16 : (const void*)c->t.U, bf ? (const void*)c->t.V16 : (const void*)c->t.V,
+               c->t.bu, c->t.bv,
+               bf ? (const void*)c->t.W16 : (const void*)c->t.W, bf ? (const void*)c->t.C16 : (const void*)c->t.C,
                c->row_ptr, c->csr_col, c->csr_rc, c->M, c->N, d.F, d.K, 1.0f / (float)d.rscale};
     int64_t blocks = ceil_div(n * kWave, 256);
     if (blocks > 65536) blocks = 65536;
     const int fp = (d.F + kWave - 1) / kWave;
     switch (fp) {
-        case 1: launch_predict_k<1>(a, qu, qi, n, out, (unsigned)blocks, s); break;
-        case 2: launch_predict_k<2>(a, qu, qi, n, out, (unsigned)blocks, s); break;
-        case 3: launch_predict_k<3>(a, qu, qi, n, out, (unsigned)blocks, s); break;
-        default: launch_predict_k<4>(a, qu, qi, n, out, (unsigned)blocks, s); break;
+        case 1: launch_predict_k<1>(a, bf, qu, qi, n, out, (unsigned)blocks, s); break;
+        case 2: launch_predict_k<2>(a, bf, qu, qi, n, out, (unsigned)blocks, s); break;
+        case 3: launch_predict_k<3>(a, bf, qu, qi, n, out, (unsigned)blocks, s); break;
+        default: launch_predict_k<4>(a, bf, qu, qi, n, out, (unsigned)blocks, s); break;
     }
     LSHMF_LAUNCHED("k_predict");
     return LSHMF_OK;

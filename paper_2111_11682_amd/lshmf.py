@@ -19,6 +19,7 @@ LIB_PATH = os.environ.get("LSHMF_LIB") or os.path.join(HERE, "liblshmf.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "lshmf.h")
 
 LSHMF_OK = 0
+LSHMF_FP32, LSHMF_BF16 = 0, 1
 STATUS = {0: "LSHMF_OK", -1: "LSHMF_EINVAL", -2: "LSHMF_ESTATE", -3: "LSHMF_ECAPACITY",
           -4: "LSHMF_EDEVICE"}
 
@@ -44,7 +45,8 @@ class HParams(C.Structure):
 
 class Tables(C.Structure):
     _fields_ = [(n, C.c_void_p) for n in
-                ("U", "V", "bu", "bv", "W", "C", "JK", "acc", "sig", "b0", "bh0", "mu")]
+                ("U", "V", "bu", "bv", "W", "C", "JK", "acc", "sig", "b0", "bh0", "mu",
+                 "U16", "V16", "W16", "C16")]
 
 
 class Layout(C.Structure):
@@ -82,6 +84,7 @@ def lib():
             L.predict.argtypes = [vp, vp, vp, i64, vp, vp]
             L.lshmf_rmse.argtypes = [vp, vp, vp, i64, vp, vp]
             L.lshmf_export_layout.argtypes = [vp, C.POINTER(Layout)]
+            L.lshmf_sync_storage.argtypes = [vp, vp]
             L.lshmf_last_error.restype = C.c_char_p
             L.lshmf_last_error.argtypes = []
             _lib = L
@@ -113,11 +116,16 @@ class LshMF:
 
     def __init__(self, M: int, N: int, F: int, K: int, G: int, p: int, q: int, rscale: int,
                  nnz: int, psi_exp: int = 2, n_strata: int = 256, device="cuda",
-                 M_cap: int = 0, N_cap: int = 0, nnz_cap: int = 0, batch_cap: int = 0):
+                 M_cap: int = 0, N_cap: int = 0, nnz_cap: int = 0, batch_cap: int = 0,
+                 storage: str = "fp32"):
         """Tables are allocated for the capacities (0: the initial M, N, nnz);
-        batch_cap > 0 enables online_update batches of up to that many ratings."""
+        batch_cap > 0 enables online_update batches of up to that many ratings.
+        storage "bf16" adds BF16 copies U16, V16, W16, C16 that predict reads."""
         self.device = torch.device(device)
-        self.dims = Dims(M, N, F, K, G, p, q, rscale, psi_exp, n_strata, 0, 0, nnz,
+        assert storage in ("fp32", "bf16")
+        self.storage = storage
+        self.dims = Dims(M, N, F, K, G, p, q, rscale, psi_exp, n_strata,
+                         LSHMF_BF16 if storage == "bf16" else LSHMF_FP32, 0, nnz,
                          M_cap, N_cap, nnz_cap, batch_cap)
         M, N = max(M, M_cap), max(N, N_cap)
         self.B = G * p * q
@@ -144,9 +152,19 @@ class LshMF:
         self.arena = torch.empty(int(nbytes.value) + 256, dtype=torch.uint8, device=dev)
         off = (-self.arena.data_ptr()) % 256
         self._arena_ptr = self.arena.data_ptr() + off
-        self.tables = Tables(*[t.data_ptr() for t in (self.U, self.V, self.bu, self.bv, self.W,
-                                                       self.C, self.JK, self.acc, self.sig,
-                                                       self.b0, self.bh0, self.mu)])
+        bf16 = dict(dtype=torch.bfloat16, device=dev)
+        if storage == "bf16":
+            self.U16 = torch.zeros(M, F, **bf16)
+            self.V16 = torch.zeros(N, F, **bf16)
+            self.W16 = torch.zeros(N, K, **bf16)
+            self.C16 = torch.zeros(N, K, **bf16)
+            half = [t.data_ptr() for t in (self.U16, self.V16, self.W16, self.C16)]
+        else:
+            self.U16 = self.V16 = self.W16 = self.C16 = None
+            half = [0, 0, 0, 0]
+        self.tables = Tables(*([t.data_ptr() for t in (self.U, self.V, self.bu, self.bv, self.W,
+                                                        self.C, self.JK, self.acc, self.sig,
+                                                        self.b0, self.bh0, self.mu)] + half))
         _check(lib().lshmf_bind(h, C.byref(self.tables), C.c_void_p(self._arena_ptr),
                                 C.c_size_t(int(nbytes.value))))
 
@@ -209,6 +227,10 @@ class LshMF:
         _check(lib().online_update(self._h, _ptr(u), _ptr(i), _ptr(rc), u.numel(), M_new, N_new,
                                    _ptr(H), C.c_uint64(seed_fill & (2**64 - 1)), C.byref(hp),
                                    epoch, passes, _stream(self.device)))
+
+    def sync_storage(self):
+        """BF16 mode: rewrite the BF16 copies from the FP32 masters."""
+        _check(lib().lshmf_sync_storage(self._h, _stream(self.device)))
 
     def predict(self, u: torch.Tensor, i: torch.Tensor, out: Optional[torch.Tensor] = None):
         assert u.dtype == torch.int32 and i.dtype == torch.int32

@@ -32,7 +32,7 @@ def _create(**kw):
 
 @pytest.mark.parametrize("bad", [dict(K=0), dict(K=1682), dict(K=129), dict(F=0), dict(F=257),
                                  dict(G=8, p=5, q=1), dict(G=8, p=1, q=33), dict(rscale=3),
-                                 dict(psi_exp=0), dict(n_strata=0), dict(storage=1),
+                                 dict(psi_exp=0), dict(n_strata=0), dict(storage=2),
                                  dict(nnz=-1), dict(M=0), dict(N=1), dict(M_cap=900),
                                  dict(N_cap=1000), dict(nnz_cap=100), dict(batch_cap=-1)])
 def test_create_rejects_bad_dims(bad):
@@ -47,11 +47,18 @@ def test_arena_size_and_bind_checks():
     n = C.c_size_t()
     assert lshmf.lib().lshmf_arena_bytes(h, C.byref(n)) == 0
     assert n.value > 90000 * 20
-    t = lshmf.Tables(*([0] * 12))
+    t = lshmf.Tables(*([0] * 16))
     assert lshmf.lib().lshmf_bind(h, C.byref(t), C.c_void_p(256), n.value) == -1   # NULL tables
-    t = lshmf.Tables(*([4096] * 12))
+    t = lshmf.Tables(*([4096] * 12 + [0] * 4))
     assert lshmf.lib().lshmf_bind(h, C.byref(t), C.c_void_p(4096 + 16), n.value) == -1  # unaligned
     assert lshmf.lib().lshmf_bind(h, C.byref(t), C.c_void_p(4096), n.value - 1) == -3  # too small
+    # BF16 storage needs its four copies
+    st, h2 = _create(storage=1)
+    assert st == 0
+    n2 = C.c_size_t()
+    assert lshmf.lib().lshmf_arena_bytes(h2, C.byref(n2)) == 0
+    assert lshmf.lib().lshmf_bind(h2, C.byref(t), C.c_void_p(4096), n2.value) == -1
+    lshmf.lib().lshmf_destroy(h2)
     # calls out of order report ESTATE without touching the device
     assert lshmf.lib().sgd_epoch(h, None, 0, None) == -2
     assert lshmf.lib().online_update(h, None, None, None, 0, 943, 1682, None, 0, None, 0, 1,

@@ -63,7 +63,7 @@ def _setup(name, frac_new, stream_frac, nb, passes):
 
     # GPU: the same, with room for the whole stream
     m = lshmf.LshMF(M0, N0, w.F, w.K, w.G, w.p, w.q, w.rscale, pu.size, n_strata=P,
-                    M_cap=w.M, N_cap=w.N, nnz_cap=d["train_u"].size,
+                    M_cap=w.M, N_cap=w.N, nnz_cap=d["train_u"].size + 64,
                     batch_cap=max(b[0].size for b in batches))
     dev = m.device
     m.ingest(*[torch.from_numpy(a).to(dev) for a in (pu, pi, prc)])
