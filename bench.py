@@ -15,6 +15,7 @@ Prints ONE JSON line.  The roofline object covers the dominant kernel
 measured average launch time, against the 8 TB/s HBM peak.
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -28,37 +29,68 @@ def log(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
 
 
-def sgd_bytes_per_epoch(nnz, nseg, F, K, nstride):
-    """Algorithmic HBM bytes of one epoch of k_sgd_stratum (FP32 tables).
+def sgd_bytes_per_epoch(nnz, nseg, F, K, nstride, storage="fp32"):
+    """Algorithmic HBM bytes of one epoch of k_sgd_stratum.
 
-    Per rating: packed (user, code) 4 + dependency 4 + neighbour codes nstride
-    + u_i read and write 8F + b_i read and write 8 + fixed baseline b0_i 4.
-    Per item segment (a run of one item inside a block): v_j read and write 8F,
-    bh_j 8, w_j and c_j read and write 16K, neighbour ids and their fixed
-    baselines 8K, segment descriptor 12.
+    Per rating: packed (user, code) 4 + hand-over word 4 + neighbour codes
+    nstride + u_i read and write 8F + b_i read and write 8 + fixed baseline
+    b0_i 4.  Per item segment (a run of one item inside a block): v_j read and
+    write 8F, bh_j read and write 8, w_j and c_j read and write 16K, the fixed
+    baselines of the K neighbours 4K, segment descriptor 12.  BF16 storage adds
+    the BF16 copies written: 2F per rating, 2F + 4K per segment.
     """
     per_rating = 4 + 4 + nstride + 8 * F + 8 + 4
-    per_seg = 8 * F + 8 + 16 * K + 8 * K + 12
+    per_seg = 8 * F + 8 + 16 * K + 4 * K + 12
+    if storage == "bf16":
+        per_rating += 2 * F
+        per_seg += 2 * F + 4 * K
     return nnz * per_rating + nseg * per_seg
 
 
-def cpu_baseline(w, d, P):
-    """The FP64 oracle's SGD epoch on a bounded sample of the same workload."""
-    import numpy as np
+KERNEL_SOURCES = ("paper_2111_11682_amd/csrc/sgd.hip", "paper_2111_11682_amd/csrc/common.hpp",
+                  "include/lshmf.h")
+PROFILE = os.path.join(ROOT, "profiles", "k_sgd_stratum_ml10m.md")
+
+
+def kernel_fingerprint():
+    """sha256 over the sources of the SGD kernel."""
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    return h.hexdigest()
+
+
+def profiled_traffic():
+    """HBM bytes per k_sgd_stratum launch from the committed counter summary,
+    or None when the kernel's sources changed since the counters were taken."""
+    if not os.path.exists(PROFILE):
+        return None
+    rec = None
+    for line in open(PROFILE):
+        line = line.strip()
+        if line.startswith("{") and "traffic_bytes_per_launch" in line:
+            rec = json.loads(line)
+    if rec is None or rec.get("source_sha256") != kernel_fingerprint():
+        return None
+    return int(rec["traffic_bytes_per_launch"])
+
+
+def cpu_baseline(w, d, P, epochs=2):
+    """The FP64 oracle's SGD on the same training set, a bounded number of epochs."""
     from oracle import oracle as orc
-    keep = (d["train_u"] % 16) == 0
-    u, it, rc = d["train_u"][keep], d["train_i"][keep], d["train_rc"][keep]
+    u, it, rc = d["train_u"], d["train_i"], d["train_rc"]
     _, sig = orc.simlsh(w.M, w.N, w.B, u, it, rc, d["H"])
     JK = orc.topk(sig, w.B, w.G, w.p, w.q, w.K, 12345)
     m = orc.Model(w.M, w.N, w.F, w.K, w.rscale, u, it, rc, JK, d["U0"], d["V0"])
-    m.sgd_epoch(P, w.alpha, w.lam, w.beta, 0)       # builds the schedule
+    m._sched[P] = orc.schedule(P, u, it)             # the layout, untimed
     t0 = time.perf_counter()
-    m.sgd_epoch(P, w.alpha, w.lam, w.beta, 1)
+    for t in range(epochs):
+        m.sgd_epoch(P, w.alpha, w.lam, w.beta, t)
     dt = time.perf_counter() - t0
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": float(u.size / dt), "unit": "updates/s", "cores": cores, "kind": "oracle",
-            "sample": "one FP64 oracle SGD epoch (K-neighbour term, P=%d strata) over the %d "
-                      "training ratings of users with id %% 16 == 0, %.1f s" % (P, u.size, dt)}
+    return {"value": float(epochs * u.size / dt), "unit": "updates/s", "cores": cores, "kind": "oracle",
+            "sample": "%d FP64 oracle SGD epochs (K-neighbour term, P=%d strata, OpenMP over the blocks "
+                      "of a stratum) over all %d training ratings, %.1f s" % (epochs, P, u.size, dt)}
 
 
 def main():
@@ -69,6 +101,8 @@ def main():
     ap.add_argument("--workload", default="ml10m")
     ap.add_argument("--epochs", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--storage", choices=("fp32", "bf16"), default="fp32",
+                    help="bf16: BF16 copies of U, V, W, C beside the FP32 masters")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one plain 1 GiB device copy, the reference for HBM byte counters")
     args = ap.parse_args()
@@ -94,7 +128,8 @@ def main():
     H = torch.from_numpy(d["H"].view(np.int32)).to(dev)
     nnz = d["train_u"].size
     P = w.n_strata
-    m = lshmf.LshMF(w.M, w.N, w.F, w.K, w.G, w.p, w.q, w.rscale, nnz, n_strata=P, device=dev)
+    m = lshmf.LshMF(w.M, w.N, w.F, w.K, w.G, w.p, w.q, w.rscale, nnz, n_strata=P, device=dev,
+                    storage=args.storage)
     pred = torch.empty(d["test_u"].size, dtype=torch.float32, device=dev)
     rmse = torch.empty(1, dtype=torch.float64, device=dev)
     sgd_events = []
@@ -142,12 +177,13 @@ def main():
 
     lay = m.layout()
     nseg = int(m.arena_view(lay.blk_seg, P * P + 1, torch.int64)[-1].item())
-    epoch_bytes = sgd_bytes_per_epoch(nnz, nseg, w.F, w.K, lay.nstride)
+    epoch_bytes = sgd_bytes_per_epoch(nnz, nseg, w.F, w.K, lay.nstride, args.storage)
     launch_bytes = epoch_bytes / P
     launch_s = sgd_ms_epoch / 1e3 / P
     achieved = launch_bytes / launch_s / 1e9
+    traffic = profiled_traffic() if (args.workload == "ml10m" and args.storage == "fp32") else None
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": 8000.0, "unit": "GB/s",
-                "frac": round(achieved / 8000.0, 5), "traffic": None,
+                "frac": round(achieved / 8000.0, 5), "traffic": traffic,
                 "kernel": "k_sgd_stratum", "launch_bytes": int(launch_bytes),
                 "launch_us": round(launch_s * 1e6, 3)}
 
@@ -174,7 +210,7 @@ def main():
         "config": {"workload": "ml10m-shaped LSH-MF training job", "users": w.M, "items": w.N,
                    "train_ratings": int(nnz), "test_ratings": int(d["test_u"].size), "F": w.F,
                    "K": w.K, "hash_bits": w.B, "p": w.p, "q": w.q, "epochs": epochs,
-                   "n_strata": P, "heldout_rmse": round(final_rmse, 6),
+                   "n_strata": P, "storage": args.storage, "heldout_rmse": round(final_rmse, 6),
                    "sgd_ms_per_epoch": round(sgd_ms_epoch, 3),
                    "sgd_updates_per_s": round(nnz / (sgd_ms_epoch / 1e3), 1)},
         "roofline": roofline,
