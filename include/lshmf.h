@@ -181,6 +181,65 @@ int online_update(lshmf_ctx* ctx, const int32_t* d_u, const int32_t* d_i, const 
                   int32_t M_new, int32_t N_new, const uint32_t* d_H, uint64_t seed_fill,
                   const lshmf_hparams* hp, int32_t epoch, int32_t passes, lshmf_stream_t stream);
 
+/* ---- Serving loop: continuous batching of online updates and queries ----
+ *
+ * lshmf_serve replays a request log against the model in arrival order, the
+ * way a server takes the online sparse stream that motivates Sec. 4.3:
+ *   - an update request is one online_update call (its initial factor rows of
+ *     new ids come from d_U0 / d_V0); one that exceeds batch_cap or the free
+ *     store is refused (status LSHMF_ECAPACITY) and leaves the model as it is;
+ *   - consecutive query requests that have arrived by the time the GPU can
+ *     take them are merged into one predict launch of at most
+ *     max_query_batch pairs (a larger single request is refused); a query
+ *     sees exactly the updates that arrived before it, so the answers do not
+ *     depend on how requests were merged;
+ *   - payload uploads and result downloads run on a copy stream beside the
+ *     compute stream, double-buffered in the caller's device staging area.
+ * Request times are seconds from the start of the call; the loop waits for
+ * arrivals in real time (all zero: back to back).  Host payload arrays
+ * should be pinned for the copies to overlap. */
+enum { LSHMF_REQ_UPDATE = 0, LSHMF_REQ_QUERY = 1 };
+
+typedef struct lshmf_request {
+    int32_t kind;            /* LSHMF_REQ_UPDATE or LSHMF_REQ_QUERY                  */
+    int32_t M_new, N_new;    /* update: users and items after the batch              */
+    int32_t reserved;
+    int64_t offset;          /* first element of the payload (h_u/h_i/h_rc or h_qu/h_qi/h_pred) */
+    int64_t n;               /* ratings or query pairs                               */
+    double arrival;          /* seconds from the start of the call                   */
+} lshmf_request;
+
+typedef struct lshmf_serve_io {
+    const lshmf_request* req;  /* host, n_req entries, arrivals non-decreasing      */
+    int64_t n_req;
+    const int32_t* h_u;        /* host update payload                               */
+    const int32_t* h_i;
+    const uint8_t* h_rc;
+    const int32_t* h_qu;       /* host query payload                                */
+    const int32_t* h_qi;
+    float* h_pred;             /* host, answers at each query request's offset      */
+    const float* d_U0;         /* device, initial rows of new users [M_cap*F]       */
+    const float* d_V0;         /* device, initial rows of new items [N_cap*F]       */
+    const uint32_t* d_H;       /* device, user strings of M_cap users               */
+    uint64_t seed_fill;
+    lshmf_hparams hp;
+    int32_t epoch, passes;     /* online_update's learning-rate epoch and passes    */
+    int64_t max_query_batch;   /* pairs per predict launch                          */
+    void* d_stage;             /* device staging, lshmf_serve_stage_bytes() bytes   */
+    size_t stage_bytes;
+    double* h_start;           /* host out: launch time of each request (s)         */
+    double* h_done;            /* host out: time its result was complete (s)        */
+    int32_t* h_status;         /* host out: LSHMF_OK or the refusal status          */
+} lshmf_serve_io;
+
+/* Device staging bytes lshmf_serve needs for max_query_batch pairs. */
+int lshmf_serve_stage_bytes(const lshmf_ctx* ctx, int64_t max_query_batch, size_t* bytes);
+
+/* Runs the loop until every request is answered or refused.  compute and
+ * copy must be different streams (NULL is not allowed).  Returns the first
+ * hard failure (a HIP error or LSHMF_ESTATE); refusals are per request. */
+int lshmf_serve(lshmf_ctx* ctx, const lshmf_serve_io* io, lshmf_stream_t compute, lshmf_stream_t copy);
+
 /* Eq. (rr) for n query pairs (d_u[x], d_i[x]) -> d_out[x] (FP32), with R(i)
  * the user's training items.  Ids out of range give NaN for that query. */
 int predict(lshmf_ctx* ctx, const int32_t* d_u, const int32_t* d_i, int64_t n, float* d_out,

@@ -18,9 +18,17 @@
 namespace lshmf {
 
 constexpr int kSgdWaves = 8;
-constexpr int kGroup = 8;                        // ratings per pipeline stage
+constexpr int kGroup = 4;                        // ratings per pipeline stage
+constexpr int kHelpers = 3;                      // helper waves of a gang
+constexpr int kGangWaves = kHelpers + 1;
+constexpr int kMaxGangs = 1;                     // gangs per block
+constexpr int kGangMin = 48;                     // shortest segment given a gang
+constexpr int kRing = 32;                        // ring slots of a gang (power of two)
+constexpr int kHG = 4;                           // ratings per helper pipeline stage
 constexpr int kSpinLimit = 1 << 24;              // bounded wait: a broken hand-over ends the kernel
-constexpr int kMaxMailboxBytes = 150 * 1024;     // dynamic LDS of one block
+constexpr int kMaxMailboxBytes = 150 * 1024;     // mailbox part of a block's dynamic LDS
+constexpr int kMaxLdsBytes = 160 * 1024 - 256;   // all of it (static LDS aside)
+static_assert(kMaxGangs * kGangWaves <= kSgdWaves, "every gang role needs a wave");
 constexpr int kMaxChainPos = (1 << 14) - 1;      // link encoding limits
 constexpr int kMaxSlots = (1 << 16) - 2;
 
@@ -47,6 +55,9 @@ struct SgdArgs {
     int32_t* err;
     int F, K, P, nstride, s, slots;
     int upd;          // bit 0: update the user side {b_i, u_i}; bit 1: the item side {bh_j, v_j, w_j, c_j}
+    int max_gangs;    // gangs the LDS holds (0: every segment is run by a single wave)
+    int ring_off;     // float offset of the gang rings in dynamic LDS
+    int ring_rs;      // floats per ring slot: u (F), rw (K), cn (K)
     float inv_s;
     float g[6], l[6];
 };
@@ -97,6 +108,15 @@ struct Stage {
 };
 
 // BF: also keep the BF16 copies of the rows the kernel writes.
+// HBM inputs of kHG ratings of a helper wave, loaded a stage ahead of use.
+template <int FP, int KP>
+struct HStage {
+    float u[kHG][FP];
+    float bi[kHG], b0[kHG];
+    uint32_t nb[kHG][KP];
+    uint32_t pw[kHG], lw[kHG];
+};
+
 template <int FP, int KP, bool BF>
 __global__ __launch_bounds__(kSgdWaves* kWave) void k_sgd_stratum(SgdArgs a, const uint32_t* __restrict__ pk,
                                                                    const uint32_t* __restrict__ link)
@@ -113,13 +133,293 @@ __global__ __launch_bounds__(kSgdWaves* kWave) void k_sgd_stratum(SgdArgs a, con
     const int64_t blk = (int64_t)a.s * a.P + blockIdx.x;
     const int64_t g0 = a.blk_seg[blk], g1 = a.blk_seg[blk + 1];
     const int nsegs = (int)(g1 - g0);
+    // The first segments of the block, while long, each get a gang: an item
+    // wave that keeps the item state and runs only the dependent update chain,
+    // fed through an LDS ring by helper waves that load and prepare the
+    // user-side inputs of every rating.
+    int ngang = 0;
+    for (int k = 0; k < a.max_gangs && k < nsegs; ++k) {
+        if (a.seg_start[g0 + k + 1] - a.seg_start[g0 + k] < kGangMin) break;
+        ngang = k + 1;
+    }
+    const int RS = a.ring_rs;
+    const int GS = kRing * RS + kRing * 4 + kRing + 4;  // floats per gang: data, headers, ready, consumed
+    float* rings = smem + a.ring_off;
     for (int x = threadIdx.x; x <= dummy; x += blockDim.x) mb_seq[x] = 0;
-    if (threadIdx.x == 0) next_seg = 0;
+    for (int gi = 0; gi < ngang; ++gi) {
+        int* ready = reinterpret_cast<int*>(rings + (size_t)gi * GS + kRing * RS + kRing * 4);
+        for (int x = threadIdx.x; x <= kRing; x += blockDim.x) ready[x] = 0;  // ready[] and consumed
+    }
+    if (threadIdx.x == 0) next_seg = ngang;
     __syncthreads();
     const float mu = (float)(*a.mu);
     const float inv_s = a.inv_s;
     const bool usr = (a.upd & 1) != 0;
     const bool itm = (a.upd & 2) != 0;
+    const int wv = threadIdx.x / kWave;
+
+    if (wv < ngang * kGangWaves) {
+        const int gang = wv / kGangWaves, role = wv % kGangWaves;
+        const int64_t seg = g0 + gang;
+        const int64_t j = a.seg_col[seg];
+        const int64_t ea = a.seg_start[seg];
+        const int len = (int)(a.seg_start[seg + 1] - ea);
+        float* rdata = rings + (size_t)gang * GS;
+        int* rhdr = reinterpret_cast<int*>(rdata + kRing * RS);
+        int* rready = rhdr + kRing * 4;
+        int* rcons = rready + kRing;
+        if (role == 0) {
+            // ---- item wave: Eq. (rr) and Eq. (sgd_update) in stream order
+            __builtin_amdgcn_s_setprio(3);
+            float v[FP], w[KP], c[KP];
+#pragma unroll
+            for (int x = 0; x < FP; ++x) {
+                const int f = lane + x * kWave;
+                v[x] = f < F ? a.V[j * F + f] : 0.0f;
+            }
+            float bh = a.bv[j];
+#pragma unroll
+            for (int y = 0; y < KP; ++y) {
+                const int k = lane + y * kWave;
+                w[y] = k < K ? a.W[j * K + k] : 0.0f;
+                c[y] = k < K ? a.C[j * K + k] : 0.0f;
+            }
+            bool dead = false;  // after one failed wait, later waits are skipped so the kernel ends
+            for (int n = 0; n < len; ++n) {
+                const int sl = n & (kRing - 1);
+                int spins = 0;
+                while (!dead &&
+                       __hip_atomic_load(&rready[sl], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) != n + 1) {
+                    if (++spins > kSpinLimit) {
+                        if (lane == 0) atomicOr(a.err, 4);
+                        dead = true;
+                    }
+                }
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+                const float* d = rdata + sl * RS;
+                float u[FP], rw[KP], cn[KP];
+#pragma unroll
+                for (int x = 0; x < FP; ++x) {
+                    const int f = lane + x * kWave;
+                    u[x] = f < F ? d[f] : 0.0f;
+                }
+#pragma unroll
+                for (int y = 0; y < KP; ++y) {
+                    const int k = lane + y * kWave;
+                    rw[y] = k < K ? d[F + k] : 0.0f;
+                    cn[y] = k < K ? d[F + K + k] : 0.0f;
+                }
+                const int* hd = rhdr + sl * 4;
+                const float reff = __int_as_float(__builtin_amdgcn_readfirstlane(hd[0]));
+                const float bi = __int_as_float(__builtin_amdgcn_readfirstlane(hd[1]));
+                const int64_t i = (int64_t)__builtin_amdgcn_readfirstlane(hd[2]);
+                const uint32_t lw = (uint32_t)__builtin_amdgcn_readfirstlane(hd[3]);
+                // the slot's contents are in registers: hand it back
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+                if (lane == 0) __hip_atomic_store(rcons, n + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                float part = 0.0f;
+#pragma unroll
+                for (int x = 0; x < FP; ++x) part += u[x] * v[x];
+#pragma unroll
+                for (int y = 0; y < KP; ++y) part += rw[y] * w[y] + cn[y] * c[y];
+                const float err = reff - (bh + wave_sum(part));
+                const bool has_succ = (lw >> 31) != 0;
+                const int ws = has_succ ? (int)(lw & 0xFFFFu) : dummy;
+                const float bnew = usr ? bi + a.g[0] * (err - a.l[0] * bi) : bi;
+                float* bsink = a.trash + 2 * kWave * FP;
+                *((lane == 0 && !has_succ) ? a.bu + i : bsink + lane) = bnew;
+                mb_b[lane == 0 ? ws : dummy] = bnew;
+                const float bh_new = bh + a.g[1] * (err - a.l[1] * bh);
+                bh = itm ? bh_new : bh;
+#pragma unroll
+                for (int x = 0; x < FP; ++x) {
+                    const int f = lane + x * kWave;
+                    const float unew = usr ? u[x] + a.g[2] * (err * v[x] - a.l[2] * u[x]) : u[x];
+                    *((!has_succ && f < F) ? a.U + i * F + f : a.trash + kWave * FP + f) = unew;
+                    if constexpr (BF) {
+                        uint16_t* sink = reinterpret_cast<uint16_t*>(a.trash + 3 * kWave * FP) + f;
+                        *((!has_succ && f < F) ? a.U16 + i * F + f : sink) = to_bf16(unew);
+                    }
+                    mb_u[f < F ? ws * F + f : dummy * F] = unew;
+                    const float vn = v[x] + a.g[3] * (err * u[x] - a.l[3] * v[x]);
+                    v[x] = itm ? vn : v[x];
+                }
+#pragma unroll
+                for (int y = 0; y < KP; ++y) {
+                    // an explicit slot has cn == 0; padding slots stay zero either way
+                    const bool rs = cn[y] == 0.0f;
+                    const float wn = w[y] + a.g[4] * (err * rw[y] - a.l[4] * w[y]);
+                    const float cnn = c[y] + a.g[5] * (err * cn[y] - a.l[5] * c[y]);
+                    w[y] = (itm && rs) ? wn : w[y];
+                    c[y] = (itm && !rs) ? cnn : c[y];
+                }
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+                if (lane == 0)
+                    __hip_atomic_store(&mb_seq[ws], (int)((lw >> 16) & 0x3FFFu) + 1, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_WORKGROUP);
+            }
+            __builtin_amdgcn_s_setprio(0);
+#pragma unroll
+            for (int x = 0; x < FP; ++x) {
+                const int f = lane + x * kWave;
+                if (f < F) {
+                    a.V[j * F + f] = v[x];
+                    if constexpr (BF) a.V16[j * F + f] = to_bf16(v[x]);
+                }
+            }
+            if (lane == 0) a.bv[j] = bh;
+#pragma unroll
+            for (int y = 0; y < KP; ++y) {
+                const int k = lane + y * kWave;
+                if (k < K) {
+                    a.W[j * K + k] = w[y];
+                    a.C[j * K + k] = c[y];
+                    if constexpr (BF) {
+                        a.W16[j * K + k] = to_bf16(w[y]);
+                        a.C16[j * K + k] = to_bf16(c[y]);
+                    }
+                }
+            }
+        } else {
+            // ---- helper wave h: ratings n = h, h + H, ... of the segment
+            const int h = role - 1;
+            const int mcount = h < len ? (len - h + kHelpers - 1) / kHelpers : 0;
+            bool dead = false;  // after one failed wait, later waits are skipped so the kernel ends
+            float bhn[KP];
+#pragma unroll
+            for (int y = 0; y < KP; ++y) {
+                const int k = lane + y * kWave;
+                bhn[y] = k < K ? a.nbr_b0[j * K + k] : 0.0f;
+            }
+            // HBM loads of kHG ratings (t0.. of the current word batch); no waits
+            auto hstage = [&](HStage<FP, KP>& S, uint32_t pkv, uint32_t lkv, int mb, int t0, int nbw) {
+#pragma unroll
+                for (int t = 0; t < kHG; ++t) {
+                    const int tt = t0 + t;
+                    const bool valid = tt < nbw;
+                    const uint32_t pw = (uint32_t)__builtin_amdgcn_readlane((int)pkv, tt & 63);
+                    const uint32_t lw = (uint32_t)__builtin_amdgcn_readlane((int)lkv, tt & 63);
+                    S.pw[t] = pw;
+                    S.lw[t] = lw;
+                    const int64_t i = valid ? (int64_t)(pw >> 4) : 0;
+                    const int64_t pos = valid ? ea + h + (int64_t)kHelpers * (mb + tt) : ea;
+#pragma unroll
+                    for (int x = 0; x < FP; ++x) {
+                        const int f = lane + x * kWave;
+                        S.u[t][x] = *(f < F ? a.U + i * F + f : a.trash + lane);
+                    }
+                    S.bi[t] = a.bu[i];
+                    S.b0[t] = a.b0[i];
+                    const uint8_t* nbp = a.nib + pos * a.nstride;
+#pragma unroll
+                    for (int y = 0; y < KP; ++y) {
+                        const int byte = (lane >> 1) + y * (kWave / 2);
+                        S.nb[t][y] = nbp[byte < a.nstride ? byte : 0];
+                    }
+                }
+            };
+            // user-side inputs of each staged rating into the ring, in order
+            auto hprep = [&](HStage<FP, KP>& S, int mb, int t0, int nbw) {
+#pragma unroll
+                for (int t = 0; t < kHG; ++t) {
+                    const int tt = t0 + t;
+                    if (tt >= nbw) break;
+                    const int n = h + kHelpers * (mb + tt);
+                    const int sl = n & (kRing - 1);
+                    const uint32_t pw = S.pw[t], lw = S.lw[t];
+                    // the ring slot is free once the item wave took rating n - kRing
+                    int spins = 0;
+                    while (!dead &&
+                           __hip_atomic_load(rcons, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) < n - kRing + 1) {
+                        if (++spins > kSpinLimit) {
+                            if (lane == 0) atomicOr(a.err, 4);
+                            dead = true;
+                        }
+                        __builtin_amdgcn_s_sleep(1);
+                    }
+                    // an earlier rating of the user in this block hands its row over
+                    const bool has_pred = ((lw >> 30) & 1u) != 0;
+                    const int pslot = has_pred ? (int)(lw & 0xFFFFu) : dummy;
+                    if (has_pred) {
+                        const int want = (int)((lw >> 16) & 0x3FFFu);
+                        spins = 0;
+                        while (!dead && __hip_atomic_load(&mb_seq[pslot], __ATOMIC_RELAXED,
+                                                          __HIP_MEMORY_SCOPE_WORKGROUP) != want) {
+                            if (++spins > kSpinLimit) {
+                                if (lane == 0) atomicOr(a.err, 2);
+                                dead = true;
+                            }
+                            __builtin_amdgcn_s_sleep(1);
+                        }
+                    }
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+                    float u[FP];
+#pragma unroll
+                    for (int x = 0; x < FP; ++x) {
+                        const int f = lane + x * kWave;
+                        const float mv = mb_u[f < F ? pslot * F + f : dummy * F];
+                        u[x] = f < F ? (has_pred ? mv : S.u[t][x]) : 0.0f;
+                    }
+                    const float bi = has_pred ? mb_b[pslot] : S.bi[t];
+                    const float base_i = mu + S.b0[t];
+                    int code[KP];
+                    int nR = 0;
+#pragma unroll
+                    for (int y = 0; y < KP; ++y) {
+                        const int k = lane + y * kWave;
+                        code[y] = k < K ? (int)((S.nb[t][y] >> ((lane & 1) * 4)) & 15u) : 0;
+                        nR += __popcll(__ballot(code[y] != 0));
+                    }
+                    const float sR = nR > 0 ? __builtin_amdgcn_rsqf((float)nR) : 0.0f;
+                    const float sN = K - nR > 0 ? __builtin_amdgcn_rsqf((float)(K - nR)) : 0.0f;
+                    float* d = rdata + sl * RS;
+#pragma unroll
+                    for (int x = 0; x < FP; ++x) {
+                        const int f = lane + x * kWave;
+                        if (f < F) d[f] = u[x];
+                    }
+#pragma unroll
+                    for (int y = 0; y < KP; ++y) {
+                        const int k = lane + y * kWave;
+                        const float resid = (float)code[y] * inv_s - base_i - bhn[y];
+                        if (k < K) {
+                            d[F + k] = code[y] ? resid * sR : 0.0f;
+                            d[F + K + k] = code[y] ? 0.0f : sN;
+                        }
+                    }
+                    const float r = (float)(pw & 15u) * inv_s;
+                    if (lane == 0) {
+                        int* hd = rhdr + sl * 4;
+                        hd[0] = __float_as_int(r - (mu + bi));
+                        hd[1] = __float_as_int(bi);
+                        hd[2] = (int)(pw >> 4);
+                        hd[3] = (int)lw;
+                    }
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+                    if (lane == 0) __hip_atomic_store(&rready[sl], n + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                }
+            };
+            HStage<FP, KP> SA, SB;
+            for (int mb = 0; mb < mcount; mb += kWave) {
+                const int nbw = mcount - mb < kWave ? mcount - mb : kWave;
+                uint32_t pkv = 0u, lkv = 0u;
+                if (lane < nbw) {
+                    const int64_t pos = ea + h + (int64_t)kHelpers * (mb + lane);
+                    pkv = pk[pos];
+                    lkv = link[pos];
+                }
+                hstage(SA, pkv, lkv, mb, 0, nbw);
+                for (int t0 = 0;; t0 += 2 * kHG) {
+                    hstage(SB, pkv, lkv, mb, t0 + kHG, nbw);
+                    hprep(SA, mb, t0, nbw);
+                    if (t0 + kHG >= nbw) break;
+                    hstage(SA, pkv, lkv, mb, t0 + 2 * kHG, nbw);
+                    hprep(SB, mb, t0 + kHG, nbw);
+                    if (t0 + 2 * kHG >= nbw) break;
+                }
+            }
+        }
+    }
 
     while (true) {
         int g = 0;
@@ -364,10 +664,18 @@ int refresh_bf16(lshmf_ctx* c, int64_t m0, int64_t m1, int64_t n0, int64_t n1, h
     return to_bf16_rows(c->t.C + n0 * K, c->t.C16 + n0 * K, (n1 - n0) * K, s);
 }
 
+// Dynamic LDS of one block: the mailbox (slots + 1 rows of F floats, b_i and
+// a sequence word) and the gang rings.
+static size_t sgd_lds_bytes(const SgdArgs& args)
+{
+    const size_t gs = (size_t)kRing * args.ring_rs + kRing * 4 + kRing + 4;
+    return ((size_t)args.ring_off + (size_t)args.max_gangs * gs) * sizeof(float);
+}
+
 template <int FP, int KP, bool BF>
 static int launch_sgd(const SgdArgs& args, const uint32_t* pk, const uint32_t* link, hipStream_t s)
 {
-    const size_t lds = (size_t)(args.slots + 1) * (args.F + 2) * sizeof(float);
+    const size_t lds = sgd_lds_bytes(args);
     if (lds > 64 * 1024) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sgd_stratum<FP, KP, BF>),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -427,6 +735,11 @@ int run_sgd(lshmf_ctx* c, Stream& st, const lshmf_hparams* hp, int epoch, int up
     a.slots = (int)st.max_block_slots;
     a.upd = upd;
     a.inv_s = 1.0f / (float)d.rscale;
+    // gangs only where their rings fit beside the mailbox
+    a.ring_off = (int)(((st.max_block_slots + 1) * (d.F + 2) + 3) & ~3LL);
+    a.ring_rs = d.F + 2 * d.K;
+    a.max_gangs = kMaxGangs;
+    while (a.max_gangs > 0 && sgd_lds_bytes(a) > (size_t)kMaxLdsBytes) --a.max_gangs;
     // Eq. (learn_rate): gamma_t = alpha / (1 + beta * t^1.5)
     const double den = 1.0 + (double)hp->beta * std::pow((double)epoch, 1.5);
     for (int x = 0; x < 6; ++x) {

@@ -12,6 +12,7 @@ import os
 import threading
 from typing import Optional, Sequence
 
+import numpy as np
 import torch
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -57,6 +58,23 @@ class Layout(C.Structure):
                 ("nnz", C.c_int64)]
 
 
+REQ_UPDATE, REQ_QUERY = 0, 1
+
+# lshmf_request, as a numpy record type
+REQUEST_DTYPE = np.dtype([("kind", "<i4"), ("M_new", "<i4"), ("N_new", "<i4"), ("reserved", "<i4"),
+                          ("offset", "<i8"), ("n", "<i8"), ("arrival", "<f8")], align=True)
+
+
+class ServeIO(C.Structure):
+    _fields_ = [("req", C.c_void_p), ("n_req", C.c_int64),
+                ("h_u", C.c_void_p), ("h_i", C.c_void_p), ("h_rc", C.c_void_p),
+                ("h_qu", C.c_void_p), ("h_qi", C.c_void_p), ("h_pred", C.c_void_p),
+                ("d_U0", C.c_void_p), ("d_V0", C.c_void_p), ("d_H", C.c_void_p),
+                ("seed_fill", C.c_uint64), ("hp", HParams), ("epoch", C.c_int32), ("passes", C.c_int32),
+                ("max_query_batch", C.c_int64), ("d_stage", C.c_void_p), ("stage_bytes", C.c_size_t),
+                ("h_start", C.c_void_p), ("h_done", C.c_void_p), ("h_status", C.c_void_p)]
+
+
 _lock = threading.Lock()
 _lib = None
 
@@ -85,6 +103,8 @@ def lib():
             L.lshmf_rmse.argtypes = [vp, vp, vp, i64, vp, vp]
             L.lshmf_export_layout.argtypes = [vp, C.POINTER(Layout)]
             L.lshmf_sync_storage.argtypes = [vp, vp]
+            L.lshmf_serve_stage_bytes.argtypes = [vp, i64, C.POINTER(C.c_size_t)]
+            L.lshmf_serve.argtypes = [vp, C.POINTER(ServeIO), vp, vp]
             L.lshmf_last_error.restype = C.c_char_p
             L.lshmf_last_error.argtypes = []
             _lib = L
@@ -231,6 +251,40 @@ class LshMF:
     def sync_storage(self):
         """BF16 mode: rewrite the BF16 copies from the FP32 masters."""
         _check(lib().lshmf_sync_storage(self._h, _stream(self.device)))
+
+    def serve(self, req: np.ndarray, upd, qry, U0: torch.Tensor, V0: torch.Tensor, H: torch.Tensor,
+              seed_fill: int, alpha, lam, beta: float, epoch: int, passes: int = 1,
+              max_query_batch: int = 65536):
+        """Runs the serving loop over a request log (REQUEST_DTYPE records).
+
+        upd = (u, i, rc) and qry = (qu, qi): host tensors (pinned for overlap)
+        holding every request's payload at its offset; U0 / V0: device tables
+        of initial rows for new ids.  Returns (answers, start, done, status)."""
+        req = np.ascontiguousarray(req, REQUEST_DTYPE)
+        n_req = req.size
+        u, i, rc = upd
+        qu, qi = qry
+        pred = torch.zeros(max(qu.numel(), 1), dtype=torch.float32, pin_memory=True)
+        start = np.zeros(n_req, np.float64)
+        done = np.zeros(n_req, np.float64)
+        status = np.zeros(n_req, np.int32)
+        nbytes = C.c_size_t()
+        _check(lib().lshmf_serve_stage_bytes(self._h, max_query_batch, C.byref(nbytes)))
+        stage = torch.empty(int(nbytes.value) + 256, dtype=torch.uint8, device=self.device)
+        sp = stage.data_ptr() + (-stage.data_ptr()) % 256
+        hp = HParams((C.c_float * 6)(*alpha), (C.c_float * 6)(*lam), beta, 0)
+        io = ServeIO(req.ctypes.data, n_req, u.data_ptr(), i.data_ptr(), rc.data_ptr(),
+                     qu.data_ptr(), qi.data_ptr(), pred.data_ptr(), U0.data_ptr(), V0.data_ptr(),
+                     H.data_ptr(), seed_fill & (2**64 - 1), hp, epoch, passes, max_query_batch, sp,
+                     int(nbytes.value), start.ctypes.data, done.ctypes.data, status.ctypes.data)
+        torch.cuda.synchronize(self.device)
+        cs = torch.cuda.Stream(self.device)
+        ps = torch.cuda.Stream(self.device)
+        _check(lib().lshmf_serve(self._h, C.byref(io), C.c_void_p(cs.cuda_stream),
+                                 C.c_void_p(ps.cuda_stream)))
+        torch.cuda.synchronize(self.device)
+        del stage
+        return pred[: qu.numel()], start, done, status
 
     def predict(self, u: torch.Tensor, i: torch.Tensor, out: Optional[torch.Tensor] = None):
         assert u.dtype == torch.int32 and i.dtype == torch.int32

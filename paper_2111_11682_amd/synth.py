@@ -316,3 +316,61 @@ def random_queries(M: int, N: int, n: int, seed: int) -> Tuple[np.ndarray, np.nd
     """Uniform (user, item) query pairs for predict."""
     rng = _rng(seed, 11)
     return (rng.integers(0, M, n).astype(np.int32), rng.integers(0, N, n).astype(np.int32))
+
+
+REQUEST_FIELDS = [("kind", "<i4"), ("M_new", "<i4"), ("N_new", "<i4"), ("reserved", "<i4"),
+                  ("offset", "<i8"), ("n", "<i8"), ("arrival", "<f8")]
+
+
+def serve_log(sp: Dict[str, np.ndarray], M: int, N: int, upd_lo: int, upd_hi: int,
+              q_lo: int, q_hi: int, queries_per_update: int = 4, seed: int = MASTER_SEED
+              ) -> Dict[str, np.ndarray]:
+    """A request log for the serving loop over the stream part of an online split.
+
+    The stream is reordered so that new users and items arrive progressively
+    (a rating of a new id is placed by its id's rank among the new ids,
+    existing x existing ratings at random), then cut into update batches of
+    log-uniform sizes in [upd_lo, upd_hi].  Each update is followed by
+    `queries_per_update` query requests of log-uniform sizes in [q_lo, q_hi],
+    uniform over the users and items known at that point.  Arrival times are
+    left at zero (set them for an offered load).  Returns req (records with
+    REQUEST_FIELDS), upd_u/upd_i/upd_rc and q_u/q_i (payloads in request order).
+    """
+    rng = _rng(seed, 31)
+    su, si, src = sp["stream_u"], sp["stream_i"], sp["stream_rc"]
+    M0, N0 = int(sp["M_old"]), int(sp["N_old"])
+    gu = np.where(su >= M0, (su - M0 + 1) / max(M - M0, 1), 0.0)
+    gi = np.where(si >= N0, (si - N0 + 1) / max(N - N0, 1), 0.0)
+    key = np.maximum(gu, gi)
+    old = key == 0
+    key[old] = rng.random(int(old.sum()))
+    order = np.argsort(key, kind="stable")
+    su, si, src = su[order], si[order], src[order]
+    recs, qus, qis = [], [], []
+    at, qat = 0, 0
+    Mc, Nc = M0, N0
+    lo, hi = np.log(upd_lo), np.log(upd_hi)
+    while at < su.size:
+        n = int(np.exp(rng.uniform(lo, hi)))
+        n = min(max(n, 1), su.size - at)
+        Mc = max(Mc, int(su[at:at + n].max()) + 1)
+        Nc = max(Nc, int(si[at:at + n].max()) + 1)
+        recs.append((0, Mc, Nc, 0, at, n, 0.0))
+        at += n
+        for _ in range(queries_per_update):
+            m = int(np.exp(rng.uniform(np.log(q_lo), np.log(q_hi))))
+            qus.append(rng.integers(0, Mc, m).astype(np.int32))
+            qis.append(rng.integers(0, Nc, m).astype(np.int32))
+            recs.append((1, 0, 0, 0, qat, m, 0.0))
+            qat += m
+    req = np.array(recs, dtype=np.dtype(REQUEST_FIELDS, align=True))
+    return {"req": req, "upd_u": su.astype(np.int32), "upd_i": si.astype(np.int32),
+            "upd_rc": src.astype(np.uint8),
+            "q_u": np.concatenate(qus) if qus else np.zeros(0, np.int32),
+            "q_i": np.concatenate(qis) if qis else np.zeros(0, np.int32)}
+
+
+def poisson_arrivals(n: int, rate: float, seed: int = MASTER_SEED) -> np.ndarray:
+    """Arrival times (s) of a Poisson process of the given rate (requests / s)."""
+    rng = _rng(seed, 41)
+    return np.cumsum(rng.exponential(1.0 / rate, n))
