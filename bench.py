@@ -93,6 +93,79 @@ def cpu_baseline(w, d, P, epochs=2):
                       "of a stratum) over all %d training ratings, %.1f s" % (epochs, P, u.size, dt)}
 
 
+def serve_main(args, w, d):
+    """Serving loop on the online split of the same workload: pre-train on
+    80%, stream the rest as update batches (log-uniform 1k-1M ratings) mixed
+    1:4 with query requests (log-uniform 1-10k pairs); Poisson arrivals at
+    0.3, 0.6 and 0.9 of the capacity measured back to back."""
+    import numpy as np
+    import torch
+    from paper_2111_11682_amd import lshmf, synth
+
+    sp = synth.online_split(w, d, frac_new=0.01, stream_frac=0.2)
+    L = synth.serve_log(sp, w.M, w.N, 1000, 1000000, 1, 10000)
+    req = L["req"]
+    M0, N0 = int(sp["M_old"]), int(sp["N_old"])
+    dev = torch.device("cuda:0")
+    pin = lambda a: torch.from_numpy(a).pin_memory()
+    upd = (pin(L["upd_u"]), pin(L["upd_i"]), pin(L["upd_rc"]))
+    qry = (pin(L["q_u"]), pin(L["q_i"]))
+    U0 = torch.from_numpy(d["U0"]).to(dev)
+    V0 = torch.from_numpy(d["V0"]).to(dev)
+    H = torch.from_numpy(d["H"].view(np.int32)).to(dev)
+    pre = [torch.from_numpy(sp[k]).to(dev) for k in ("pretrain_u", "pretrain_i", "pretrain_rc")]
+    batch_cap = int(req["n"][req["kind"] == 0].max())
+    log("serve: %d requests (%d updates, %d update ratings, %d query pairs), batch_cap %d" %
+        (req.size, int((req["kind"] == 0).sum()), L["upd_u"].size, L["q_u"].size, batch_cap))
+
+    def run(arrival):
+        m = lshmf.LshMF(M0, N0, w.F, w.K, w.G, w.p, w.q, w.rscale, pre[0].numel(), n_strata=w.n_strata,
+                        device=dev, M_cap=w.M, N_cap=w.N, nnz_cap=d["train_u"].size,
+                        batch_cap=batch_cap, storage=args.storage)
+        m.ingest(*pre)
+        m.set_factors(U0[:M0], V0[:N0])
+        m.build_lsh_neighbours(H, 12345)
+        for t in range(w.epochs):
+            m.sgd_epoch(w.alpha, w.lam, w.beta, t)
+        torch.cuda.synchronize()
+        r = req.copy()
+        r["arrival"] = arrival
+        _, start, done, status = m.serve(r, upd, qry, U0, V0, H, 12345, w.alpha, w.lam, w.beta, w.epochs, 1,
+                                         max_query_batch=65536)
+        assert m.device_status() == 0
+        m.close()
+        return start, done, status
+
+    def summary(arrival, start, done, status):
+        out = {}
+        for kind, name in ((1, "query"), (0, "update")):
+            sel = (req["kind"] == kind) & (status == 0)
+            lat = (done - arrival)[sel] * 1e3
+            out[name + "_p50_ms"] = round(float(np.percentile(lat, 50)), 3)
+            out[name + "_p99_ms"] = round(float(np.percentile(lat, 99)), 3)
+        out["refused"] = int((status != 0).sum())
+        return out
+
+    zero = np.zeros(req.size)
+    start, done, status = run(zero)
+    makespan = float(done.max())
+    capacity = req.size / makespan
+    log("back to back: %.3f s for %d requests (%.1f requests/s)" % (makespan, req.size, capacity))
+    loads = {"back_to_back": dict(summary(zero, start, done, status), makespan_s=round(makespan, 4))}
+    for rho in (0.3, 0.6, 0.9):
+        arr = synth.poisson_arrivals(req.size, rho * capacity)
+        start, done, status = run(arr)
+        loads["load_%.1f" % rho] = summary(arr, start, done, status)
+        log("load %.1f: %s" % (rho, loads["load_%.1f" % rho]))
+    out = {"metric": "serving query latency p99 at 0.6 of capacity", "value": loads["load_0.6"]["query_p99_ms"],
+           "unit": "ms", "n_gpus": 1, "higher_is_better": False, "vs_baseline": None, "dtype": "f32",
+           "data": "synthetic (MovieLens-10M shape, 1% new users and items, 20% of ratings streamed)",
+           "config": {"workload": "ml10m-shaped online stream", "requests": int(req.size),
+                      "update_ratings": int(L["upd_u"].size), "query_pairs": int(L["q_u"].size),
+                      "capacity_requests_per_s": round(capacity, 2), "storage": args.storage, "loads": loads}}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -101,6 +174,8 @@ def main():
     ap.add_argument("--workload", default="ml10m")
     ap.add_argument("--epochs", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--mode", choices=("train", "serve"), default="train",
+                    help="serve: the serving loop over an online stream instead of the training job")
     ap.add_argument("--storage", choices=("fp32", "bf16"), default="fp32",
                     help="bf16: BF16 copies of U, V, W, C beside the FP32 masters")
     ap.add_argument("--calib-copy", action="store_true",
@@ -124,6 +199,9 @@ def main():
         (w.name, d["train_u"].size, d["test_u"].size, time.time() - t0))
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.mode == "serve":
+        serve_main(args, w, d)
+        return
     g = {k: torch.from_numpy(v).to(dev) for k, v in d.items() if k != "H"}
     H = torch.from_numpy(d["H"].view(np.int32)).to(dev)
     nnz = d["train_u"].size

@@ -83,3 +83,30 @@ def test_binding_has_no_cpu_fallback(monkeypatch):
     monkeypatch.setattr(lshmf, "LIB_PATH", os.path.join(os.path.dirname(lshmf.LIB_PATH), "missing.so"))
     with pytest.raises(ImportError):
         lshmf.lib()
+
+
+def test_serve_entry_checks_on_host():
+    st, h = _create(batch_cap=1000)
+    assert st == 0
+    n = C.c_size_t()
+    assert lshmf.lib().lshmf_serve_stage_bytes(h, 4096, C.byref(n)) == 0
+    assert n.value >= 1000 * 9 + 2 * 3 * 4096 * 4
+    assert lshmf.lib().lshmf_serve_stage_bytes(h, 0, C.byref(n)) == -1
+    io = lshmf.ServeIO()
+    # before the neighbours exist the loop refuses to start, without touching the device
+    assert lshmf.lib().lshmf_serve(h, C.byref(io), C.c_void_p(1), C.c_void_p(2)) == -2
+    lshmf.lib().lshmf_destroy(h)
+
+
+def test_request_record_layout():
+    import numpy as np
+    from paper_2111_11682_amd import synth
+
+    class Req(C.Structure):
+        _fields_ = [("kind", C.c_int32), ("M_new", C.c_int32), ("N_new", C.c_int32),
+                    ("reserved", C.c_int32), ("offset", C.c_int64), ("n", C.c_int64),
+                    ("arrival", C.c_double)]
+    assert lshmf.REQUEST_DTYPE.itemsize == C.sizeof(Req) == 40
+    assert np.dtype(synth.REQUEST_FIELDS, align=True) == lshmf.REQUEST_DTYPE
+    for name, _ in Req._fields_:
+        assert lshmf.REQUEST_DTYPE.fields[name][1] == getattr(Req, name).offset

@@ -480,7 +480,7 @@ def test_online_phases_freeze_sides():
     # phase A only: new users on existing items -> item side untouched
     a = (bu_ >= m.M) & (bi_ < m.N)
     m2, _, _ = orc.online_update(m, acc, sig, w.B, w.G, w.p, w.q, 9, bu_[a], bi_[a], brc[a], d["H"],
-                                 d["U0"][m.M:m.M + 0] if False else d["U0"][m.M:int(bu_[a].max()) + 1],
+                                 d["U0"][m.M:int(bu_[a].max()) + 1],
                                  d["V0"][m.N:m.N], w.n_strata, w.alpha, w.lam, w.beta, 1)
     assert m2.N == m.N
     for k in ("V", "bv", "W", "C"):
@@ -498,6 +498,22 @@ def test_online_phases_freeze_sides():
     assert np.array_equal(m3.U[m.M:], np.asarray(d["U0"][m.M:M2], np.float64))
     for k in ("V", "bv", "W", "C"):
         assert np.array_equal(getattr(m3, k)[: m.N], getattr(m, k)), k
+
+
+def test_online_new_id_baselines_hand_computed():
+    # one new user rating 4 and 5 on existing items, one new item rated 2 and 3
+    # by existing users: b0 = 4.5 - mu, bh0 = 2.5 - mu; the existing ones stay
+    w, d, sp, m, acc, sig, _ = _online_setup()
+    u = np.array([m.M, m.M, 0, 1], np.int32)
+    it = np.array([0, 1, m.N, m.N], np.int32)
+    rc = np.array([4, 5, 2, 3], np.uint8) * w.rscale
+    m2, _, _ = orc.online_update(m, acc, sig, w.B, w.G, w.p, w.q, 9, u, it, rc, d["H"],
+                                 d["U0"][m.M:m.M + 1], d["V0"][m.N:m.N + 1], w.n_strata, w.alpha,
+                                 w.lam, w.beta, 1)
+    assert m2.mu == m.mu
+    assert m2.b0[m.M] == pytest.approx(4.5 - m.mu, abs=1e-12)
+    assert m2.bh0[m.N] == pytest.approx(2.5 - m.mu, abs=1e-12)
+    assert np.array_equal(m2.b0[: m.M], m.b0) and np.array_equal(m2.bh0[: m.N], m.bh0)
 
 
 def test_online_empty_batch_is_identity():
