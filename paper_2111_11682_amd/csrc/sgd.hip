@@ -23,7 +23,8 @@ constexpr int kHelpers = 3;                      // helper waves of a gang
 constexpr int kGangWaves = kHelpers + 1;
 constexpr int kMaxGangs = 1;                     // gangs per block
 constexpr int kGangMin = 48;                     // shortest segment given a gang
-constexpr int kRing = 32;                        // ring slots of a gang (power of two)
+constexpr int kRing = 11 * kHelpers;              // ring slots of a gang (a multiple of kHelpers)
+constexpr int kIG = 8;                           // ratings per item-wave group
 constexpr int kHG = 4;                           // ratings per helper pipeline stage
 constexpr int kSpinLimit = 1 << 24;              // bounded wait: a broken hand-over ends the kernel
 constexpr int kMaxMailboxBytes = 150 * 1024;     // mailbox part of a block's dynamic LDS
@@ -143,12 +144,12 @@ __global__ __launch_bounds__(kSgdWaves* kWave) void k_sgd_stratum(SgdArgs a, con
         ngang = k + 1;
     }
     const int RS = a.ring_rs;
-    const int GS = kRing * RS + kRing * 4 + kRing + 4;  // floats per gang: data, headers, ready, consumed
+    const int GS = kRing * (RS + 7);  // floats per gang: data, headers, ready, done, err
     float* rings = smem + a.ring_off;
     for (int x = threadIdx.x; x <= dummy; x += blockDim.x) mb_seq[x] = 0;
     for (int gi = 0; gi < ngang; ++gi) {
         int* ready = reinterpret_cast<int*>(rings + (size_t)gi * GS + kRing * RS + kRing * 4);
-        for (int x = threadIdx.x; x <= kRing; x += blockDim.x) ready[x] = 0;  // ready[] and consumed
+        for (int x = threadIdx.x; x < 2 * kRing; x += blockDim.x) ready[x] = 0;  // ready[] and done[]
     }
     if (threadIdx.x == 0) next_seg = ngang;
     __syncthreads();
@@ -156,9 +157,18 @@ __global__ __launch_bounds__(kSgdWaves* kWave) void k_sgd_stratum(SgdArgs a, con
     const float inv_s = a.inv_s;
     const bool usr = (a.upd & 1) != 0;
     const bool itm = (a.upd & 2) != 0;
-    const int wv = threadIdx.x / kWave;
+    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));  // wave-uniform
 
     if (wv < ngang * kGangWaves) {
+        // Ring protocol.  Helper h prepares ratings n = h, h + H, ... into
+        // slot n % kRing and sets ready; the item wave runs each group of kIG
+        // ratings, writes u_i's new row into the slot and the error beside it,
+        // then sets done for the group; helper h finishes its ratings (b_i, the
+        // user's row to HBM or to the mailbox) after preparing its next group.
+        // A slot is reused by the same helper kRing / H of its ratings later,
+        // after it finished the slot's previous rating.  The item wave waits
+        // only after publishing all it has done, and a helper waits only for
+        // ratings below those it has prepared, so every wait ends.
         const int gang = wv / kGangWaves, role = wv % kGangWaves;
         const int64_t seg = g0 + gang;
         const int64_t j = a.seg_col[seg];
@@ -167,7 +177,8 @@ __global__ __launch_bounds__(kSgdWaves* kWave) void k_sgd_stratum(SgdArgs a, con
         float* rdata = rings + (size_t)gang * GS;
         int* rhdr = reinterpret_cast<int*>(rdata + kRing * RS);
         int* rready = rhdr + kRing * 4;
-        int* rcons = rready + kRing;
+        int* rdone = rready + kRing;
+        float* rerr = reinterpret_cast<float*>(rdone + kRing);
         if (role == 0) {
             // ---- item wave: Eq. (rr) and Eq. (sgd_update) in stream order
             __builtin_amdgcn_s_setprio(3);
@@ -185,78 +196,114 @@ __global__ __launch_bounds__(kSgdWaves* kWave) void k_sgd_stratum(SgdArgs a, con
                 c[y] = k < K ? a.C[j * K + k] : 0.0f;
             }
             bool dead = false;  // after one failed wait, later waits are skipped so the kernel ends
-            for (int n = 0; n < len; ++n) {
-                const int sl = n & (kRing - 1);
+            // lane t < cnt checks slot (g0 + t): are all kIG inputs of the group there?
+            auto group_ready = [&](int gs, int cnt) {
+                const int sl = (gs + lane) % kRing;
+                const int want = gs + lane + 1;
+                const bool ok = lane >= cnt ||
+                                __hip_atomic_load(&rready[sl], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) == want;
+                return __ballot(!ok) == 0ull;
+            };
+            auto wait_group = [&](int gs, int cnt) {
                 int spins = 0;
-                while (!dead &&
-                       __hip_atomic_load(&rready[sl], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) != n + 1) {
+                while (!dead && !group_ready(gs, cnt)) {
                     if (++spins > kSpinLimit) {
                         if (lane == 0) atomicOr(a.err, 4);
                         dead = true;
                     }
                 }
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
-                const float* d = rdata + sl * RS;
-                float u[FP], rw[KP], cn[KP];
+            };
+            float pu[kIG][FP], prw[kIG][KP], pcn[kIG][KP];
+            float preff = 0.0f;  // lane t: r - mu - b_i of rating gs + t
+            auto load_group = [&](int gs, int cnt) {
 #pragma unroll
-                for (int x = 0; x < FP; ++x) {
-                    const int f = lane + x * kWave;
-                    u[x] = f < F ? d[f] : 0.0f;
-                }
+                for (int t = 0; t < kIG; ++t) {
+                    const float* d = rdata + ((gs + t) % kRing) * RS;
 #pragma unroll
-                for (int y = 0; y < KP; ++y) {
-                    const int k = lane + y * kWave;
-                    rw[y] = k < K ? d[F + k] : 0.0f;
-                    cn[y] = k < K ? d[F + K + k] : 0.0f;
-                }
-                const int* hd = rhdr + sl * 4;
-                const float reff = __int_as_float(__builtin_amdgcn_readfirstlane(hd[0]));
-                const float bi = __int_as_float(__builtin_amdgcn_readfirstlane(hd[1]));
-                const int64_t i = (int64_t)__builtin_amdgcn_readfirstlane(hd[2]);
-                const uint32_t lw = (uint32_t)__builtin_amdgcn_readfirstlane(hd[3]);
-                // the slot's contents are in registers: hand it back
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
-                if (lane == 0) __hip_atomic_store(rcons, n + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                float part = 0.0f;
-#pragma unroll
-                for (int x = 0; x < FP; ++x) part += u[x] * v[x];
-#pragma unroll
-                for (int y = 0; y < KP; ++y) part += rw[y] * w[y] + cn[y] * c[y];
-                const float err = reff - (bh + wave_sum(part));
-                const bool has_succ = (lw >> 31) != 0;
-                const int ws = has_succ ? (int)(lw & 0xFFFFu) : dummy;
-                const float bnew = usr ? bi + a.g[0] * (err - a.l[0] * bi) : bi;
-                float* bsink = a.trash + 2 * kWave * FP;
-                *((lane == 0 && !has_succ) ? a.bu + i : bsink + lane) = bnew;
-                mb_b[lane == 0 ? ws : dummy] = bnew;
-                const float bh_new = bh + a.g[1] * (err - a.l[1] * bh);
-                bh = itm ? bh_new : bh;
-#pragma unroll
-                for (int x = 0; x < FP; ++x) {
-                    const int f = lane + x * kWave;
-                    const float unew = usr ? u[x] + a.g[2] * (err * v[x] - a.l[2] * u[x]) : u[x];
-                    *((!has_succ && f < F) ? a.U + i * F + f : a.trash + kWave * FP + f) = unew;
-                    if constexpr (BF) {
-                        uint16_t* sink = reinterpret_cast<uint16_t*>(a.trash + 3 * kWave * FP) + f;
-                        *((!has_succ && f < F) ? a.U16 + i * F + f : sink) = to_bf16(unew);
+                    for (int x = 0; x < FP; ++x) {
+                        const int f = lane + x * kWave;
+                        pu[t][x] = f < F ? d[f] : 0.0f;
                     }
-                    mb_u[f < F ? ws * F + f : dummy * F] = unew;
-                    const float vn = v[x] + a.g[3] * (err * u[x] - a.l[3] * v[x]);
-                    v[x] = itm ? vn : v[x];
-                }
 #pragma unroll
-                for (int y = 0; y < KP; ++y) {
-                    // an explicit slot has cn == 0; padding slots stay zero either way
-                    const bool rs = cn[y] == 0.0f;
-                    const float wn = w[y] + a.g[4] * (err * rw[y] - a.l[4] * w[y]);
-                    const float cnn = c[y] + a.g[5] * (err * cn[y] - a.l[5] * c[y]);
-                    w[y] = (itm && rs) ? wn : w[y];
-                    c[y] = (itm && !rs) ? cnn : c[y];
+                    for (int y = 0; y < KP; ++y) {
+                        const int k = lane + y * kWave;
+                        prw[t][y] = k < K ? d[F + k] : 0.0f;
+                        pcn[t][y] = k < K ? d[F + K + k] : 0.0f;
+                    }
                 }
+                preff = __int_as_float(rhdr[((gs + (lane < cnt ? lane : 0)) % kRing) * 4]);
+            };
+            wait_group(0, len < kIG ? len : kIG);
+            load_group(0, len < kIG ? len : kIG);
+            for (int gs = 0; gs < len; gs += kIG) {
+                const int cnt = len - gs < kIG ? len - gs : kIG;
+                float u[kIG][FP], rw[kIG][KP], cn[kIG][KP];
+#pragma unroll
+                for (int t = 0; t < kIG; ++t) {
+#pragma unroll
+                    for (int x = 0; x < FP; ++x) u[t][x] = pu[t][x];
+#pragma unroll
+                    for (int y = 0; y < KP; ++y) {
+                        rw[t][y] = prw[t][y];
+                        cn[t][y] = pcn[t][y];
+                    }
+                }
+                const float reff_v = preff;
+                // the next group's inputs, if they are already there
+                const int gn = gs + kIG;
+                const int cntn = len - gn < kIG ? len - gn : kIG;
+                bool have_next = false;
+                if (gn < len && group_ready(gn, cntn)) {
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+                    load_group(gn, cntn);
+                    have_next = true;
+                }
+                float errv = 0.0f;  // lane t: error of rating gs + t
+#pragma unroll
+                for (int t = 0; t < kIG; ++t) {
+                    if (t >= cnt) break;
+                    const int sl = (gs + t) % kRing;
+                    const float reff = __builtin_bit_cast(
+                        float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, reff_v), t));
+                    float part = 0.0f;
+#pragma unroll
+                    for (int x = 0; x < FP; ++x) part += u[t][x] * v[x];
+#pragma unroll
+                    for (int y = 0; y < KP; ++y) part += rw[t][y] * w[y] + cn[t][y] * c[y];
+                    const float err = reff - (bh + wave_sum(part));
+                    errv = lane == t ? err : errv;
+                    float* d = rdata + sl * RS;
+#pragma unroll
+                    for (int x = 0; x < FP; ++x) {
+                        const int f = lane + x * kWave;
+                        const float unew = usr ? u[t][x] + a.g[2] * (err * v[x] - a.l[2] * u[t][x]) : u[t][x];
+                        if (f < F) d[f] = unew;
+                        const float vn = v[x] + a.g[3] * (err * u[t][x] - a.l[3] * v[x]);
+                        v[x] = itm ? vn : v[x];
+                    }
+                    const float bh_new = bh + a.g[1] * (err - a.l[1] * bh);
+                    bh = itm ? bh_new : bh;
+#pragma unroll
+                    for (int y = 0; y < KP; ++y) {
+                        // an explicit slot has cn == 0; padding slots stay zero either way
+                        const bool rs = cn[t][y] == 0.0f;
+                        const float wn = w[y] + a.g[4] * (err * rw[t][y] - a.l[4] * w[y]);
+                        const float cnn = c[y] + a.g[5] * (err * cn[t][y] - a.l[5] * c[y]);
+                        w[y] = (itm && rs) ? wn : w[y];
+                        c[y] = (itm && !rs) ? cnn : c[y];
+                    }
+                }
+                // publish the group: errors, then done flags
+                if (lane < cnt) rerr[(gs + lane) % kRing] = errv;
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
-                if (lane == 0)
-                    __hip_atomic_store(&mb_seq[ws], (int)((lw >> 16) & 0x3FFFu) + 1, __ATOMIC_RELAXED,
+                if (lane < cnt)
+                    __hip_atomic_store(&rdone[(gs + lane) % kRing], gs + lane + 1, __ATOMIC_RELAXED,
                                        __HIP_MEMORY_SCOPE_WORKGROUP);
+                if (gn < len && !have_next) {
+                    wait_group(gn, cntn);
+                    load_group(gn, cntn);
+                }
             }
             __builtin_amdgcn_s_setprio(0);
 #pragma unroll
@@ -325,26 +372,16 @@ __global__ __launch_bounds__(kSgdWaves* kWave) void k_sgd_stratum(SgdArgs a, con
                     const int tt = t0 + t;
                     if (tt >= nbw) break;
                     const int n = h + kHelpers * (mb + tt);
-                    const int sl = n & (kRing - 1);
+                    const int sl = n % kRing;
                     const uint32_t pw = S.pw[t], lw = S.lw[t];
-                    // the ring slot is free once the item wave took rating n - kRing
-                    int spins = 0;
-                    while (!dead &&
-                           __hip_atomic_load(rcons, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) < n - kRing + 1) {
-                        if (++spins > kSpinLimit) {
-                            if (lane == 0) atomicOr(a.err, 4);
-                            dead = true;
-                        }
-                        __builtin_amdgcn_s_sleep(1);
-                    }
                     // an earlier rating of the user in this block hands its row over
                     const bool has_pred = ((lw >> 30) & 1u) != 0;
                     const int pslot = has_pred ? (int)(lw & 0xFFFFu) : dummy;
                     if (has_pred) {
                         const int want = (int)((lw >> 16) & 0x3FFFu);
-                        spins = 0;
-                        while (!dead && __hip_atomic_load(&mb_seq[pslot], __ATOMIC_RELAXED,
-                                                          __HIP_MEMORY_SCOPE_WORKGROUP) != want) {
+                        int spins = 0;
+                        while (!dead && __builtin_amdgcn_readfirstlane(__hip_atomic_load(
+                                            &mb_seq[pslot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) != want) {
                             if (++spins > kSpinLimit) {
                                 if (lane == 0) atomicOr(a.err, 2);
                                 dead = true;
@@ -399,6 +436,51 @@ __global__ __launch_bounds__(kSgdWaves* kWave) void k_sgd_stratum(SgdArgs a, con
                     if (lane == 0) __hip_atomic_store(&rready[sl], n + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
                 }
             };
+            // b_i and u_i of this helper's ratings [fin, to) once the item wave is done with them
+            int fin = 0;
+            auto hfinish = [&](int to) {
+                for (; fin < to; ++fin) {
+                    const int n = h + kHelpers * fin;
+                    const int sl = n % kRing;
+                    int spins = 0;
+                    while (!dead && __builtin_amdgcn_readfirstlane(__hip_atomic_load(
+                                        &rdone[sl], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) != n + 1) {
+                        if (++spins > kSpinLimit) {
+                            if (lane == 0) atomicOr(a.err, 4);
+                            dead = true;
+                        }
+                        __builtin_amdgcn_s_sleep(1);
+                    }
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+                    const float* d = rdata + sl * RS;
+                    const int* hd = rhdr + sl * 4;
+                    const float err = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(rerr[sl])));
+                    const float bi = __int_as_float(__builtin_amdgcn_readfirstlane(hd[1]));
+                    const int64_t i = (int64_t)__builtin_amdgcn_readfirstlane(hd[2]);
+                    const uint32_t lw = (uint32_t)__builtin_amdgcn_readfirstlane(hd[3]);
+                    const bool has_succ = (lw >> 31) != 0;
+                    const int ws = has_succ ? (int)(lw & 0xFFFFu) : dummy;
+                    const float bnew = usr ? bi + a.g[0] * (err - a.l[0] * bi) : bi;
+                    float* bsink = a.trash + 2 * kWave * FP;
+                    *((lane == 0 && !has_succ) ? a.bu + i : bsink + lane) = bnew;
+                    mb_b[lane == 0 ? ws : dummy] = bnew;
+#pragma unroll
+                    for (int x = 0; x < FP; ++x) {
+                        const int f = lane + x * kWave;
+                        const float unew = d[f < F ? f : 0];
+                        *((!has_succ && f < F) ? a.U + i * F + f : a.trash + kWave * FP + f) = unew;
+                        if constexpr (BF) {
+                            uint16_t* sink = reinterpret_cast<uint16_t*>(a.trash + 3 * kWave * FP) + f;
+                            *((!has_succ && f < F) ? a.U16 + i * F + f : sink) = to_bf16(unew);
+                        }
+                        mb_u[f < F ? ws * F + f : dummy * F] = unew;
+                    }
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+                    if (lane == 0)
+                        __hip_atomic_store(&mb_seq[ws], (int)((lw >> 16) & 0x3FFFu) + 1, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_WORKGROUP);
+                }
+            };
             HStage<FP, KP> SA, SB;
             for (int mb = 0; mb < mcount; mb += kWave) {
                 const int nbw = mcount - mb < kWave ? mcount - mb : kWave;
@@ -412,12 +494,15 @@ __global__ __launch_bounds__(kSgdWaves* kWave) void k_sgd_stratum(SgdArgs a, con
                 for (int t0 = 0;; t0 += 2 * kHG) {
                     hstage(SB, pkv, lkv, mb, t0 + kHG, nbw);
                     hprep(SA, mb, t0, nbw);
+                    hfinish(mb + t0);
                     if (t0 + kHG >= nbw) break;
                     hstage(SA, pkv, lkv, mb, t0 + 2 * kHG, nbw);
                     hprep(SB, mb, t0 + kHG, nbw);
+                    hfinish(mb + t0 + kHG);
                     if (t0 + 2 * kHG >= nbw) break;
                 }
             }
+            hfinish(mcount);
         }
     }
 
@@ -466,7 +551,8 @@ __global__ __launch_bounds__(kSgdWaves* kWave) void k_sgd_stratum(SgdArgs a, con
                 if (has_pred) {
                     const int want = (int)((lw >> 16) & 0x3FFFu);
                     int spins = 0;
-                    while (__hip_atomic_load(&mb_seq[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) != want) {
+                    while (__builtin_amdgcn_readfirstlane(__hip_atomic_load(&mb_seq[slot], __ATOMIC_RELAXED,
+                                                                            __HIP_MEMORY_SCOPE_WORKGROUP)) != want) {
                         if (++spins > kSpinLimit) {
                             if (lane == 0) atomicOr(a.err, 2);
                             break;
@@ -668,7 +754,7 @@ int refresh_bf16(lshmf_ctx* c, int64_t m0, int64_t m1, int64_t n0, int64_t n1, h
 // a sequence word) and the gang rings.
 static size_t sgd_lds_bytes(const SgdArgs& args)
 {
-    const size_t gs = (size_t)kRing * args.ring_rs + kRing * 4 + kRing + 4;
+    const size_t gs = (size_t)kRing * (args.ring_rs + 7);
     return ((size_t)args.ring_off + (size_t)args.max_gangs * gs) * sizeof(float);
 }
 
