@@ -425,12 +425,13 @@ void orc_rates_for_epoch(const double* alpha, const double* lam, double beta, in
 /* into P column blocks by j mod P.  Stratum s = 0..P-1 holds the P blocks    */
 /* (b, (b+s) mod P); blocks of one stratum share no user and no item.  Inside */
 /* a block ratings run item by item -- the column-resident order of Alg.      */
-/* CULSH-MF -- with items taken by decreasing number of training ratings     */
-/* (ties by ascending id), and users ascending inside an item.  P = 1 is a    */
-/* serial order of that algorithm.                                            */
+/* CULSH-MF -- with items taken by decreasing number of ratings in the pass  */
+/* (ties by ascending id), and inside an item users by decreasing number of  */
+/* ratings in the pass (ties by ascending id).  P = 1 is a serial order of   */
+/* that algorithm.                                                            */
 /* ------------------------------------------------------------------------ */
 typedef struct {
-    int64_t s, b, rank, i, idx;
+    int64_t s, b, rank, urank, idx;
 } orc_sched;
 
 static int cmp_sched(const void* a, const void* b)
@@ -440,13 +441,13 @@ static int cmp_sched(const void* a, const void* b)
     if (x->s != y->s) return (x->s > y->s) - (x->s < y->s);
     if (x->b != y->b) return (x->b > y->b) - (x->b < y->b);
     if (x->rank != y->rank) return (x->rank > y->rank) - (x->rank < y->rank);
-    return (x->i > y->i) - (x->i < y->i);
+    return (x->urank > y->urank) - (x->urank < y->urank);
 }
 
-/* item order key: more training ratings first, then smaller id */
-static int64_t item_rank_key(const int64_t* deg, int64_t nnz, int j)
+/* order key of an item or a user: more ratings first, then smaller id */
+static int64_t rank_key(const int64_t* deg, int64_t nnz, int id)
 {
-    return (nnz - deg[j]) * (int64_t)(1u << 31) + j;
+    return (nnz - deg[id]) * (int64_t)(1u << 31) + id;
 }
 
 /* order[x] = index into the COO arrays of the x-th rating of the epoch;      */
@@ -455,18 +456,25 @@ int orc_schedule(int P, int64_t nnz, const int32_t* u, const int32_t* it,
                  int64_t* order /* nnz */, int64_t* blk_ptr /* P*P+1 */)
 {
     if (P <= 0) return ORC_EINVAL;
-    int32_t N = 0;
-    for (int64_t x = 0; x < nnz; ++x) N = it[x] + 1 > N ? it[x] + 1 : N;
+    int32_t N = 0, M = 0;
+    for (int64_t x = 0; x < nnz; ++x) {
+        N = it[x] + 1 > N ? it[x] + 1 : N;
+        M = u[x] + 1 > M ? u[x] + 1 : M;
+    }
     int64_t* deg = (int64_t*)calloc((size_t)(N > 0 ? N : 1), sizeof(int64_t));
+    int64_t* udeg = (int64_t*)calloc((size_t)(M > 0 ? M : 1), sizeof(int64_t));
     orc_sched* e = (orc_sched*)malloc(sizeof(orc_sched) * (size_t)(nnz > 0 ? nnz : 1));
-    if (!e || !deg) { free(e); free(deg); return ORC_ENOMEM; }
-    for (int64_t x = 0; x < nnz; ++x) deg[it[x]]++;
+    if (!e || !deg || !udeg) { free(e); free(deg); free(udeg); return ORC_ENOMEM; }
+    for (int64_t x = 0; x < nnz; ++x) {
+        deg[it[x]]++;
+        udeg[u[x]]++;
+    }
     for (int64_t x = 0; x < nnz; ++x) {
         const int64_t rb = u[x] % P, cb = it[x] % P;
         e[x].s = ((cb - rb) % P + P) % P;
         e[x].b = rb;
-        e[x].rank = item_rank_key(deg, nnz, it[x]);
-        e[x].i = u[x];
+        e[x].rank = rank_key(deg, nnz, it[x]);
+        e[x].urank = rank_key(udeg, nnz, u[x]);
         e[x].idx = x;
     }
     qsort(e, (size_t)nnz, sizeof(orc_sched), cmp_sched);
@@ -478,6 +486,7 @@ int orc_schedule(int P, int64_t nnz, const int32_t* u, const int32_t* it,
     for (int64_t x = 0; x < (int64_t)P * P; ++x) blk_ptr[x + 1] += blk_ptr[x];
     free(e);
     free(deg);
+    free(udeg);
     return ORC_OK;
 }
 

@@ -82,11 +82,12 @@ size_t carve(lshmf_ctx* c, char* base)
     c->bcsc_row = k.take<int32_t>(bc);
     c->bcsc_rc = k.take<uint8_t>(bc);
     c->irank = k.take<int32_t>(Nc);
+    c->urank = k.take<int32_t>(Mc);
     c->e2s = k.take<int32_t>(nz > bc ? nz : bc);
     c->trash = k.take<float>(1024);
     const int64_t cn = max3(max3(2 * Mc, 2 * Nc, P * P), max3(nz, nq, bc), 4);
     c->cnt = k.take<int64_t>(cn + 2);
-    c->sort_n = max3(nz, nq, bc > Nc ? bc : Nc) + 2;
+    c->sort_n = max3(max3(nz, nq, bc), Nc, Mc) + 2;
     c->sk[0] = k.take<uint64_t>(c->sort_n);
     c->sk[1] = k.take<uint64_t>(c->sort_n);
     c->sv[0] = k.take<uint32_t>(c->sort_n);

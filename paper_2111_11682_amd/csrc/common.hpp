@@ -133,6 +133,7 @@ struct lshmf_ctx {
 
     // shared scratch
     int32_t* irank;            // N_cap   item order of the stream being built
+    int32_t* urank;            // M_cap   user order of the stream being built
     int32_t* e2s;              // max(nnz_cap, batch_cap) rating -> stream position
     int64_t* cnt;              // counters / flags
     uint64_t* sk[2];           // sort keys

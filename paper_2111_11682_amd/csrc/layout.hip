@@ -36,14 +36,15 @@ __global__ void k_keys_pair(const int32_t* major, const int32_t* minor, int64_t 
 }
 
 struct StratKey {
-    int64_t P, MP, N;  // strata, ceil(M/P), items
+    int64_t P, MP, N, M;  // strata, ceil(M/P), items, users
 };
 
-// Stream order: (stratum s, block b, item rank, user i), where an item's rank
-// orders items by decreasing training degree, then id.  Users inside a block
-// are i = b mod P, so i/P orders them like i.
-__global__ void k_keys_stream(const int32_t* u, const int32_t* it, const int32_t* rank, int64_t n,
-                              StratKey sk, uint64_t* keys, uint32_t* vals)
+// Stream order: (stratum s, block b, item rank, user rank), where a rank
+// orders items (users) by decreasing degree within the stream's ratings, then
+// id.  Heavy users come first in every item run, so the chains of their many
+// ratings in a block start early.
+__global__ void k_keys_stream(const int32_t* u, const int32_t* it, const int32_t* rank, const int32_t* urank,
+                              int64_t n, StratKey sk, uint64_t* keys, uint32_t* vals)
 {
     for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < n;
          x += (int64_t)gridDim.x * blockDim.x) {
@@ -51,12 +52,12 @@ __global__ void k_keys_stream(const int32_t* u, const int32_t* it, const int32_t
         const int64_t rb = i % sk.P, cb = j % sk.P;
         const int64_t s = (cb - rb + sk.P) % sk.P;
         const uint64_t blk = (uint64_t)(s * sk.P + rb);
-        keys[x] = ((blk * (uint64_t)sk.N + (uint64_t)rank[j]) * (uint64_t)sk.MP) + (uint64_t)(i / sk.P);
+        keys[x] = ((blk * (uint64_t)sk.N + (uint64_t)rank[j]) * (uint64_t)sk.M) + (uint64_t)urank[i];
         vals[x] = (uint32_t)x;
     }
 }
 
-// Items by (degree in the stream desc, id asc): key = (n - deg) * 2^idbits + j.
+// Items (or users) by (degree in the stream desc, id asc): key = (n - deg) * 2^idbits + j.
 __global__ void k_keys_rank(const int64_t* deg, int32_t N, int64_t n, int idbits, uint64_t* keys,
                             uint32_t* vals)
 {
@@ -325,10 +326,16 @@ int build_stream(lshmf_ctx* c, Stream& st, const int32_t* u, const int32_t* it, 
     st.codes = false;
     if (n == 0) return LSHMF_OK;
     const int64_t P = c->P;
-    const StratKey sk{P, ceil_div(c->M, P), c->N};
+    const StratKey sk{P, ceil_div(c->M, P), c->N, c->M};
+    const int sbits = bits_for((uint64_t)(P * P)) + bits_for((uint64_t)sk.N) + bits_for((uint64_t)sk.M);
+    if (sbits > 64) {
+        set_error("stream sort key of %d bits: too many strata, items and users for 64 bits", sbits);
+        return LSHMF_ECAPACITY;
+    }
     int ri = 0;
 
-    // item order inside blocks: degree within these ratings desc, id asc
+    // item order inside blocks, then user order inside item runs: degree
+    // within these ratings desc, id asc
     const int idbits = bits_for((uint64_t)c->N);
     LSHMF_TRY(count_bins(it, n, c->cnt, c->N, s));
     hipLaunchKernelGGL(k_keys_rank, dim3(grid_for(c->N)), dim3(256), 0, s, c->cnt, c->N, n, idbits, c->sk[0],
@@ -337,13 +344,20 @@ int build_stream(lshmf_ctx* c, Stream& st, const int32_t* u, const int32_t* it, 
     LSHMF_TRY(radix_sort(c->sk, c->sv, c->N, idbits + bits_for((uint64_t)n + 1), c->hist, c->scan_tmp, s, &ri));
     hipLaunchKernelGGL(k_rank_fill, dim3(grid_for(c->N)), dim3(256), 0, s, c->sv[ri], c->N, c->irank);
     LSHMF_LAUNCHED("k_rank_fill");
+    const int ubits = bits_for((uint64_t)c->M);
+    LSHMF_TRY(count_bins(u, n, c->cnt, c->M, s));
+    hipLaunchKernelGGL(k_keys_rank, dim3(grid_for(c->M)), dim3(256), 0, s, c->cnt, c->M, n, ubits, c->sk[0],
+                       c->sv[0]);
+    LSHMF_LAUNCHED("k_keys_rank(users)");
+    LSHMF_TRY(radix_sort(c->sk, c->sv, c->M, ubits + bits_for((uint64_t)n + 1), c->hist, c->scan_tmp, s, &ri));
+    hipLaunchKernelGGL(k_rank_fill, dim3(grid_for(c->M)), dim3(256), 0, s, c->sv[ri], c->M, c->urank);
+    LSHMF_LAUNCHED("k_rank_fill(users)");
 
     // stream order and block ranges
     int32_t* bop = reinterpret_cast<int32_t*>(c->cnt);       // block of each stream position
-    hipLaunchKernelGGL(k_keys_stream, dim3(grid_for(n)), dim3(256), 0, s, u, it, c->irank, n, sk, c->sk[0],
-                       c->sv[0]);
+    hipLaunchKernelGGL(k_keys_stream, dim3(grid_for(n)), dim3(256), 0, s, u, it, c->irank, c->urank, n, sk,
+                       c->sk[0], c->sv[0]);
     LSHMF_LAUNCHED("k_keys_stream");
-    const int sbits = bits_for((uint64_t)(P * P) * (uint64_t)sk.N * (uint64_t)sk.MP);
     LSHMF_TRY(radix_sort(c->sk, c->sv, n, sbits, c->hist, c->scan_tmp, s, &ri));
     hipLaunchKernelGGL(k_stream_fill, dim3(grid_for(n)), dim3(256), 0, s, c->sv[ri], u, it, rc, n, P, st.pk,
                        st.sj, bop, c->e2s);

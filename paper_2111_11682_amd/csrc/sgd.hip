@@ -17,9 +17,9 @@
 
 namespace lshmf {
 
-constexpr int kSgdWaves = 8;
+constexpr int kSgdWaves = 12;
 constexpr int kGroup = 4;                        // ratings per pipeline stage
-constexpr int kHelpers = 3;                      // helper waves of a gang
+constexpr int kHelpers = 5;                      // helper waves of a gang
 constexpr int kGangWaves = kHelpers + 1;
 constexpr int kMaxGangs = 1;                     // gangs per block
 constexpr int kGangMin = 48;                     // shortest segment given a gang

@@ -391,11 +391,14 @@ def test_schedule_blocks_are_conflict_free():
             items |= bi
             assert all(x % P == b for x in bu)
             assert all(x % P == (b + s) % P for x in bi)
-            # inside a block: items by (degree desc, id asc), users ascending
+            # inside a block: items by (degree desc, id asc), inside an item
+            # users by (degree desc, id asc)
             deg = np.bincount(d["train_i"], minlength=w.N)
+            udeg = np.bincount(d["train_u"], minlength=w.M)
             jj = d["train_i"][sl].astype(np.int64)
-            key = (-deg[jj]) * (1 << 40) + jj * (1 << 20) + d["train_u"][sl]
-            assert np.all(np.diff(key) > 0)
+            ii = d["train_u"][sl].astype(np.int64)
+            key = list(zip(-deg[jj], jj, -udeg[ii], ii))
+            assert all(key[x] < key[x + 1] for x in range(len(key) - 1))
 
 
 def test_block_order_invariance_bit_exact():
