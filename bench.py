@@ -75,7 +75,7 @@ def profiled_traffic():
     return int(rec["traffic_bytes_per_launch"])
 
 
-def cpu_baseline(w, d, P, epochs=2):
+def cpu_baseline(w, d, P, epochs=4):
     """The FP64 oracle's SGD on the same training set, a bounded number of epochs."""
     from oracle import oracle as orc
     u, it, rc = d["train_u"], d["train_i"], d["train_rc"]
