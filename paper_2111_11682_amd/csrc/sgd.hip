@@ -94,21 +94,18 @@ __device__ inline float wave_sum(float v)
     return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 63));
 }
 
-// User-side inputs of one group of ratings, loaded a group ahead of use.  A
-// user rated earlier in the same block is read from the block's LDS mailbox
-// (m*), otherwise from HBM (g*); both loads are always issued so that every
-// group issues the same memory operations.
+// User-side HBM inputs of one group of ratings, loaded a group ahead of use.
+// A user rated earlier in the same block is read from the block's LDS mailbox
+// instead, when its rating is computed.
 template <int FP, int KP>
 struct Stage {
     float gu[kGroup][FP];
-    float mu[kGroup][FP];
-    float gbi[kGroup], mbi[kGroup], b0[kGroup];
+    float gbi[kGroup], b0[kGroup];
     uint32_t nb[kGroup][KP];  // raw neighbour-code bytes of this lane's slots
     uint32_t pk[kGroup];      // (user << 4) | code
     uint32_t lk[kGroup];      // hand-over word
 };
 
-// BF: also keep the BF16 copies of the rows the kernel writes.
 // HBM inputs of kHG ratings of a helper wave, loaded a stage ahead of use.
 template <int FP, int KP>
 struct HStage {
@@ -118,6 +115,7 @@ struct HStage {
     uint32_t pw[kHG], lw[kHG];
 };
 
+// BF: also keep the BF16 copies of the rows the kernel writes.
 template <int FP, int KP, bool BF>
 __global__ __launch_bounds__(kSgdWaves* kWave) void k_sgd_stratum(SgdArgs a, const uint32_t* __restrict__ pk,
                                                                    const uint32_t* __restrict__ link)
@@ -541,42 +539,24 @@ __global__ __launch_bounds__(kSgdWaves* kWave) void k_sgd_stratum(SgdArgs a, con
             lx = lane < kGroup ? link[gb + lane] : 0u;
         };
         // wait for an earlier rating of the same user, then load the inputs
+        // HBM inputs of a group, loaded a group ahead; no waits here, so a
+        // rating never waits on a hand-over meant for a later one
         auto stage = [&](Stage<FP, KP>& S, uint32_t px, uint32_t lx, int64_t gb) {
 #pragma unroll
             for (int sl = 0; sl < kGroup; ++sl) {
                 const uint32_t pw = (uint32_t)__builtin_amdgcn_readlane((int)px, sl);
                 const uint32_t lw = (uint32_t)__builtin_amdgcn_readlane((int)lx, sl);
-                const bool has_pred = gb + sl < ez && ((lw >> 30) & 1u);
-                const int slot = (int)(lw & 0xFFFFu);
-                if (has_pred) {
-                    const int want = (int)((lw >> 16) & 0x3FFFu);
-                    int spins = 0;
-                    while (__builtin_amdgcn_readfirstlane(__hip_atomic_load(&mb_seq[slot], __ATOMIC_RELAXED,
-                                                                            __HIP_MEMORY_SCOPE_WORKGROUP)) != want) {
-                        if (++spins > kSpinLimit) {
-                            if (lane == 0) atomicOr(a.err, 2);
-                            break;
-                        }
-                        __builtin_amdgcn_s_sleep(1);
-                    }
-                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
-                }
                 S.pk[sl] = pw;
                 S.lk[sl] = lw;
                 const int64_t i = pw >> 4;
-                const float* urow = has_pred ? a.trash : a.U + i * F;
-                const int rs = has_pred ? slot : dummy;
                 // lanes past F read the sink row: every load is issued by all lanes
 #pragma unroll
                 for (int x = 0; x < FP; ++x) {
                     const int f = lane + x * kWave;
-                    const float gv = *(f < F ? urow + f : a.trash + lane);
-                    const float mv = mb_u[(f < F ? rs * F + f : dummy * F)];
+                    const float gv = *(f < F ? a.U + i * F + f : a.trash + lane);
                     S.gu[sl][x] = f < F ? gv : 0.0f;   // lanes past F keep u = 0 (and so v = 0)
-                    S.mu[sl][x] = f < F ? mv : 0.0f;
                 }
-                S.gbi[sl] = has_pred ? a.trash[F] : a.bu[i];
-                S.mbi[sl] = mb_b[rs];
+                S.gbi[sl] = a.bu[i];
                 S.b0[sl] = a.b0[i];
                 const uint8_t* nbp = a.nib + (gb + sl) * a.nstride;
 #pragma unroll
@@ -611,10 +591,29 @@ __global__ __launch_bounds__(kSgdWaves* kWave) void k_sgd_stratum(SgdArgs a, con
                 }
                 const float sR = nR > 0 ? __builtin_amdgcn_rsqf((float)nR) : 0.0f;
                 const float sN = K - nR > 0 ? __builtin_amdgcn_rsqf((float)(K - nR)) : 0.0f;
+                // an earlier rating of the user in this block hands its row over
+                if (has_pred) {
+                    const int want = (int)((lw >> 16) & 0x3FFFu);
+                    int spins = 0;
+                    while (__builtin_amdgcn_readfirstlane(__hip_atomic_load(&mb_seq[slot], __ATOMIC_RELAXED,
+                                                                            __HIP_MEMORY_SCOPE_WORKGROUP)) != want) {
+                        if (++spins > kSpinLimit) {
+                            if (lane == 0) atomicOr(a.err, 2);
+                            break;
+                        }
+                        __builtin_amdgcn_s_sleep(1);
+                    }
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+                }
+                const int rs = has_pred ? slot : dummy;
                 float u[FP];
 #pragma unroll
-                for (int x = 0; x < FP; ++x) u[x] = has_pred ? S.mu[sl][x] : S.gu[sl][x];
-                const float bi = has_pred ? S.mbi[sl] : S.gbi[sl];
+                for (int x = 0; x < FP; ++x) {
+                    const int f = lane + x * kWave;
+                    const float mv = mb_u[f < F ? rs * F + f : dummy * F];
+                    u[x] = has_pred ? (f < F ? mv : 0.0f) : S.gu[sl][x];
+                }
+                const float bi = has_pred ? mb_b[rs] : S.gbi[sl];
                 // u.v + |R^K|^-1/2 sum resid*w + |N^K|^-1/2 sum c: one reduction
                 float part = 0.0f;
 #pragma unroll
