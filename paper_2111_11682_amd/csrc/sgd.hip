@@ -569,6 +569,30 @@ __global__ __launch_bounds__(kSgdWaves* kWave) void k_sgd_stratum(SgdArgs a, con
         // Eq. (rr) and Eq. (sgd_update) for the ratings of one group, in order;
         // then hand the updated user rows to later ratings of the same users
         auto compute = [&](Stage<FP, KP>& S, int64_t gb) {
+            // are the hand-overs of the whole group there?  lane t checks rating gb + t
+            uint32_t lwl = 0u;
+#pragma unroll
+            for (int sl = 0; sl < kGroup; ++sl) lwl = lane == sl ? S.lk[sl] : lwl;
+            const bool hpl = lane < kGroup && gb + lane < ez && ((lwl >> 30) & 1u);
+            const bool okl = !hpl || __hip_atomic_load(&mb_seq[lwl & 0xFFFFu], __ATOMIC_RELAXED,
+                                                       __HIP_MEMORY_SCOPE_WORKGROUP) == (int)((lwl >> 16) & 0x3FFFu);
+            const bool ready = __ballot(!okl) == 0ull;
+            float mrow[kGroup][FP], mbv[kGroup];
+            if (ready) {
+                // read every handed-over row of the group at once
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+#pragma unroll
+                for (int sl = 0; sl < kGroup; ++sl) {
+                    const uint32_t lw = S.lk[sl];
+                    const int rs = (gb + sl < ez && ((lw >> 30) & 1u)) ? (int)(lw & 0xFFFFu) : dummy;
+#pragma unroll
+                    for (int x = 0; x < FP; ++x) {
+                        const int f = lane + x * kWave;
+                        mrow[sl][x] = mb_u[f < F ? rs * F + f : dummy * F];
+                    }
+                    mbv[sl] = mb_b[rs];
+                }
+            }
 #pragma unroll
             for (int sl = 0; sl < kGroup; ++sl) {
                 const bool valid = gb + sl < ez;
@@ -592,7 +616,7 @@ __global__ __launch_bounds__(kSgdWaves* kWave) void k_sgd_stratum(SgdArgs a, con
                 const float sR = nR > 0 ? __builtin_amdgcn_rsqf((float)nR) : 0.0f;
                 const float sN = K - nR > 0 ? __builtin_amdgcn_rsqf((float)(K - nR)) : 0.0f;
                 // an earlier rating of the user in this block hands its row over
-                if (has_pred) {
+                if (has_pred && !ready) {
                     const int want = (int)((lw >> 16) & 0x3FFFu);
                     int spins = 0;
                     while (__builtin_amdgcn_readfirstlane(__hip_atomic_load(&mb_seq[slot], __ATOMIC_RELAXED,
@@ -604,16 +628,20 @@ __global__ __launch_bounds__(kSgdWaves* kWave) void k_sgd_stratum(SgdArgs a, con
                         __builtin_amdgcn_s_sleep(1);
                     }
                     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+#pragma unroll
+                    for (int x = 0; x < FP; ++x) {
+                        const int f = lane + x * kWave;
+                        mrow[sl][x] = mb_u[f < F ? slot * F + f : dummy * F];
+                    }
+                    mbv[sl] = mb_b[slot];
                 }
-                const int rs = has_pred ? slot : dummy;
                 float u[FP];
 #pragma unroll
                 for (int x = 0; x < FP; ++x) {
                     const int f = lane + x * kWave;
-                    const float mv = mb_u[f < F ? rs * F + f : dummy * F];
-                    u[x] = has_pred ? (f < F ? mv : 0.0f) : S.gu[sl][x];
+                    u[x] = has_pred ? (f < F ? mrow[sl][x] : 0.0f) : S.gu[sl][x];
                 }
-                const float bi = has_pred ? mb_b[rs] : S.gbi[sl];
+                const float bi = has_pred ? mbv[sl] : S.gbi[sl];
                 // u.v + |R^K|^-1/2 sum resid*w + |N^K|^-1/2 sum c: one reduction
                 float part = 0.0f;
 #pragma unroll
