@@ -149,8 +149,9 @@ int build_lsh_neighbours(lshmf_ctx* ctx, const uint32_t* d_H, uint64_t seed_fill
 /* One SGD epoch t (0-based) over all training ratings in the stratified
  * order: stratum s = 0..P-1 runs the P blocks (b, (b+s) mod P) of users
  * i mod P = b and items j mod P = (b+s) mod P; inside a block, runs of one
- * item by decreasing item degree (ties by smaller id), users ascending within
- * a run.  Each rating applies Eq.
+ * item by decreasing item degree (ties by smaller id), and inside a run users
+ * by decreasing user degree (ties by smaller id); degrees count the ratings
+ * of the pass.  Each rating applies Eq.
  * (sgd_update) with the prediction of Eq. (rr), N(i) the complement of R(i)
  * (the CULSH-MF adjustment), and the residual baseline of the w-term fixed to
  * the simple-case means.  Results do not depend on how blocks are scheduled.

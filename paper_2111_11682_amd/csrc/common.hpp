@@ -72,7 +72,8 @@ namespace lshmf {
 // One stratified stream of ratings: the order an SGD pass visits them in.
 // Stratum s runs blocks (b, (b+s) mod P) of users i mod P = b and items
 // j mod P = (b+s) mod P; inside a block item runs go by decreasing degree
-// (within the stream's own ratings, ties by id), users ascending in a run.
+// (within the stream's own ratings, ties by id), users inside a run by
+// decreasing degree too (ties by id).
 struct Stream {
     int64_t cap = 0;           // ratings it can hold
     uint32_t* pk;              // cap + kStreamPad  (user << 4) | code

@@ -2,15 +2,18 @@
 // FP64 RMSE reduction.
 //
 // k_sgd_stratum (Alg. CULSH-MF, Eq. sgd_update with Eq. rr): one workgroup per
-// block of the stratum, 8 waves.  A wave takes the next item segment of its
-// block (a run of ratings of one item j), holds the item state {v_j, bh_j,
-// w_j, c_j} in registers for the whole run -- the register-resident column
-// state of the paper's kernel -- and streams the users' {u_i, b_i} from HBM.
-// Lanes own features f = lane + 64x and neighbour slots k = lane + 64y, so
-// u.v, the explicit w-sum and the implicit c-sum of Eq. (rr) fold into ONE
-// 64-lane reduction.  Blocks of a stratum share no user and no item; inside a
-// block, a rating waits (LDS flag) for the previous rating of the same user,
-// which makes the result identical to running the block's ratings in order.
+// block of the stratum, kSgdWaves waves.  A wave takes the next item run of
+// its block (the ratings of one item j), holds the item state {v_j, bh_j, w_j,
+// c_j} in registers for the whole run -- the register-resident column state
+// of the paper's kernel -- and streams the users' {u_i, b_i} from HBM.  Lanes
+// own features f = lane + 64x and neighbour slots k = lane + 64y, so u.v, the
+// explicit w-sum and the implicit c-sum of Eq. (rr) fold into ONE 64-lane
+// reduction.  The block's first run, when long, is split between an item
+// wave that runs only the dependent update chain and helper waves that
+// prepare and finish the user side (a gang, below).  Blocks of a stratum
+// share no user and no item; inside a block, a rating waits (LDS mailbox with
+// sequence numbers) for the previous rating of the same user, which makes the
+// result identical to running the block's ratings in order.
 #include <cmath>
 
 #include "common.hpp"
