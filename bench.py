@@ -47,6 +47,8 @@ def sgd_bytes_per_epoch(nnz, nseg, F, K, nstride, storage="fp32"):
     return nnz * per_rating + nseg * per_seg
 
 
+SHAPE_NAMES = {"ml10m": "MovieLens-10M", "netflix": "Netflix", "ml100k": "MovieLens-100K"}
+
 KERNEL_SOURCES = ("paper_2111_11682_amd/csrc/sgd.hip", "paper_2111_11682_amd/csrc/common.hpp",
                   "include/lshmf.h")
 PROFILE = os.path.join(ROOT, "profiles", "k_sgd_stratum_ml10m.md")
@@ -176,11 +178,14 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--mode", choices=("train", "serve"), default="train",
                     help="serve: the serving loop over an online stream instead of the training job")
-    ap.add_argument("--storage", choices=("fp32", "bf16"), default="fp32",
-                    help="bf16: BF16 copies of U, V, W, C beside the FP32 masters")
+    ap.add_argument("--storage", choices=("fp32", "bf16"), default=None,
+                    help="bf16: BF16 copies of U, V, W, C beside the FP32 masters "
+                         "(default fp32 for training, bf16 for serving)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one plain 1 GiB device copy, the reference for HBM byte counters")
     args = ap.parse_args()
+    if args.storage is None:
+        args.storage = "bf16" if args.mode == "serve" else "fp32"
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
@@ -284,8 +289,8 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
-        "data": "synthetic (seeded Zipf/lognormal ratings with planted structure, MovieLens-10M shape)",
-        "config": {"workload": "ml10m-shaped LSH-MF training job", "users": w.M, "items": w.N,
+        "data": "synthetic (seeded Zipf/lognormal ratings with planted structure, %s shape)" % SHAPE_NAMES.get(w.name, w.name),
+        "config": {"workload": "%s-shaped LSH-MF training job" % w.name, "users": w.M, "items": w.N,
                    "train_ratings": int(nnz), "test_ratings": int(d["test_u"].size), "F": w.F,
                    "K": w.K, "hash_bits": w.B, "p": w.p, "q": w.q, "epochs": epochs,
                    "n_strata": P, "storage": args.storage, "heldout_rmse": round(final_rmse, 6),

@@ -89,7 +89,7 @@ WORKLOADS: Dict[str, Workload] = {
     # Netflix-shaped (Table "Data sets", Netflix column)
     "netflix": Workload("netflix", 480_189, 17_770, 100_000_000, 1, 1.2, "lognormal",
                         4.5, 1.2, 1, 1_408_395, 128, 100, 8, 1, 16, 20,
-                        _NF_ALPHA, _NF_LAM, 0.3, n_strata=256),
+                        _NF_ALPHA, _NF_LAM, 0.3, n_strata=1536),
     # small shapes for CPU tests
     "tiny": Workload("tiny", 120, 90, 2_400, 1, 1.0, "c1", 0.0, 1.0, 5,
                      240, 8, 6, 8, 1, 4, 3, (0.01,) * 6, (0.05,) * 6, 0.0,
