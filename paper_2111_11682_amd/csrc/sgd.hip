@@ -26,9 +26,11 @@ constexpr int kHelpers = 5;                      // helper waves of a gang
 constexpr int kGangWaves = kHelpers + 1;
 constexpr int kMaxGangs = 1;                     // gangs per block
 constexpr int kGangMin = 48;                     // shortest segment given a gang
-constexpr int kRing = 11 * kHelpers;              // ring slots of a gang (a multiple of kHelpers)
-constexpr int kIG = 8;                           // ratings per item-wave group
 constexpr int kHG = 4;                           // ratings per helper pipeline stage
+// ring slots of a gang: a multiple of kHelpers, and more than two helper
+// stages per helper, so that a helper reuses a slot only after finishing it
+constexpr int kRing = (2 * kHG + 3) * kHelpers;
+constexpr int kIG = 8;                           // ratings per item-wave group
 constexpr int kSpinLimit = 1 << 24;              // bounded wait: a broken hand-over ends the kernel
 constexpr int kMaxMailboxBytes = 150 * 1024;     // mailbox part of a block's dynamic LDS
 constexpr int kMaxLdsBytes = 160 * 1024 - 256;   // all of it (static LDS aside)
