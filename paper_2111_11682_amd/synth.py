@@ -98,6 +98,14 @@ WORKLOADS: Dict[str, Workload] = {
                       _ln_mu_for_mean(43.0, 1.0), 1.0, 5,
                       2_000, 64, 50, 8, 1, 16, 2, _ML_ALPHA, _ML_LAM, 0.3,
                       n_strata=8),
+    # Netflix-like at 1/100 of the users: F = 128, K = 100 (two lane passes)
+    "nfsmall": Workload("nfsmall", 4_800, 1_777, 600_000, 1, 1.2, "lognormal",
+                        _ln_mu_for_mean(125.0, 1.2), 1.2, 1, 10_000, 128, 100, 8, 1, 16, 2,
+                        _NF_ALPHA, _NF_LAM, 0.3, n_strata=32),
+    # wide factors and an odd neighbour count: F = 200, K = 70
+    "wide": Workload("wide", 900, 600, 40_000, 2, 1.1, "lognormal",
+                     _ln_mu_for_mean(44.0, 1.0), 1.0, 5, 2_000, 200, 70, 8, 1, 8, 2,
+                     _ML_ALPHA, _ML_LAM, 0.3, n_strata=12),
 }
 
 

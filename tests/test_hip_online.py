@@ -110,7 +110,7 @@ def _check_state(m, o, acc, sig, Mc, Nc, tol):
     return worst
 
 
-@pytest.mark.parametrize("name,nb,passes", [("tiny", 2, 1), ("small", 3, 2), ("ml100k", 2, 1)])
+@pytest.mark.parametrize("name,nb,passes", [("tiny", 2, 1), ("small", 3, 2), ("ml100k", 2, 1), ("nfsmall", 2, 1), ("wide", 2, 1)])
 def test_online_update_parity(name, nb, passes):
     w, d, m, o, acc, sig, Mc, Nc = _setup(name, 0.03, 0.2, nb, passes)
     worst = _check_state(m, o, acc, sig, Mc, Nc, 1e-4)

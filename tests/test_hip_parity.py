@@ -92,7 +92,7 @@ def test_worked_example_on_gpu():
     assert m.JK.cpu().tolist() == [[1], [0]]
 
 
-@pytest.mark.parametrize("name", ["tiny", "small", "ml100k"])
+@pytest.mark.parametrize("name", ["tiny", "small", "ml100k", "nfsmall", "wide"])
 def test_layout_matches_oracle_order(name):
     from paper_2111_11682_amd import lshmf  # noqa: F401
     w, d, m = gpu_model(name)
@@ -129,7 +129,7 @@ def test_layout_matches_oracle_order(name):
     assert np.allclose(m.bh0.cpu().numpy(), bh0, rtol=0, atol=1e-6)
 
 
-@pytest.mark.parametrize("name", ["tiny", "small", "ml100k"])
+@pytest.mark.parametrize("name", ["tiny", "small", "ml100k", "nfsmall", "wide"])
 def test_signatures_and_neighbours_bit_exact(name):
     w, d, m = gpu_model(name)
     acc, sig, JK = oracle_neighbours(name)
@@ -138,14 +138,14 @@ def test_signatures_and_neighbours_bit_exact(name):
     assert np.array_equal(m.JK.cpu().numpy(), JK)
 
 
-@pytest.mark.parametrize("name", ["small", "ml100k"])
+@pytest.mark.parametrize("name", ["small", "ml100k", "nfsmall", "wide"])
 def test_neighbour_codes_exact(name):
     w, d, m = gpu_model(name)
     nnz = d["train_u"].size
     lay = m.layout()
     nib = m.arena_view(lay.nib, nnz * lay.nstride, torch.uint8).cpu().numpy().reshape(nnz, lay.nstride)
     order, _ = orc.schedule(w.n_strata, d["train_u"], d["train_i"])
-    JK = m.JK.cpu().numpy()
+    _, _, JK = oracle_neighbours(name)
     lookup = {}
     for a, b, r in zip(d["train_u"], d["train_i"], d["train_rc"]):
         lookup[(int(a), int(b))] = int(r)
@@ -168,7 +168,7 @@ def _random_tables(w, seed):
                 W=rng.normal(0, 0.1, (w.N, w.K)), C=rng.normal(0, 0.1, (w.N, w.K)))
 
 
-@pytest.mark.parametrize("name", ["tiny", "small", "ml100k"])
+@pytest.mark.parametrize("name", ["tiny", "small", "ml100k", "nfsmall", "wide"])
 def test_predict_parity(name):
     w, d, m = gpu_model(name)
     _, _, JK = oracle_neighbours(name)
@@ -203,7 +203,7 @@ def _compare_tables(m, o, tol):
     return worst
 
 
-@pytest.mark.parametrize("name", ["tiny", "small", "ml100k"])
+@pytest.mark.parametrize("name", ["tiny", "small", "ml100k", "nfsmall", "wide"])
 def test_one_epoch_parity(name):
     w, d, m = gpu_model(name)
     _, _, JK = oracle_neighbours(name)
