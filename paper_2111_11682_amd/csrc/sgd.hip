@@ -26,10 +26,12 @@ constexpr int kHelpers = 5;                      // helper waves of a gang
 constexpr int kGangWaves = kHelpers + 1;
 constexpr int kMaxGangs = 1;                     // gangs per block
 constexpr int kGangMin = 48;                     // shortest segment given a gang
-constexpr int kHG = 4;                           // ratings per helper pipeline stage
-// ring slots of a gang: a multiple of kHelpers, and more than two helper
-// stages per helper, so that a helper reuses a slot only after finishing it
-constexpr int kRing = (2 * kHG + 3) * kHelpers;
+constexpr int kHG = 6;                           // ratings per helper pipeline stage
+constexpr int kFinLag = 1;                       // stages a helper prepares ahead of those it finishes
+// ring slots of a gang: a multiple of kHelpers, and more than kFinLag + 1
+// helper stages per helper, so that a helper reuses a slot only after
+// finishing it
+constexpr int kRing = ((kFinLag + 1) * kHG + 3) * kHelpers;
 constexpr int kIG = 8;                           // ratings per item-wave group
 constexpr int kSpinLimit = 1 << 24;              // bounded wait: a broken hand-over ends the kernel
 constexpr int kMaxMailboxBytes = 150 * 1024;     // mailbox part of a block's dynamic LDS
@@ -497,11 +499,11 @@ __global__ __launch_bounds__(kSgdWaves* kWave) void k_sgd_stratum(SgdArgs a, con
                 for (int t0 = 0;; t0 += 2 * kHG) {
                     hstage(SB, pkv, lkv, mb, t0 + kHG, nbw);
                     hprep(SA, mb, t0, nbw);
-                    hfinish(mb + t0);
+                    hfinish(mb + t0 - (kFinLag - 1) * kHG);
                     if (t0 + kHG >= nbw) break;
                     hstage(SA, pkv, lkv, mb, t0 + 2 * kHG, nbw);
                     hprep(SB, mb, t0 + kHG, nbw);
-                    hfinish(mb + t0 + kHG);
+                    hfinish(mb + t0 + kHG - (kFinLag - 1) * kHG);
                     if (t0 + 2 * kHG >= nbw) break;
                 }
             }
