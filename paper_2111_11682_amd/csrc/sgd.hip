@@ -220,7 +220,8 @@ __global__ __launch_bounds__(kSgdWaves* kWave) void k_sgd_stratum(SgdArgs a, con
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
             };
             float pu[kIG][FP], prw[kIG][KP], pcn[kIG][KP];
-            float preff = 0.0f;  // lane t: r - mu - b_i of rating gs + t
+            float preff = 0.0f, pbi = 0.0f;  // lane t: r - mu - b_i and b_i of rating gs + t
+            int pi = 0, plw = 0;               // lane t: user and hand-over word of rating gs + t
             auto load_group = [&](int gs, int cnt) {
 #pragma unroll
                 for (int t = 0; t < kIG; ++t) {
@@ -237,7 +238,11 @@ __global__ __launch_bounds__(kSgdWaves* kWave) void k_sgd_stratum(SgdArgs a, con
                         pcn[t][y] = k < K ? d[F + K + k] : 0.0f;
                     }
                 }
-                preff = __int_as_float(rhdr[((gs + (lane < cnt ? lane : 0)) % kRing) * 4]);
+                const int* hd = rhdr + ((gs + (lane < cnt ? lane : 0)) % kRing) * 4;
+                preff = __int_as_float(hd[0]);
+                pbi = __int_as_float(hd[1]);
+                pi = hd[2];
+                plw = hd[3];
             };
             wait_group(0, len < kIG ? len : kIG);
             load_group(0, len < kIG ? len : kIG);
@@ -254,7 +259,8 @@ __global__ __launch_bounds__(kSgdWaves* kWave) void k_sgd_stratum(SgdArgs a, con
                         cn[t][y] = pcn[t][y];
                     }
                 }
-                const float reff_v = preff;
+                const float reff_v = preff, bi_v = pbi;
+                const int i_v = pi, lw_v = plw;
                 // the next group's inputs, if they are already there
                 const int gn = gs + kIG;
                 const int cntn = len - gn < kIG ? len - gn : kIG;
@@ -278,15 +284,26 @@ __global__ __launch_bounds__(kSgdWaves* kWave) void k_sgd_stratum(SgdArgs a, con
                     for (int y = 0; y < KP; ++y) part += rw[t][y] * w[y] + cn[t][y] * c[y];
                     const float err = reff - (bh + wave_sum(part));
                     errv = lane == t ? err : errv;
-                    float* d = rdata + sl * RS;
+                    // u_i's new row: to the mailbox for the user's next rating in
+                    // the block, else to HBM (the other store goes to a sink)
+                    const int64_t i = (int64_t)__builtin_amdgcn_readlane(i_v, t);
+                    const uint32_t lw = (uint32_t)__builtin_amdgcn_readlane(lw_v, t);
+                    const bool has_succ = (lw >> 31) != 0;
+                    const int ws = has_succ ? (int)(lw & 0xFFFFu) : dummy;
 #pragma unroll
                     for (int x = 0; x < FP; ++x) {
                         const int f = lane + x * kWave;
                         const float unew = usr ? u[t][x] + a.g[2] * (err * v[x] - a.l[2] * u[t][x]) : u[t][x];
-                        if (f < F) d[f] = unew;
+                        mb_u[f < F ? ws * F + f : dummy * F] = unew;
+                        *((!has_succ && f < F) ? a.U + i * F + f : a.trash + kWave * FP + f) = unew;
+                        if constexpr (BF) {
+                            uint16_t* sink = reinterpret_cast<uint16_t*>(a.trash + 3 * kWave * FP) + f;
+                            *((!has_succ && f < F) ? a.U16 + i * F + f : sink) = to_bf16(unew);
+                        }
                         const float vn = v[x] + a.g[3] * (err * u[t][x] - a.l[3] * v[x]);
                         v[x] = itm ? vn : v[x];
                     }
+                    (void)sl;
                     const float bh_new = bh + a.g[1] * (err - a.l[1] * bh);
                     bh = itm ? bh_new : bh;
 #pragma unroll
@@ -299,12 +316,25 @@ __global__ __launch_bounds__(kSgdWaves* kWave) void k_sgd_stratum(SgdArgs a, con
                         c[y] = (itm && !rs) ? cnn : c[y];
                     }
                 }
-                // publish the group: errors, then done flags
-                if (lane < cnt) rerr[(gs + lane) % kRing] = errv;
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
-                if (lane < cnt)
-                    __hip_atomic_store(&rdone[(gs + lane) % kRing], gs + lane + 1, __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_WORKGROUP);
+                // publish the group (lane t: rating gs + t): b_i to the mailbox or
+                // HBM, then the hand-over sequence numbers and the done flags
+                {
+                    const bool live = lane < cnt;
+                    const bool succ = live && ((uint32_t)lw_v >> 31) != 0;
+                    const int ws = succ ? (lw_v & 0xFFFF) : dummy;
+                    const float bnew = usr ? bi_v + a.g[0] * (errv - a.l[0] * bi_v) : bi_v;
+                    if (live) {
+                        mb_b[ws] = bnew;
+                        *(succ ? a.trash + 2 * kWave * FP + lane : a.bu + i_v) = bnew;
+                    }
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+                    if (live) {
+                        __hip_atomic_store(&mb_seq[ws], ((lw_v >> 16) & 0x3FFF) + 1, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_WORKGROUP);
+                        __hip_atomic_store(&rdone[(gs + lane) % kRing], gs + lane + 1, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_WORKGROUP);
+                    }
+                }
                 if (gn < len && !have_next) {
                     wait_group(gn, cntn);
                     load_group(gn, cntn);
@@ -379,6 +409,18 @@ __global__ __launch_bounds__(kSgdWaves* kWave) void k_sgd_stratum(SgdArgs a, con
                     const int n = h + kHelpers * (mb + tt);
                     const int sl = n % kRing;
                     const uint32_t pw = S.pw[t], lw = S.lw[t];
+                    // the slot's previous rating, n - kRing, must be done
+                    if (n >= kRing) {
+                        int spins = 0;
+                        while (!dead && __builtin_amdgcn_readfirstlane(__hip_atomic_load(
+                                            &rdone[sl], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) < n - kRing + 1) {
+                            if (++spins > kSpinLimit) {
+                                if (lane == 0) atomicOr(a.err, 4);
+                                dead = true;
+                            }
+                            __builtin_amdgcn_s_sleep(1);
+                        }
+                    }
                     // an earlier rating of the user in this block hands its row over
                     const bool has_pred = ((lw >> 30) & 1u) != 0;
                     const int pslot = has_pred ? (int)(lw & 0xFFFFu) : dummy;
@@ -441,51 +483,6 @@ __global__ __launch_bounds__(kSgdWaves* kWave) void k_sgd_stratum(SgdArgs a, con
                     if (lane == 0) __hip_atomic_store(&rready[sl], n + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
                 }
             };
-            // b_i and u_i of this helper's ratings [fin, to) once the item wave is done with them
-            int fin = 0;
-            auto hfinish = [&](int to) {
-                for (; fin < to; ++fin) {
-                    const int n = h + kHelpers * fin;
-                    const int sl = n % kRing;
-                    int spins = 0;
-                    while (!dead && __builtin_amdgcn_readfirstlane(__hip_atomic_load(
-                                        &rdone[sl], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) != n + 1) {
-                        if (++spins > kSpinLimit) {
-                            if (lane == 0) atomicOr(a.err, 4);
-                            dead = true;
-                        }
-                        __builtin_amdgcn_s_sleep(1);
-                    }
-                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
-                    const float* d = rdata + sl * RS;
-                    const int* hd = rhdr + sl * 4;
-                    const float err = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(rerr[sl])));
-                    const float bi = __int_as_float(__builtin_amdgcn_readfirstlane(hd[1]));
-                    const int64_t i = (int64_t)__builtin_amdgcn_readfirstlane(hd[2]);
-                    const uint32_t lw = (uint32_t)__builtin_amdgcn_readfirstlane(hd[3]);
-                    const bool has_succ = (lw >> 31) != 0;
-                    const int ws = has_succ ? (int)(lw & 0xFFFFu) : dummy;
-                    const float bnew = usr ? bi + a.g[0] * (err - a.l[0] * bi) : bi;
-                    float* bsink = a.trash + 2 * kWave * FP;
-                    *((lane == 0 && !has_succ) ? a.bu + i : bsink + lane) = bnew;
-                    mb_b[lane == 0 ? ws : dummy] = bnew;
-#pragma unroll
-                    for (int x = 0; x < FP; ++x) {
-                        const int f = lane + x * kWave;
-                        const float unew = d[f < F ? f : 0];
-                        *((!has_succ && f < F) ? a.U + i * F + f : a.trash + kWave * FP + f) = unew;
-                        if constexpr (BF) {
-                            uint16_t* sink = reinterpret_cast<uint16_t*>(a.trash + 3 * kWave * FP) + f;
-                            *((!has_succ && f < F) ? a.U16 + i * F + f : sink) = to_bf16(unew);
-                        }
-                        mb_u[f < F ? ws * F + f : dummy * F] = unew;
-                    }
-                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
-                    if (lane == 0)
-                        __hip_atomic_store(&mb_seq[ws], (int)((lw >> 16) & 0x3FFFu) + 1, __ATOMIC_RELAXED,
-                                           __HIP_MEMORY_SCOPE_WORKGROUP);
-                }
-            };
             HStage<FP, KP> SA, SB;
             for (int mb = 0; mb < mcount; mb += kWave) {
                 const int nbw = mcount - mb < kWave ? mcount - mb : kWave;
@@ -499,15 +496,12 @@ __global__ __launch_bounds__(kSgdWaves* kWave) void k_sgd_stratum(SgdArgs a, con
                 for (int t0 = 0;; t0 += 2 * kHG) {
                     hstage(SB, pkv, lkv, mb, t0 + kHG, nbw);
                     hprep(SA, mb, t0, nbw);
-                    hfinish(mb + t0 - (kFinLag - 1) * kHG);
                     if (t0 + kHG >= nbw) break;
                     hstage(SA, pkv, lkv, mb, t0 + 2 * kHG, nbw);
                     hprep(SB, mb, t0 + kHG, nbw);
-                    hfinish(mb + t0 + kHG - (kFinLag - 1) * kHG);
                     if (t0 + 2 * kHG >= nbw) break;
                 }
             }
-            hfinish(mcount);
         }
     }
 
