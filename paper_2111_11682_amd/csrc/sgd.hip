@@ -290,15 +290,18 @@ __global__ __launch_bounds__(kSgdWaves* kWave) void k_sgd_stratum(SgdArgs a, con
                     const uint32_t lw = (uint32_t)__builtin_amdgcn_readlane(lw_v, t);
                     const bool has_succ = (lw >> 31) != 0;
                     const int ws = has_succ ? (int)(lw & 0xFFFFu) : dummy;
+                    // wave-uniform destinations: the HBM row or a sink row
+                    float* urow = has_succ ? a.trash + kWave * FP : a.U + i * F;
+                    uint16_t* urow16 = has_succ ? reinterpret_cast<uint16_t*>(a.trash + 3 * kWave * FP) : a.U16 + i * F;
+                    float* mrow = mb_u + ws * F;
 #pragma unroll
                     for (int x = 0; x < FP; ++x) {
                         const int f = lane + x * kWave;
                         const float unew = usr ? u[t][x] + a.g[2] * (err * v[x] - a.l[2] * u[t][x]) : u[t][x];
-                        mb_u[f < F ? ws * F + f : dummy * F] = unew;
-                        *((!has_succ && f < F) ? a.U + i * F + f : a.trash + kWave * FP + f) = unew;
-                        if constexpr (BF) {
-                            uint16_t* sink = reinterpret_cast<uint16_t*>(a.trash + 3 * kWave * FP) + f;
-                            *((!has_succ && f < F) ? a.U16 + i * F + f : sink) = to_bf16(unew);
+                        if (f < F) {
+                            mrow[f] = unew;
+                            urow[f] = unew;
+                            if constexpr (BF) urow16[f] = to_bf16(unew);
                         }
                         const float vn = v[x] + a.g[3] * (err * u[t][x] - a.l[3] * v[x]);
                         v[x] = itm ? vn : v[x];
