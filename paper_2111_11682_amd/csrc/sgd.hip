@@ -27,11 +27,10 @@ constexpr int kGangWaves = kHelpers + 1;
 constexpr int kMaxGangs = 1;                     // gangs per block
 constexpr int kGangMin = 48;                     // shortest segment given a gang
 constexpr int kHG = 6;                           // ratings per helper pipeline stage
-constexpr int kFinLag = 1;                       // stages a helper prepares ahead of those it finishes
-// ring slots of a gang: a multiple of kHelpers, and more than kFinLag + 1
-// helper stages per helper, so that a helper reuses a slot only after
-// finishing it
-constexpr int kRing = ((kFinLag + 1) * kHG + 3) * kHelpers;
+// ring slots of a gang: a multiple of kHelpers, so that every slot belongs to
+// one helper, and 2 * kHG + 3 per helper, so that a helper can prepare two
+// stages ahead of the item wave
+constexpr int kRing = (2 * kHG + 3) * kHelpers;
 constexpr int kIG = 8;                           // ratings per item-wave group
 constexpr int kSpinLimit = 1 << 24;              // bounded wait: a broken hand-over ends the kernel
 constexpr int kMaxMailboxBytes = 150 * 1024;     // mailbox part of a block's dynamic LDS
@@ -149,7 +148,7 @@ __global__ __launch_bounds__(kSgdWaves* kWave) void k_sgd_stratum(SgdArgs a, con
         ngang = k + 1;
     }
     const int RS = a.ring_rs;
-    const int GS = kRing * (RS + 7);  // floats per gang: data, headers, ready, done, err
+    const int GS = kRing * (RS + 6);  // floats per gang: data, headers, ready, done
     float* rings = smem + a.ring_off;
     for (int x = threadIdx.x; x <= dummy; x += blockDim.x) mb_seq[x] = 0;
     for (int gi = 0; gi < ngang; ++gi) {
@@ -167,13 +166,13 @@ __global__ __launch_bounds__(kSgdWaves* kWave) void k_sgd_stratum(SgdArgs a, con
     if (wv < ngang * kGangWaves) {
         // Ring protocol.  Helper h prepares ratings n = h, h + H, ... into
         // slot n % kRing and sets ready; the item wave runs each group of kIG
-        // ratings, writes u_i's new row into the slot and the error beside it,
-        // then sets done for the group; helper h finishes its ratings (b_i, the
-        // user's row to HBM or to the mailbox) after preparing its next group.
-        // A slot is reused by the same helper kRing / H of its ratings later,
-        // after it finished the slot's previous rating.  The item wave waits
-        // only after publishing all it has done, and a helper waits only for
-        // ratings below those it has prepared, so every wait ends.
+        // ratings, writes each u_i's new row to the mailbox (the user rates
+        // again later in the block) or to HBM, then publishes b_i, the
+        // hand-over sequence numbers and done for the group.  A slot is
+        // reused by the same helper kRing / H of its ratings later, once the
+        // slot's previous rating is done.  The item wave waits only after
+        // publishing all it has done, and a helper waits only for ratings
+        // below those it prepares, so every wait ends.
         const int gang = wv / kGangWaves, role = wv % kGangWaves;
         const int64_t seg = g0 + gang;
         const int64_t j = a.seg_col[seg];
@@ -183,7 +182,6 @@ __global__ __launch_bounds__(kSgdWaves* kWave) void k_sgd_stratum(SgdArgs a, con
         int* rhdr = reinterpret_cast<int*>(rdata + kRing * RS);
         int* rready = rhdr + kRing * 4;
         int* rdone = rready + kRing;
-        float* rerr = reinterpret_cast<float*>(rdone + kRing);
         if (role == 0) {
             // ---- item wave: Eq. (rr) and Eq. (sgd_update) in stream order
             __builtin_amdgcn_s_setprio(3);
@@ -222,6 +220,9 @@ __global__ __launch_bounds__(kSgdWaves* kWave) void k_sgd_stratum(SgdArgs a, con
             float pu[kIG][FP], prw[kIG][KP], pcn[kIG][KP];
             float preff = 0.0f, pbi = 0.0f;  // lane t: r - mu - b_i and b_i of rating gs + t
             int pi = 0, plw = 0;               // lane t: user and hand-over word of rating gs + t
+            // The slot reads are unconditional and the lanes past F (or K)
+            // drop what they read: the next section of the slot, or past the
+            // last slot the ring headers, all inside the gang's LDS area.
             auto load_group = [&](int gs, int cnt) {
 #pragma unroll
                 for (int t = 0; t < kIG; ++t) {
@@ -229,13 +230,15 @@ __global__ __launch_bounds__(kSgdWaves* kWave) void k_sgd_stratum(SgdArgs a, con
 #pragma unroll
                     for (int x = 0; x < FP; ++x) {
                         const int f = lane + x * kWave;
-                        pu[t][x] = f < F ? d[f] : 0.0f;
+                        const float uv = d[f];
+                        pu[t][x] = f < F ? uv : 0.0f;
                     }
 #pragma unroll
                     for (int y = 0; y < KP; ++y) {
                         const int k = lane + y * kWave;
-                        prw[t][y] = k < K ? d[F + k] : 0.0f;
-                        pcn[t][y] = k < K ? d[F + K + k] : 0.0f;
+                        const float rv = d[F + k], cv = d[F + K + k];
+                        prw[t][y] = k < K ? rv : 0.0f;
+                        pcn[t][y] = k < K ? cv : 0.0f;
                     }
                 }
                 const int* hd = rhdr + ((gs + (lane < cnt ? lane : 0)) % kRing) * 4;
@@ -274,7 +277,6 @@ __global__ __launch_bounds__(kSgdWaves* kWave) void k_sgd_stratum(SgdArgs a, con
 #pragma unroll
                 for (int t = 0; t < kIG; ++t) {
                     if (t >= cnt) break;
-                    const int sl = (gs + t) % kRing;
                     const float reff = __builtin_bit_cast(
                         float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, reff_v), t));
                     float part = 0.0f;
@@ -306,7 +308,6 @@ __global__ __launch_bounds__(kSgdWaves* kWave) void k_sgd_stratum(SgdArgs a, con
                         const float vn = v[x] + a.g[3] * (err * u[t][x] - a.l[3] * v[x]);
                         v[x] = itm ? vn : v[x];
                     }
-                    (void)sl;
                     const float bh_new = bh + a.g[1] * (err - a.l[1] * bh);
                     bh = itm ? bh_new : bh;
 #pragma unroll
@@ -785,7 +786,7 @@ int refresh_bf16(lshmf_ctx* c, int64_t m0, int64_t m1, int64_t n0, int64_t n1, h
 // a sequence word) and the gang rings.
 static size_t sgd_lds_bytes(const SgdArgs& args)
 {
-    const size_t gs = (size_t)kRing * (args.ring_rs + 7);
+    const size_t gs = (size_t)kRing * (args.ring_rs + 6);
     return ((size_t)args.ring_off + (size_t)args.max_gangs * gs) * sizeof(float);
 }
 
