@@ -341,6 +341,49 @@ def test_sgd_step_is_half_gradient_of_sample_loss():
     del base
 
 
+def _hand_model_k0():
+    # the same ratings with K = 0: no neighbour term at all (biased MF)
+    u = np.array([0, 0, 1, 1], np.int32)
+    it = np.array([0, 1, 1, 2], np.int32)
+    rc = np.array([4, 2, 5, 3], np.uint8)
+    U0 = np.array([[1.0, 2.0], [0.5, -1.0]])
+    V0 = np.array([[0.2, 0.1], [-0.3, 0.4], [0.0, 0.5]])
+    return orc.Model(2, 3, 2, 0, 1, u, it, rc, np.zeros((3, 0), np.int32), U0, V0,
+                     bu0=np.array([0.1, -0.2]), bv0=np.array([0.3, 0.0, -0.1]))
+
+
+def test_k0_predict_is_biased_mf():
+    # With K = 0, Eq. (rr) keeps only mu + b_i + bh_j + u_i . v_j.
+    m = _hand_model_k0()
+    qu = np.array([0, 0, 0, 1, 1, 1])
+    qi = np.array([0, 1, 2, 0, 1, 2])
+    ref = 3.5 + np.array([0.1, 0.1, 0.1, -0.2, -0.2, -0.2]) + np.array([0.3, 0.0, -0.1] * 2) + \
+        np.array([0.4, 0.5, 1.0, 0.0, -0.55, -0.5])
+    assert np.allclose(m.predict(qu, qi), ref, rtol=0, atol=1e-14)
+
+
+def test_k0_sgd_step_is_half_gradient_of_sample_loss():
+    g = np.array([0.01, 0.02, 0.03, 0.04, 0.05, 0.06])
+    lam = np.array([0.1, 0.2, 0.3, 0.4, 0.5, 0.6])
+    for (i, j, r) in [(0, 1, 2), (1, 1, 5), (1, 2, 3), (0, 0, 4)]:
+        m0, m1 = _hand_model_k0(), _hand_model_k0()
+        m1.sgd_one(i, j, r, g, lam)
+        e = r - m0.predict([i], [j])[0]
+        for name, row, gi in [("bu", i, 0), ("bv", j, 1), ("U", i, 2), ("V", j, 3)]:
+            before, after = getattr(m0, name), getattr(m1, name)
+            idxs = [(row,)] if before.ndim == 1 else [(row, c) for c in range(before.shape[1])]
+            for idx in idxs:
+                h = 1e-6
+                mp, mm = _hand_model_k0(), _hand_model_k0()
+                getattr(mp, name)[idx] += h
+                getattr(mm, name)[idx] -= h
+                drhat = (mp.predict([i], [j])[0] - mm.predict([i], [j])[0]) / (2 * h)
+                theta = before[idx]
+                assert after[idx] == pytest.approx(theta - g[gi] * (-e * drhat + lam[gi] * theta),
+                                                   abs=1e-8), (name, idx)
+        assert np.array_equal(m1.U[1 - i], m0.U[1 - i])
+
+
 def test_sgd_frozen_sides():
     g = np.full(6, 0.05)
     lam = np.full(6, 0.1)
