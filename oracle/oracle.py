@@ -343,9 +343,10 @@ def online_update(m: "Model", acc, sig, B: int, G: int, p: int, q: int, seed_fil
     # 2. neighbour lists
     K = m.K
     JK2 = np.zeros((N2, K), np.int32)
-    JK2[: m.N] = m.JK
-    if N2 > m.N:
-        JK2[m.N:] = topk(sig2, B, G, p, q, K, seed_fill, items=np.arange(m.N, N2, dtype=np.int32))
+    if K > 0:   # K = 0: no neighbour lists
+        JK2[: m.N] = m.JK
+        if N2 > m.N:
+            JK2[m.N:] = topk(sig2, B, G, p, q, K, seed_fill, items=np.arange(m.N, N2, dtype=np.int32))
     # 3. baselines
     b02 = np.zeros(M2)
     b02[: m.M] = m.b0
