@@ -47,7 +47,8 @@ def sgd_bytes_per_epoch(nnz, nseg, F, K, nstride, storage="fp32"):
     return nnz * per_rating + nseg * per_seg
 
 
-SHAPE_NAMES = {"ml10m": "MovieLens-10M", "netflix": "Netflix", "ml100k": "MovieLens-100K"}
+SHAPE_NAMES = {"ml10m": "MovieLens-10M", "netflix": "Netflix", "ml100k": "MovieLens-100K",
+               "ml10m_k0": "MovieLens-10M", "ml100k_k0": "MovieLens-100K"}
 
 KERNEL_SOURCES = ("paper_2111_11682_amd/csrc/sgd.hip", "paper_2111_11682_amd/csrc/common.hpp",
                   "include/lshmf.h")
@@ -79,10 +80,11 @@ def profiled_traffic():
 
 def cpu_baseline(w, d, P, epochs=4):
     """The FP64 oracle's SGD on the same training set, a bounded number of epochs."""
+    import numpy as np
     from oracle import oracle as orc
     u, it, rc = d["train_u"], d["train_i"], d["train_rc"]
     _, sig = orc.simlsh(w.M, w.N, w.B, u, it, rc, d["H"])
-    JK = orc.topk(sig, w.B, w.G, w.p, w.q, w.K, 12345)
+    JK = orc.topk(sig, w.B, w.G, w.p, w.q, w.K, 12345) if w.K > 0 else np.zeros((w.N, 0), np.int32)
     m = orc.Model(w.M, w.N, w.F, w.K, w.rscale, u, it, rc, JK, d["U0"], d["V0"])
     m._sched[P] = orc.schedule(P, u, it)             # the layout, untimed
     t0 = time.perf_counter()
@@ -91,8 +93,9 @@ def cpu_baseline(w, d, P, epochs=4):
     dt = time.perf_counter() - t0
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {"value": float(epochs * u.size / dt), "unit": "updates/s", "cores": cores, "kind": "oracle",
-            "sample": "%d FP64 oracle SGD epochs (K-neighbour term, P=%d strata, OpenMP over the blocks "
-                      "of a stratum) over all %d training ratings, %.1f s" % (epochs, P, u.size, dt)}
+            "sample": "%d FP64 oracle SGD epochs (%s, P=%d strata, OpenMP over the blocks "
+                      "of a stratum) over all %d training ratings, %.1f s"
+                      % (epochs, "K-neighbour term" if w.K > 0 else "K = 0, no neighbour term", P, u.size, dt)}
 
 
 def serve_main(args, w, d):
@@ -278,7 +281,8 @@ def main():
 
     value = epochs * nnz / (ms / 1e3)
     out = {
-        "metric": "rating SGD updates/sec (K-neighbour term incl.)",
+        "metric": ("rating SGD updates/sec (K-neighbour term incl.)" if w.K > 0
+                   else "rating SGD updates/sec (biased MF, K = 0)"),
         "value": round(value, 1),
         "unit": "updates/s",
         "n_gpus": 1,
@@ -290,7 +294,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic (seeded Zipf/lognormal ratings with planted structure, %s shape)" % SHAPE_NAMES.get(w.name, w.name),
-        "config": {"workload": "%s-shaped LSH-MF training job" % w.name, "users": w.M, "items": w.N,
+        "config": {"workload": ("%s-shaped LSH-MF training job" % w.name if w.K > 0
+                               else "%s-shaped biased-MF training job (K = 0)" % w.name[:-3]), "users": w.M, "items": w.N,
                    "train_ratings": int(nnz), "test_ratings": int(d["test_u"].size), "F": w.F,
                    "K": w.K, "hash_bits": w.B, "p": w.p, "q": w.q, "epochs": epochs,
                    "n_strata": P, "storage": args.storage, "heldout_rmse": round(final_rmse, 6),

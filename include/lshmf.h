@@ -46,7 +46,8 @@ enum { LSHMF_FP32 = 0, LSHMF_BF16 = 1 };
 typedef struct lshmf_dims {
     int32_t M, N;      /* users, items                                       */
     int32_t F;         /* rank of U (M x F) and V (N x F), 1..256            */
-    int32_t K;         /* neighbours per item, 1..128, K <= N - 1            */
+    int32_t K;         /* neighbours per item, 0..128, K <= N - 1; K = 0 is  */
+                       /* biased MF without the neighbour term (no w, c)     */
     int32_t G, p, q;   /* simLSH: G bits per hash, p hashes ANDed per band,
                           q bands ORed (Sec. 4.1); B = G*p*q <= 256 bits,
                           band width p*G <= 32                               */
@@ -92,7 +93,8 @@ typedef struct lshmf_hparams {
  * BF16 bit patterns (round to nearest even) of the FP32 tables above, which
  * stay the masters that SGD reads and writes.  Every call that changes a
  * master row also rewrites its BF16 copy; predict reads the copies.  The
- * pointers are ignored in mode LSHMF_FP32. */
+ * pointers are ignored in mode LSHMF_FP32.  With K = 0, W, C, JK, W16 and C16
+ * hold nothing and may be NULL. */
 typedef struct lshmf_tables {
     float* U;
     float* V;
@@ -142,7 +144,7 @@ int lshmf_ingest(lshmf_ctx* ctx, const int32_t* d_u, const int32_t* d_i, const u
  * mod N, a = 0, 1, ...), rows stored by ascending id.  d_H holds the random
  * user strings H_i, M rows of ceil(B/32) uint32 words.  Also resolves, for
  * every training rating (i, j), which neighbours of j user i has rated.
- * Requires lshmf_ingest. */
+ * With K = 0 only acc and sig are computed.  Requires lshmf_ingest. */
 int build_lsh_neighbours(lshmf_ctx* ctx, const uint32_t* d_H, uint64_t seed_fill,
                          lshmf_stream_t stream);
 

@@ -122,8 +122,8 @@ int validate(const lshmf_dims* d)
         set_error("F=%d outside 1..256", d->F);
         return LSHMF_EINVAL;
     }
-    if (d->K < 1 || d->K > 128 || d->K > d->N - 1) {
-        set_error("K=%d outside 1..min(128, N-1)", d->K);
+    if (d->K < 0 || d->K > 128 || d->K > d->N - 1) {
+        set_error("K=%d outside 0..min(128, N-1)", d->K);
         return LSHMF_EINVAL;
     }
     if (d->G < 1 || d->p < 1 || d->q < 1 || B > 256 || (int64_t)d->G * d->p > 32 || d->q > 2048) {
@@ -229,12 +229,14 @@ int lshmf_bind(lshmf_ctx* ctx, const lshmf_tables* t, void* d_arena, size_t aren
         set_error("NULL argument");
         return LSHMF_EINVAL;
     }
-    if (!t->U || !t->V || !t->bu || !t->bv || !t->W || !t->C || !t->JK || !t->acc || !t->sig || !t->b0 ||
-        !t->bh0 || !t->mu) {
+    // with K = 0 the neighbour tables hold nothing and may be NULL
+    const bool nbr = ctx->d.K > 0;
+    if (!t->U || !t->V || !t->bu || !t->bv || (nbr && (!t->W || !t->C || !t->JK)) || !t->acc || !t->sig ||
+        !t->b0 || !t->bh0 || !t->mu) {
         set_error("a table pointer is NULL");
         return LSHMF_EINVAL;
     }
-    if (ctx->d.storage == LSHMF_BF16 && (!t->U16 || !t->V16 || !t->W16 || !t->C16)) {
+    if (ctx->d.storage == LSHMF_BF16 && (!t->U16 || !t->V16 || (nbr && (!t->W16 || !t->C16)))) {
         set_error("storage mode BF16 needs the U16, V16, W16 and C16 tables");
         return LSHMF_EINVAL;
     }

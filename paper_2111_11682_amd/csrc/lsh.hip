@@ -378,6 +378,7 @@ int signs(lshmf_ctx* c, hipStream_t s)
 int neighbours_for(lshmf_ctx* c, int32_t j_first, int32_t count, uint64_t seed_fill, hipStream_t s)
 {
     const lshmf_dims& d = c->d;
+    if (d.K == 0) return LSHMF_OK;  // no neighbour lists to find
     const int64_t nq = (int64_t)d.q * c->N;
     hipLaunchKernelGGL(k_band_keys, dim3(grid_for(nq)), dim3(256), 0, s, c->t.sig, c->N, c->words, c->pG, d.q,
                        c->sk[0], c->sv[0]);
@@ -410,7 +411,7 @@ int neighbours_for(lshmf_ctx* c, int32_t j_first, int32_t count, uint64_t seed_f
 // Neighbour codes of every rating of a stream (R^K / N^K resolution).
 int stream_codes(lshmf_ctx* c, Stream& st, hipStream_t s)
 {
-    if (st.n > 0) {
+    if (st.n > 0 && c->d.K > 0) {
         hipLaunchKernelGGL(k_nbr_codes, dim3(grid_for(st.n * kWave, 256, 65536)), dim3(256), 0, s, st.pk, st.sj,
                            st.n, c->t.JK, c->d.K, c->row_ptr, c->csr_col, c->csr_rc, st.nib, c->nstride);
         LSHMF_LAUNCHED("k_nbr_codes");

@@ -826,7 +826,8 @@ int run_sgd(lshmf_ctx* c, Stream& st, const lshmf_hparams* hp, int epoch, int up
         return LSHMF_ECAPACITY;
     }
     SgdArgs a;
-    a.nib = st.nib;
+    // K = 0: no codes; the kernel's clamped code reads then land on the sink
+    a.nib = c->nstride > 0 ? st.nib : reinterpret_cast<const uint8_t*>(c->trash);
     a.blk_ptr = st.blk_ptr;
     a.blk_seg = st.blk_seg;
     a.seg_col = st.seg_col;

@@ -108,6 +108,11 @@ WORKLOADS: Dict[str, Workload] = {
                      _ML_ALPHA, _ML_LAM, 0.3, n_strata=12),
 }
 
+# The same workloads with K = 0: biased MF without the neighbour term, on the
+# same data (isolates the cost and the effect of the K-neighbour term).
+for _name in ("tiny", "ml100k", "ml10m"):
+    WORKLOADS[_name + "_k0"] = dataclasses.replace(WORKLOADS[_name], name=_name + "_k0", K=0)
+
 
 def derive_seed(*parts: int) -> int:
     """Independent sub-stream seeds from the master seed (numpy SeedSequence)."""

@@ -30,7 +30,7 @@ def _create(**kw):
     return st, h
 
 
-@pytest.mark.parametrize("bad", [dict(K=0), dict(K=1682), dict(K=129), dict(F=0), dict(F=257),
+@pytest.mark.parametrize("bad", [dict(K=-1), dict(K=1682), dict(K=129), dict(F=0), dict(F=257),
                                  dict(G=8, p=5, q=1), dict(G=8, p=1, q=33), dict(rscale=3),
                                  dict(psi_exp=0), dict(n_strata=0), dict(storage=2),
                                  dict(nnz=-1), dict(M=0), dict(N=1), dict(M_cap=900),
@@ -63,6 +63,27 @@ def test_arena_size_and_bind_checks():
     assert lshmf.lib().sgd_epoch(h, None, 0, None) == -2
     assert lshmf.lib().online_update(h, None, None, None, 0, 943, 1682, None, 0, None, 0, 1,
                                      None) == -2
+    lshmf.lib().lshmf_destroy(h)
+
+
+def test_k0_binds_without_neighbour_tables():
+    # K = 0 (no neighbour term): W, C, JK and their BF16 copies may be NULL;
+    # with K > 0 they may not.  A one-byte-short arena then gives ECAPACITY.
+    for storage in (0, 1):
+        st, h = _create(K=0, storage=storage)
+        assert st == 0
+        n = C.c_size_t()
+        assert lshmf.lib().lshmf_arena_bytes(h, C.byref(n)) == 0
+        ptr = [4096] * 16
+        for x in (4, 5, 6, 14, 15):   # W, C, JK, W16, C16
+            ptr[x] = 0
+        t = lshmf.Tables(*ptr)
+        assert lshmf.lib().lshmf_bind(h, C.byref(t), C.c_void_p(4096), n.value - 1) == -3
+        lshmf.lib().lshmf_destroy(h)
+    st, h = _create(K=10)
+    n = C.c_size_t()
+    assert lshmf.lib().lshmf_arena_bytes(h, C.byref(n)) == 0
+    assert lshmf.lib().lshmf_bind(h, C.byref(t), C.c_void_p(4096), n.value - 1) == -1
     lshmf.lib().lshmf_destroy(h)
 
 
