@@ -92,7 +92,8 @@ typedef struct lshmf_hparams {
  * Storage mode LSHMF_BF16 adds U16 [M*F], V16 [N*F], W16 [N*K], C16 [N*K]:
  * BF16 bit patterns (round to nearest even) of the FP32 tables above, which
  * stay the masters that SGD reads and writes.  Every call that changes a
- * master row also rewrites its BF16 copy; predict reads the copies.  The
+ * master row also rewrites its BF16 copy before it returns (one conversion
+ * pass over the tables after the SGD); predict reads the copies.  The
  * pointers are ignored in mode LSHMF_FP32.  With K = 0, W, C, JK, W16 and C16
  * hold nothing and may be NULL. */
 typedef struct lshmf_tables {

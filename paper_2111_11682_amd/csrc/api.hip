@@ -312,7 +312,9 @@ int sgd_epoch(lshmf_ctx* ctx, const lshmf_hparams* hp, int32_t epoch, lshmf_stre
         ctx->train_stale = false;
     }
     if (!ctx->train.codes) LSHMF_TRY(stream_codes(ctx, ctx->train, s));
-    return run_sgd(ctx, ctx->train, hp, epoch, 3, s);
+    LSHMF_TRY(run_sgd(ctx, ctx->train, hp, epoch, 3, s));
+    // the SGD writes only the FP32 masters; the BF16 copies follow in one pass
+    return refresh_bf16(ctx, 0, ctx->M, 0, ctx->N, s);
 }
 
 int online_update(lshmf_ctx* ctx, const int32_t* d_u, const int32_t* d_i, const uint8_t* d_rc, int64_t n,

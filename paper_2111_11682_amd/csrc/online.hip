@@ -105,7 +105,6 @@ int run_online(lshmf_ctx* c, const int32_t* u, const int32_t* it, const uint8_t*
     LSHMF_TRY(fill_f32(c->t.bv + N_old, N_new - N_old, 0.0f, s));
     LSHMF_TRY(fill_f32(c->t.W + (int64_t)N_old * K, (int64_t)(N_new - N_old) * K, 0.0f, s));
     LSHMF_TRY(fill_f32(c->t.C + (int64_t)N_old * K, (int64_t)(N_new - N_old) * K, 0.0f, s));
-    LSHMF_TRY(refresh_bf16(c, M_old, M_new, N_old, N_new, s));
 
     // 3. fixed baselines of the new ids (before the neighbour baselines read them)
     LSHMF_TRY(baselines_new(c, u, rc, n, M_old, M_new - M_old, c->t.b0, s));
@@ -143,6 +142,8 @@ int run_online(lshmf_ctx* c, const int32_t* u, const int32_t* it, const uint8_t*
     static const int kUpd[3] = {1, 2, 3};  // user side, item side, both
     for (int p = 0; p < passes; ++p)
         for (int k = 0; k < 3; ++k) LSHMF_TRY(run_sgd(c, c->phase[k], hp, epoch, kUpd[k], s));
+    // BF16 copies of the FP32 masters, in one pass after the SGD
+    LSHMF_TRY(refresh_bf16(c, 0, M_new, 0, N_new, s));
     c->neighbours = true;
     return LSHMF_OK;
 }

@@ -54,10 +54,6 @@ struct SgdArgs {
     float* bv;
     float* W;
     float* C;
-    uint16_t* U16;    // BF16 serving copies (storage mode BF16 only)
-    uint16_t* V16;
-    uint16_t* W16;
-    uint16_t* C16;
     float* trash;
     int32_t* err;
     int F, K, P, nstride, s, slots;
@@ -121,8 +117,7 @@ struct HStage {
     uint32_t pw[kHG], lw[kHG];
 };
 
-// BF: also keep the BF16 copies of the rows the kernel writes.
-template <int FP, int KP, bool BF>
+template <int FP, int KP>
 __global__ __launch_bounds__(kSgdWaves* kWave) void k_sgd_stratum(SgdArgs a, const uint32_t* __restrict__ pk,
                                                                    const uint32_t* __restrict__ link)
 {
@@ -294,7 +289,6 @@ __global__ __launch_bounds__(kSgdWaves* kWave) void k_sgd_stratum(SgdArgs a, con
                     const int ws = has_succ ? (int)(lw & 0xFFFFu) : dummy;
                     // wave-uniform destinations: the HBM row or a sink row
                     float* urow = has_succ ? a.trash + kWave * FP : a.U + i * F;
-                    uint16_t* urow16 = has_succ ? reinterpret_cast<uint16_t*>(a.trash + 3 * kWave * FP) : a.U16 + i * F;
                     float* mrow = mb_u + ws * F;
 #pragma unroll
                     for (int x = 0; x < FP; ++x) {
@@ -303,7 +297,6 @@ __global__ __launch_bounds__(kSgdWaves* kWave) void k_sgd_stratum(SgdArgs a, con
                         if (f < F) {
                             mrow[f] = unew;
                             urow[f] = unew;
-                            if constexpr (BF) urow16[f] = to_bf16(unew);
                         }
                         const float vn = v[x] + a.g[3] * (err * u[t][x] - a.l[3] * v[x]);
                         v[x] = itm ? vn : v[x];
@@ -350,7 +343,6 @@ __global__ __launch_bounds__(kSgdWaves* kWave) void k_sgd_stratum(SgdArgs a, con
                 const int f = lane + x * kWave;
                 if (f < F) {
                     a.V[j * F + f] = v[x];
-                    if constexpr (BF) a.V16[j * F + f] = to_bf16(v[x]);
                 }
             }
             if (lane == 0) a.bv[j] = bh;
@@ -360,10 +352,6 @@ __global__ __launch_bounds__(kSgdWaves* kWave) void k_sgd_stratum(SgdArgs a, con
                 if (k < K) {
                     a.W[j * K + k] = w[y];
                     a.C[j * K + k] = c[y];
-                    if constexpr (BF) {
-                        a.W16[j * K + k] = to_bf16(w[y]);
-                        a.C16[j * K + k] = to_bf16(c[y]);
-                    }
                 }
             }
         } else {
@@ -674,10 +662,6 @@ __global__ __launch_bounds__(kSgdWaves* kWave) void k_sgd_stratum(SgdArgs a, con
                     const int f = lane + x * kWave;
                     const float unew = usr ? u[x] + a.g[2] * (err * v[x] - a.l[2] * u[x]) : u[x];
                     *((to_hbm && f < F) ? a.U + i * F + f : a.trash + kWave * FP + f) = unew;
-                    if constexpr (BF) {
-                        uint16_t* sink = reinterpret_cast<uint16_t*>(a.trash + 3 * kWave * FP) + f;
-                        *((to_hbm && f < F) ? a.U16 + i * F + f : sink) = to_bf16(unew);
-                    }
                     mb_u[f < F ? ws * F + f : dummy * F] = unew;
                     const float vn = v[x] + a.g[3] * (err * u[x] - a.l[3] * v[x]);
                     v[x] = (valid && itm) ? vn : v[x];
@@ -734,7 +718,6 @@ __global__ __launch_bounds__(kSgdWaves* kWave) void k_sgd_stratum(SgdArgs a, con
             const int f = lane + x * kWave;
             if (f < F) {
                 a.V[j * F + f] = v[x];
-                if constexpr (BF) a.V16[j * F + f] = to_bf16(v[x]);
             }
         }
         if (lane == 0) a.bv[j] = bh;
@@ -744,10 +727,6 @@ __global__ __launch_bounds__(kSgdWaves* kWave) void k_sgd_stratum(SgdArgs a, con
             if (k < K) {
                 a.W[j * K + k] = w[y];
                 a.C[j * K + k] = c[y];
-                if constexpr (BF) {
-                    a.W16[j * K + k] = to_bf16(w[y]);
-                    a.C16[j * K + k] = to_bf16(c[y]);
-                }
             }
         }
     }
@@ -790,27 +769,25 @@ static size_t sgd_lds_bytes(const SgdArgs& args)
     return ((size_t)args.ring_off + (size_t)args.max_gangs * gs) * sizeof(float);
 }
 
-template <int FP, int KP, bool BF>
+template <int FP, int KP>
 static int launch_sgd(const SgdArgs& args, const uint32_t* pk, const uint32_t* link, hipStream_t s)
 {
     const size_t lds = sgd_lds_bytes(args);
     if (lds > 64 * 1024) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sgd_stratum<FP, KP, BF>),
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sgd_stratum<FP, KP>),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return hip_fail(e, "hipFuncSetAttribute(k_sgd_stratum)");
     }
-    hipLaunchKernelGGL((k_sgd_stratum<FP, KP, BF>), dim3((unsigned)args.P), dim3(kSgdWaves * kWave), lds, s, args,
+    hipLaunchKernelGGL((k_sgd_stratum<FP, KP>), dim3((unsigned)args.P), dim3(kSgdWaves * kWave), lds, s, args,
                        pk, link);
     LSHMF_LAUNCHED("k_sgd_stratum");
     return LSHMF_OK;
 }
 
 template <int FP>
-static int launch_sgd_k(const SgdArgs& args, bool bf, const uint32_t* pk, const uint32_t* link, hipStream_t s)
+static int launch_sgd_k(const SgdArgs& args, const uint32_t* pk, const uint32_t* link, hipStream_t s)
 {
-    if (bf)
-        return args.K <= kWave ? launch_sgd<FP, 1, true>(args, pk, link, s) : launch_sgd<FP, 2, true>(args, pk, link, s);
-    return args.K <= kWave ? launch_sgd<FP, 1, false>(args, pk, link, s) : launch_sgd<FP, 2, false>(args, pk, link, s);
+    return args.K <= kWave ? launch_sgd<FP, 1>(args, pk, link, s) : launch_sgd<FP, 2>(args, pk, link, s);
 }
 
 // One SGD pass over a stream; upd selects the parameter sides to update.
@@ -841,10 +818,6 @@ int run_sgd(lshmf_ctx* c, Stream& st, const lshmf_hparams* hp, int epoch, int up
     a.bv = c->t.bv;
     a.W = c->t.W;
     a.C = c->t.C;
-    a.U16 = c->t.U16;
-    a.V16 = c->t.V16;
-    a.W16 = c->t.W16;
-    a.C16 = c->t.C16;
     a.trash = c->trash;
     a.err = c->err;
     a.F = d.F;
@@ -866,14 +839,13 @@ int run_sgd(lshmf_ctx* c, Stream& st, const lshmf_hparams* hp, int epoch, int up
         a.l[x] = hp->lambda[x];
     }
     const int fp = (d.F + kWave - 1) / kWave;
-    const bool bf = d.storage == LSHMF_BF16;
     for (int stratum = 0; stratum < c->P; ++stratum) {
         a.s = stratum;
         switch (fp) {
-            case 1: LSHMF_TRY(launch_sgd_k<1>(a, bf, st.pk, st.link, s)); break;
-            case 2: LSHMF_TRY(launch_sgd_k<2>(a, bf, st.pk, st.link, s)); break;
-            case 3: LSHMF_TRY(launch_sgd_k<3>(a, bf, st.pk, st.link, s)); break;
-            default: LSHMF_TRY(launch_sgd_k<4>(a, bf, st.pk, st.link, s)); break;
+            case 1: LSHMF_TRY(launch_sgd_k<1>(a, st.pk, st.link, s)); break;
+            case 2: LSHMF_TRY(launch_sgd_k<2>(a, st.pk, st.link, s)); break;
+            case 3: LSHMF_TRY(launch_sgd_k<3>(a, st.pk, st.link, s)); break;
+            default: LSHMF_TRY(launch_sgd_k<4>(a, st.pk, st.link, s)); break;
         }
     }
     return LSHMF_OK;
