@@ -36,14 +36,11 @@ def sgd_bytes_per_epoch(nnz, nseg, F, K, nstride, storage="fp32"):
     nstride + u_i read and write 8F + b_i read and write 8 + fixed baseline
     b0_i 4.  Per item segment (a run of one item inside a block): v_j read and
     write 8F, bh_j read and write 8, w_j and c_j read and write 16K, the fixed
-    baselines of the K neighbours 4K, segment descriptor 12.  BF16 storage adds
-    the BF16 copies written: 2F per rating, 2F + 4K per segment.
+    baselines of the K neighbours 4K, segment descriptor 12.  The kernel is
+    the same in both storage modes (BF16 copies are converted after it).
     """
     per_rating = 4 + 4 + nstride + 8 * F + 8 + 4
     per_seg = 8 * F + 8 + 16 * K + 4 * K + 12
-    if storage == "bf16":
-        per_rating += 2 * F
-        per_seg += 2 * F + 4 * K
     return nnz * per_rating + nseg * per_seg
 
 
