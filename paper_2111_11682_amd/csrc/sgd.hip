@@ -9,8 +9,8 @@
 // own features f = lane + 64x and neighbour slots k = lane + 64y, so u.v, the
 // explicit w-sum and the implicit c-sum of Eq. (rr) fold into ONE 64-lane
 // reduction.  The block's first run, when long, is split between an item
-// wave that runs only the dependent update chain and helper waves that
-// prepare and finish the user side (a gang, below).  Blocks of a stratum
+// wave that runs only the dependent update chain and helper waves that load
+// and prepare the user side (a gang, below).  Blocks of a stratum
 // share no user and no item; inside a block, a rating waits (LDS mailbox with
 // sequence numbers) for the previous rating of the same user, which makes the
 // result identical to running the block's ratings in order.
