@@ -187,7 +187,7 @@ def main():
     if args.storage is None:
         args.storage = "bf16" if args.mode == "serve" else "fp32"
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
