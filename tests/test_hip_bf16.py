@@ -140,6 +140,9 @@ def test_bf16_online_keeps_copies():
     m.online_update(su, si, src, w.M, w.N, H, SEED_FILL, w.alpha, w.lam, w.beta, 1, 1,
                     U_new=torch.from_numpy(d["U0"][M0:]).to(dev),
                     V_new=torch.from_numpy(d["V0"][N0:]).to(dev))
+    torch.cuda.synchronize()
+    assert m.device_status() == 0
+    _copies_are_rne(m)          # online_update ends with the copies rewritten
     m.sgd_epoch(w.alpha, w.lam, w.beta, 2)
     torch.cuda.synchronize()
     assert m.device_status() == 0

@@ -97,6 +97,30 @@ def test_k0_full_run_rmse_ml100k():
     assert abs(r_gpu - r_orc) <= 0.005 * r_orc
 
 
+def test_k0_bf16_copies():
+    # K = 0 with BF16 storage: no W16 / C16 to keep; U16, V16 are the RNE
+    # images of the masters after an epoch, and the masters equal FP32 mode's
+    from paper_2111_11682_amd import lshmf
+    w = synth.WORKLOADS["ml100k_k0"]
+    d = synth.generate(w)
+    runs = {}
+    for storage in ("fp32", "bf16"):
+        m = lshmf.LshMF(w.M, w.N, w.F, 0, w.G, w.p, w.q, w.rscale, d["train_u"].size,
+                        n_strata=w.n_strata, storage=storage)
+        dev = m.device
+        m.ingest(*[torch.from_numpy(d[k]).to(dev) for k in ("train_u", "train_i", "train_rc")])
+        m.set_factors(torch.from_numpy(d["U0"]).to(dev), torch.from_numpy(d["V0"]).to(dev))
+        m.build_lsh_neighbours(torch.from_numpy(d["H"].view(np.int32)).to(dev), SEED_FILL)
+        m.sgd_epoch(w.alpha, w.lam, w.beta, 0)
+        torch.cuda.synchronize()
+        assert m.device_status() == 0
+        runs[storage] = m
+    a, b = runs["fp32"], runs["bf16"]
+    assert torch.equal(a.U, b.U) and torch.equal(a.V, b.V)
+    for master, copy in ((b.U, b.U16), (b.V, b.V16)):
+        assert torch.equal(copy.cpu().view(torch.int16), master.cpu().to(torch.bfloat16).view(torch.int16))
+
+
 def test_k0_online_update():
     from paper_2111_11682_amd import lshmf
     w = synth.WORKLOADS["tiny_k0"]
