@@ -20,11 +20,11 @@
 
 namespace lshmf {
 
-constexpr int kSgdWaves = 12;
+constexpr int kSgdWaves = 16;
 constexpr int kGroup = 4;                        // ratings per pipeline stage
-constexpr int kHelpers = 5;                      // helper waves of a gang
+constexpr int kHelpers = 4;                      // helper waves of a gang
 constexpr int kGangWaves = kHelpers + 1;
-constexpr int kMaxGangs = 1;                     // gangs per block
+constexpr int kMaxGangs = 2;                     // gangs per block
 constexpr int kGangMin = 48;                     // shortest segment given a gang
 constexpr int kHG = 6;                           // ratings per helper pipeline stage
 // ring slots of a gang: a multiple of kHelpers, so that every slot belongs to
