@@ -20,6 +20,11 @@
  *   - objective ............................ Eq. (loss_r)
  *   - RMSE ................................. Sec. 5.1
  *   - online update ........................ Sec. 4.3, Alg. "Online Learning"
+ *   - neighbour-list rebuild with w, c
+ *     following their neighbour ids ........ a reading (the paper keeps old
+ *                                            lists; see orc_remap_slots)
+ *   - RP_cos and minHash hash families ..... Sec. 5.3, the top-K comparison
+ *                                            (Table of top-K methods)
  *
  * Readings where the paper is silent are documented next to the code that
  * takes them.  Random numbers: the user hash strings H_i and the initial
@@ -27,6 +32,7 @@
  * SplitMix64 (Steele, Lea, Flood 2014), written here from its definition.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -45,6 +51,10 @@ uint64_t orc_splitmix64(uint64_t seed, uint64_t c)
     z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
     return z ^ (z >> 31);
 }
+
+/* OpenMP threads of the parallel loops (timing on one thread or all).      */
+void orc_set_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
+int orc_max_threads(void) { return omp_get_max_threads(); }
 
 /* ------------------------------------------------------------------------ */
 /* simLSH coding, Sec. 4.1 Eq. (item_hash).                                 */
@@ -196,6 +206,128 @@ int orc_topk(int N, int B, int G, int p, int q, int K, const uint32_t* sig,
     }
     free(keys);
     return status;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Neighbour-list rebuild (a reading; the paper keeps the lists of existing  */
+/* items, Sec. 4.3).  When the lists of all items are searched again, each  */
+/* item's w and c values follow their neighbour ids: a neighbour kept       */
+/* across the rebuild brings its w_{j,k}, c_{j,k} to its new slot, and a    */
+/* slot whose neighbour is new starts at 0.  Rows j >= n_old are new items  */
+/* and start at 0.  Lists are sorted by id, so the search is a merge.       */
+/* ------------------------------------------------------------------------ */
+int orc_remap_slots(int N, int n_old, int K, const int32_t* JK_old, const double* W_old,
+                    const double* C_old, const int32_t* JK_new, double* W_new, double* C_new)
+{
+    if (K <= 0 || n_old < 0 || n_old > N) return ORC_EINVAL;
+    for (int j = 0; j < N; ++j)
+        for (int k = 0; k < K; ++k) {
+            double w = 0.0, c = 0.0;
+            if (j < n_old) {
+                const int n = JK_new[(int64_t)j * K + k];
+                for (int k2 = 0; k2 < K; ++k2)
+                    if (JK_old[(int64_t)j * K + k2] == n) {
+                        w = W_old[(int64_t)j * K + k2];
+                        c = C_old[(int64_t)j * K + k2];
+                        break;
+                    }
+            }
+            W_new[(int64_t)j * K + k] = w;
+            C_new[(int64_t)j * K + k] = c;
+        }
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* The two other LSH families of the top-K comparison, Sec. 5.3.  Both fill */
+/* the same signature layout as simLSH (B = G*p*q bits, hash h of band t at */
+/* bits [(t*p + h)*G, (t*p + h + 1)*G)), so banding and top-K are shared.   */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    int32_t j, i;
+    int64_t idx;
+} orc_colent;
+
+static int cmp_col_user(const void* a, const void* b)
+{
+    const orc_colent* x = (const orc_colent*)a;
+    const orc_colent* y = (const orc_colent*)b;
+    if (x->j != y->j) return (x->j > y->j) - (x->j < y->j);
+    return (x->i > y->i) - (x->i < y->i);
+}
+
+/* RP_cos: sign random projection for the cosine similarity (Charikar's     */
+/* simHash, the hash simLSH is modelled on).  Item column x_j holds the      */
+/* plain ratings r_ij; each of the B bits projects it on a Gaussian          */
+/* direction g_.b:  acc[j][b] = sum_i r_ij g_ib,  bit b = [acc >= 0].        */
+/* The sign is an integer decided by floating point, so this follows the    */
+/* kernel's precision and order: FP32, one fused multiply-add per rating,   */
+/* the raters of a column in ascending user id, continuing the stored sum   */
+/* (an online batch adds its own raters of the column, ascending).          */
+int orc_rpcos_add(int M, int N, int B, int64_t nnz, const int32_t* u, const int32_t* it,
+                  const uint8_t* rc, int rscale, const float* g /* M*B */, float* acc /* N*B */)
+{
+    if (M <= 0 || N <= 0 || B <= 0 || nnz < 0 || rscale <= 0) return ORC_EINVAL;
+    orc_colent* e = (orc_colent*)malloc(sizeof(orc_colent) * (size_t)(nnz > 0 ? nnz : 1));
+    if (!e) return ORC_ENOMEM;
+    for (int64_t x = 0; x < nnz; ++x) {
+        if (u[x] < 0 || u[x] >= M || it[x] < 0 || it[x] >= N) { free(e); return ORC_EINVAL; }
+        e[x].j = it[x]; e[x].i = u[x]; e[x].idx = x;
+    }
+    qsort(e, (size_t)nnz, sizeof(orc_colent), cmp_col_user);
+    for (int64_t x = 0; x < nnz; ++x) {
+        const float r = (float)rc[e[x].idx] / (float)rscale;   /* exact: rc <= 15, rscale 1 or 2 */
+        float* a = acc + (int64_t)e[x].j * B;
+        const float* gi = g + (int64_t)e[x].i * B;
+        for (int b = 0; b < B; ++b) a[b] = fmaf(r, gi[b], a[b]);
+    }
+    free(e);
+    return ORC_OK;
+}
+
+void orc_rpcos_signs(int N, int B, const float* acc, uint32_t* sig)
+{
+    const int words = (B + 31) / 32;
+    memset(sig, 0, sizeof(uint32_t) * (size_t)N * words);
+    for (int j = 0; j < N; ++j)
+        for (int b = 0; b < B; ++b)
+            if (acc[(int64_t)j * B + b] >= 0.0f) sig[(int64_t)j * words + b / 32] |= 1u << (b % 32);
+}
+
+/* minHash (Broder) for the Jaccard similarity of the rater sets, which the */
+/* paper contrasts with simLSH in Sec. 4.1: hash h of item j is the least   */
+/* random value v_ih over its raters (a random permutation of the users).   */
+/* mins must start at 0xFFFFFFFF, the value of an item without raters;     */
+/* adding ratings only lowers it, so an online batch continues it.          */
+int orc_minhash_add(int M, int N, int nh, int64_t nnz, const int32_t* u, const int32_t* it,
+                    const uint32_t* v /* M*nh */, uint32_t* mins /* N*nh */)
+{
+    if (M <= 0 || N <= 0 || nh <= 0 || nnz < 0) return ORC_EINVAL;
+    for (int64_t x = 0; x < nnz; ++x) {
+        const int i = u[x], j = it[x];
+        if (i < 0 || i >= M || j < 0 || j >= N) return ORC_EINVAL;
+        for (int h = 0; h < nh; ++h) {
+            const uint32_t val = v[(int64_t)i * nh + h];
+            if (val < mins[(int64_t)j * nh + h]) mins[(int64_t)j * nh + h] = val;
+        }
+    }
+    return ORC_OK;
+}
+
+/* The G-bit hash is the lowest G bits of the minimum (b-bit minwise         */
+/* hashing, Li and Konig 2010): hash h fills bits [h*G, (h+1)*G), LSB first. */
+int orc_minhash_sig(int N, int nh, int G, const uint32_t* mins, uint32_t* sig)
+{
+    if (G < 1 || G > 32) return ORC_EINVAL;
+    const int B = nh * G, words = (B + 31) / 32;
+    memset(sig, 0, sizeof(uint32_t) * (size_t)N * words);
+    for (int j = 0; j < N; ++j)
+        for (int h = 0; h < nh; ++h)
+            for (int x = 0; x < G; ++x) {
+                const int b = h * G + x;
+                if ((mins[(int64_t)j * nh + h] >> x) & 1u) sig[(int64_t)j * words + b / 32] |= 1u << (b % 32);
+            }
+    return ORC_OK;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -493,14 +625,14 @@ int orc_schedule(int P, int64_t nnz, const int32_t* u, const int32_t* it,
 /* One epoch (Alg. CULSH-MF's inner loops) in the stratified order.           */
 /* reverse_blocks runs the blocks of each stratum in descending b: the result */
 /* must not change, since the blocks are independent.                          */
-int orc_sgd_epoch(orc_model* m, const orc_csr* R, int64_t nnz, const int32_t* u,
-                  const int32_t* it, const uint8_t* rc, const int64_t* order,
-                  const int64_t* blk_ptr, int P, const orc_rates* h, int reverse_blocks,
-                  int upd)
+/* Strata [s0, s1) of that order: a bounded sample of an epoch (timing).   */
+int orc_sgd_strata(orc_model* m, const orc_csr* R, const int32_t* u, const int32_t* it,
+                   const uint8_t* rc, const int64_t* order, const int64_t* blk_ptr, int P, int s0,
+                   int s1, const orc_rates* h, int reverse_blocks, int upd)
 {
     int status = ORC_OK;
-    (void)nnz;
-    for (int s = 0; s < P; ++s) {
+    if (s0 < 0 || s1 > P || s0 > s1) return ORC_EINVAL;
+    for (int s = s0; s < s1; ++s) {
         /* the blocks of one stratum touch disjoint users and items */
 #pragma omp parallel for schedule(dynamic, 1)
         for (int bb = 0; bb < P; ++bb) {
@@ -521,6 +653,15 @@ int orc_sgd_epoch(orc_model* m, const orc_csr* R, int64_t nnz, const int32_t* u,
         }
     }
     return status;
+}
+
+int orc_sgd_epoch(orc_model* m, const orc_csr* R, int64_t nnz, const int32_t* u,
+                  const int32_t* it, const uint8_t* rc, const int64_t* order,
+                  const int64_t* blk_ptr, int P, const orc_rates* h, int reverse_blocks,
+                  int upd)
+{
+    (void)nnz;
+    return orc_sgd_strata(m, R, u, it, rc, order, blk_ptr, P, 0, P, h, reverse_blocks, upd);
 }
 
 /* Objective, Eq. (loss_r): squared training error plus the L2 penalties.     */

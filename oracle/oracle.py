@@ -87,6 +87,18 @@ def lib():
                                       i32, i32, i32]
             L.orc_loss.restype = dbl
             L.orc_loss.argtypes = [C.POINTER(_Model), C.POINTER(_Csr), vp]
+            L.orc_sgd_strata.argtypes = [C.POINTER(_Model), C.POINTER(_Csr), vp, vp, vp, vp, vp,
+                                         i32, i32, i32, C.POINTER(_Rates), i32, i32]
+            L.orc_set_threads.argtypes = [i32]
+            L.orc_set_threads.restype = None
+            L.orc_max_threads.argtypes = []
+            L.orc_max_threads.restype = i32
+            L.orc_remap_slots.argtypes = [i32, i32, i32, vp, vp, vp, vp, vp, vp]
+            L.orc_rpcos_add.argtypes = [i32, i32, i32, i64, vp, vp, vp, i32, vp, vp]
+            L.orc_rpcos_signs.argtypes = [i32, i32, vp, vp]
+            L.orc_rpcos_signs.restype = None
+            L.orc_minhash_add.argtypes = [i32, i32, i32, i64, vp, vp, vp, vp]
+            L.orc_minhash_sig.argtypes = [i32, i32, i32, vp, vp]
             _lib = L
     return _lib
 
@@ -98,6 +110,15 @@ def _p(a: np.ndarray):
 def _chk(status: int, what: str):
     if status != ORC_OK:
         raise ValueError("oracle %s failed with status %d" % (what, status))
+
+
+def set_threads(n: int):
+    """OpenMP threads of the oracle's parallel loops."""
+    lib().orc_set_threads(int(n))
+
+
+def max_threads() -> int:
+    return int(lib().orc_max_threads())
 
 
 def splitmix64(seed: int, counter: int) -> int:
@@ -167,6 +188,104 @@ def topk(sig, B: int, G: int, p: int, q: int, K: int, seed_fill: int,
     _chk(lib().orc_topk(N, B, G, p, q, K, _p(sig), seed_fill & (2**64 - 1), _p(items),
                         items.size, _p(JK)), "topk")
     return JK
+
+
+def remap_slots(JK_old, W_old, C_old, JK_new, n_old: int):
+    """w and c values after a rebuild of the neighbour lists: each kept
+    neighbour brings its value to its new slot, new slots and new items
+    (rows >= n_old) start at 0."""
+    JK_new = np.ascontiguousarray(JK_new, np.int32)
+    N, K = JK_new.shape
+    JK_old = np.ascontiguousarray(JK_old, np.int32)
+    W_old = np.ascontiguousarray(W_old, np.float64)
+    C_old = np.ascontiguousarray(C_old, np.float64)
+    assert JK_old.shape[0] >= n_old and W_old.shape[0] >= n_old and C_old.shape[0] >= n_old
+    W = np.zeros((N, K))
+    Cn = np.zeros((N, K))
+    _chk(lib().orc_remap_slots(N, n_old, K, _p(JK_old), _p(W_old), _p(C_old), _p(JK_new), _p(W),
+                               _p(Cn)), "remap_slots")
+    return W, Cn
+
+
+# --------------------------------------------------------------------------
+# Hash families of the top-K comparison (Sec. 5.3): simLSH, RP_cos, minHash.
+# Each keeps a per-item state that ratings are added to, and a signature of
+# B = G*p*q bits in the layout the banding step reads.
+# --------------------------------------------------------------------------
+SIMLSH, RPCOS, MINHASH = 0, 1, 2
+
+
+def rpcos_add(acc, B: int, u, it, rc, rscale: int, g):
+    """acc (float32 [N, B]) += r_ij g_i in FP32, raters ascending per item."""
+    u = np.ascontiguousarray(u, np.int32)
+    it = np.ascontiguousarray(it, np.int32)
+    rc = np.ascontiguousarray(rc, np.uint8)
+    g = np.ascontiguousarray(g, np.float32)
+    assert acc.dtype == np.float32 and acc.flags.c_contiguous and g.shape[1] == B
+    _chk(lib().orc_rpcos_add(g.shape[0], acc.shape[0], B, u.size, _p(u), _p(it), _p(rc), rscale,
+                             _p(g), _p(acc)), "rpcos_add")
+    return acc
+
+
+def rpcos_signs(acc, B: int) -> np.ndarray:
+    acc = np.ascontiguousarray(acc, np.float32)
+    sig = np.zeros((acc.shape[0], (B + 31) // 32), np.uint32)
+    lib().orc_rpcos_signs(acc.shape[0], B, _p(acc), _p(sig))
+    return sig
+
+
+def minhash_add(mins, u, it, v):
+    """mins (uint32 [N, nh]) = min(mins, v_i) over the raters of each item."""
+    u = np.ascontiguousarray(u, np.int32)
+    it = np.ascontiguousarray(it, np.int32)
+    v = np.ascontiguousarray(v, np.uint32)
+    assert mins.dtype == np.uint32 and mins.flags.c_contiguous and v.shape[1] == mins.shape[1]
+    _chk(lib().orc_minhash_add(v.shape[0], mins.shape[0], mins.shape[1], u.size, _p(u), _p(it),
+                               _p(v), _p(mins)), "minhash_add")
+    return mins
+
+
+def minhash_sig(mins, G: int) -> np.ndarray:
+    mins = np.ascontiguousarray(mins, np.uint32)
+    N, nh = mins.shape
+    sig = np.zeros((N, (nh * G + 31) // 32), np.uint32)
+    _chk(lib().orc_minhash_sig(N, nh, G, _p(mins), _p(sig)), "minhash_sig")
+    return sig
+
+
+def lsh_init(family: int, N: int, B: int, G: int):
+    """Empty per-item hash state of a family."""
+    if family == SIMLSH:
+        return np.zeros((N, B), np.int64)
+    if family == RPCOS:
+        return np.zeros((N, B), np.float32)
+    return np.full((N, B // G), 0xFFFFFFFF, np.uint32)
+
+
+def lsh_add(family: int, state, B: int, G: int, u, it, rc, R, rscale: int, psi_exp: int = 2):
+    """Adds ratings to the state; R is the family's random input per user
+    (simLSH: bit strings H, RP_cos: Gaussians, minHash: random values)."""
+    if family == SIMLSH:
+        return simlsh_add(state, B, u, it, rc, R, psi_exp)
+    if family == RPCOS:
+        return rpcos_add(state, B, u, it, rc, rscale, R)
+    return minhash_add(state, u, it, R)
+
+
+def lsh_sig(family: int, state, B: int, G: int) -> np.ndarray:
+    if family == SIMLSH:
+        return signs(state, B)
+    if family == RPCOS:
+        return rpcos_signs(state, B)
+    return minhash_sig(state, G)
+
+
+def lsh_build(family: int, M: int, N: int, B: int, G: int, u, it, rc, R, rscale: int,
+              psi_exp: int = 2):
+    """(state, signature) of the ratings under one hash family."""
+    st = lsh_init(family, N, B, G)
+    lsh_add(family, st, B, G, u, it, rc, R, rscale, psi_exp)
+    return st, lsh_sig(family, st, B, G)
 
 
 class Csr:
@@ -293,6 +412,21 @@ class Model:
                                  _p(order), _p(blk), P, C.byref(r), int(reverse_blocks), upd),
              "sgd_epoch")
 
+    def sgd_strata(self, P: int, s0: int, s1: int, alpha, lam, beta: float, t: int, upd: int = 3):
+        """Strata [s0, s1) of one epoch over the model's own ratings (a bounded
+        sample of an epoch, for timing)."""
+        if P not in self._sched:
+            self._sched[P] = schedule(P, self.u, self.i)
+        order, blk = self._sched[P]
+        r = _Rates()
+        a = np.ascontiguousarray(alpha, np.float64)
+        l = np.ascontiguousarray(lam, np.float64)
+        lib().orc_rates_for_epoch(_p(a), _p(l), beta, t, C.byref(r))
+        m = self._c()
+        _chk(lib().orc_sgd_strata(C.byref(m), C.byref(self.R.c), _p(self.u), _p(self.i),
+                                  _p(self.rc), _p(order), _p(blk), P, s0, s1, C.byref(r), 0, upd),
+             "sgd_strata")
+
     def sgd_one(self, i: int, j: int, code: int, g, lam, upd: int = 3):
         """One update (Eq. sgd_update) with explicit rates g and regularisers lam."""
         r = _Rates()
@@ -314,14 +448,18 @@ class Model:
 
 def online_update(m: "Model", acc, sig, B: int, G: int, p: int, q: int, seed_fill: int,
                   new_u, new_i, new_rc, H, U0_new, V0_new, P: int, alpha, lam, beta: float,
-                  t: int, passes: int = 1, psi_exp: int = 2):
+                  t: int, passes: int = 1, psi_exp: int = 2, rebuild: bool = False,
+                  family: int = SIMLSH):
     """Online learning, Sec. 4.3 and Alg. "Online Learning".
 
     The batch may bring new users (ids >= m.M) and new items (ids >= m.N).
       1. the saved pre-sign sums of the items the batch touches are increased
-         by the batch's terms (new items start from zero) and signs recomputed;
+         by the batch's terms (new items start from zero) and signs recomputed
+         (RP_cos and minHash: their own per-item state, continued the same way);
       2. existing items keep their neighbour lists; every new item gets its
-         top-K over all items from the updated signatures;
+         top-K over all items from the updated signatures.  With `rebuild`
+         every item's list is searched again instead, and the w, c values of
+         the old items follow their neighbour ids (remap_slots);
       3. mu stays; a new user's / item's fixed baseline is the mean of its
          batch ratings minus mu; existing baselines stay;
       4. `passes` times: (A) ratings of new users on existing items update only
@@ -336,14 +474,16 @@ def online_update(m: "Model", acc, sig, B: int, G: int, p: int, q: int, seed_fil
     M2 = max(m.M, int(new_u.max()) + 1 if new_u.size else 0)
     N2 = max(m.N, int(new_i.max()) + 1 if new_i.size else 0)
     # 1. sums and signs
-    acc2 = np.zeros((N2, B), np.int64)
+    acc2 = lsh_init(family, N2, B, G)
     acc2[: m.N] = acc
-    simlsh_add(acc2, B, new_u, new_i, new_rc, H, psi_exp)
-    sig2 = signs(acc2, B)
+    lsh_add(family, acc2, B, G, new_u, new_i, new_rc, H, m.rscale, psi_exp)
+    sig2 = lsh_sig(family, acc2, B, G)
     # 2. neighbour lists
     K = m.K
     JK2 = np.zeros((N2, K), np.int32)
-    if K > 0:   # K = 0: no neighbour lists
+    if K > 0 and rebuild:
+        JK2[:] = topk(sig2, B, G, p, q, K, seed_fill)
+    elif K > 0:   # K = 0: no neighbour lists
         JK2[: m.N] = m.JK
         if N2 > m.N:
             JK2[m.N:] = topk(sig2, B, G, p, q, K, seed_fill, items=np.arange(m.N, N2, dtype=np.int32))
@@ -368,9 +508,12 @@ def online_update(m: "Model", acc, sig, B: int, G: int, p: int, q: int, seed_fil
     V2[: m.N] = m.V
     V2[m.N:] = np.asarray(V0_new, np.float64).reshape(N2 - m.N, m.F)
     W2 = np.zeros((N2, max(K, 1)))
-    W2[: m.N] = m.W
     C2 = np.zeros((N2, max(K, 1)))
-    C2[: m.N] = m.C
+    if K > 0 and rebuild:
+        W2[:], C2[:] = remap_slots(m.JK, m.W, m.C, JK2, m.N)
+    else:
+        W2[: m.N] = m.W
+        C2[: m.N] = m.C
     bu2 = np.zeros(M2)
     bu2[: m.M] = m.bu
     bv2 = np.zeros(N2)

@@ -462,8 +462,142 @@ def test_monotone_loss_ml100k():
         m.sgd_epoch(w.n_strata, w.alpha, w.lam, w.beta, t)
         losses.append(m.loss(w.lam))
     assert all(b < a for a, b in zip(losses, losses[1:])), losses
+    # the trained model predicts held-out ratings better than their global
+    # mean does (numpy, independent of the oracle's RMSE)
     r = m.rmse(d["test_u"], d["test_i"], d["test_rc"])
-    assert 0.5 < r < 1.5
+    mean_only = math.sqrt(np.mean((d["test_rc"] / w.rscale - m.mu) ** 2))
+    assert r < mean_only, (r, mean_only)
+
+
+# --------------------------------------------------------------------------
+# Objective, Eq. (loss_r), and RMSE (Sec. 5.1), worked by hand
+# --------------------------------------------------------------------------
+# The four training ratings of the hand model, predicted by hand (Eq. rr):
+#   (u0,i0): 3.5+0.1+0.3 + u.v 0.4 + w-term (2-3.0)*0.5/1 + c-term 0.2/1 = 4.0,  e = 0
+#   (u0,i1): 3.9 (see the predict test),                                  e = -1.9
+#   (u1,i1): 2.85,                                                        e = 2.15
+#   (u1,i2): 3.5-0.2-0.1 + u.v -0.5 + w-term (5-4.0)*(-1.0) + c 0.05 = 1.75, e = 1.25
+_HAND_SSE = 0.0 ** 2 + 1.9 ** 2 + 2.15 ** 2 + 1.25 ** 2          # 9.795
+# squared norms of b, bh, U, V, W, C of the hand model
+_HAND_PEN = [0.01 + 0.04,
+             0.09 + 0.0 + 0.01,
+             1.0 + 4.0 + 0.25 + 1.0,
+             0.04 + 0.01 + 0.09 + 0.16 + 0.0 + 0.25,
+             0.25 + 0.0625 + 0.04 + 0.16 + 1.0 + 1.0,
+             0.01 + 0.04 + 0.09 + 0.09 + 0.0025 + 0.0225]
+
+
+def test_loss_hand_computed():
+    m = _hand_model()
+    assert m.loss([0.0] * 6) == pytest.approx(_HAND_SSE, abs=1e-12)
+    # each penalty on its own: dropping or mis-indexing any one term fails
+    for g in range(6):
+        lam = [0.0] * 6
+        lam[g] = 0.5
+        assert m.loss(lam) == pytest.approx(_HAND_SSE + 0.5 * _HAND_PEN[g], abs=1e-12), g
+    lam = [0.1, 0.2, 0.3, 0.4, 0.5, 0.6]
+    assert m.loss(lam) == pytest.approx(13.32425, abs=1e-12)
+
+
+def test_rmse_hand_computed():
+    # half-step codes 7, 4, 10 are ratings 3.5, 2.0, 5.0; predictions 3, 2.5, 4
+    # give errors 0.5, -0.5, 1.0: sqrt(1.5 / 3) = 1/sqrt(2)
+    r = orc.rmse(np.array([3.0, 2.5, 4.0]), np.array([7, 4, 10], np.uint8), 2)
+    assert r == pytest.approx(1.0 / math.sqrt(2.0), abs=1e-15)
+    assert orc.rmse(np.zeros(0), np.zeros(0, np.uint8), 1) == 0.0
+    # integer codes are the ratings themselves
+    assert orc.rmse(np.array([1.0, 5.0]), np.array([2, 2], np.uint8), 1) == pytest.approx(
+        math.sqrt((1.0 + 9.0) / 2.0), abs=1e-15)
+
+
+# --------------------------------------------------------------------------
+# Neighbour-list rebuild: w and c follow their neighbour ids
+# --------------------------------------------------------------------------
+def test_remap_slots_hand_case():
+    # item 0: old neighbours (1, 2, 3), new (2, 3, 5): 2 and 3 keep their
+    # values in their new slots, 5 is new; item 1 is new: zeros
+    JK_old = np.array([[1, 2, 3]], np.int32)
+    W_old = np.array([[0.25, -0.5, 0.75]])
+    C_old = np.array([[1.0, 2.0, 3.0]])
+    JK_new = np.array([[2, 3, 5], [0, 2, 3]], np.int32)
+    W, Cn = orc.remap_slots(JK_old, W_old, C_old, JK_new, 1)
+    assert W.tolist() == [[-0.5, 0.75, 0.0], [0.0, 0.0, 0.0]]
+    assert Cn.tolist() == [[2.0, 3.0, 0.0], [0.0, 0.0, 0.0]]
+
+
+# --------------------------------------------------------------------------
+# The other hash families of the top-K comparison (Sec. 5.3)
+# --------------------------------------------------------------------------
+def test_rpcos_hand_example():
+    # two raters of item 0 with ratings 2 and 4 and directions (1.5, -1),
+    # (-0.25, 0.5): sums 2*1.5 + 4*(-0.25) = 2 and 2*(-1) + 4*0.5 = 0; both
+    # bits set (a zero sum counts as non-negative).  Item 1 has one rater with
+    # rating 1 on direction (-0.25, 0.5): bits 0, 1.
+    g = np.array([[1.5, -1.0], [-0.25, 0.5]], np.float32)
+    u = np.array([0, 1, 1], np.int32)
+    it = np.array([0, 0, 1], np.int32)
+    rc = np.array([2, 4, 1], np.uint8)
+    acc, sig = orc.lsh_build(orc.RPCOS, 2, 2, 2, 2, u, it, rc, g, 1)
+    assert acc.tolist() == [[2.0, 0.0], [-0.25, 0.5]]
+    assert sig[:, 0].tolist() == [0b11, 0b10]
+    # half-step codes: rating = code / 2
+    acc2, _ = orc.lsh_build(orc.RPCOS, 2, 2, 2, 2, u, it, rc * 2, g, 2)
+    assert np.array_equal(acc2, acc)
+
+
+def test_rpcos_collision_rate_is_one_minus_angle_over_pi():
+    # Charikar: a Gaussian sign projection puts two vectors on the same side
+    # with probability 1 - theta/pi.  Monte Carlo over seeded directions.
+    M, B, trials = 16, 64, 300
+    x = np.array([5, 4, 0, 3, 0, 1, 2, 0, 5, 0, 3, 0, 0, 4, 1, 2], np.uint8)
+    y = np.array([4, 0, 2, 3, 1, 0, 2, 5, 4, 0, 0, 1, 3, 4, 0, 0], np.uint8)
+    u = np.concatenate([np.nonzero(x)[0], np.nonzero(y)[0]]).astype(np.int32)
+    it = np.concatenate([np.zeros(np.count_nonzero(x)), np.ones(np.count_nonzero(y))]).astype(np.int32)
+    rc = np.concatenate([x[x > 0], y[y > 0]])
+    xf, yf = x.astype(float), y.astype(float)
+    theta = math.acos(xf @ yf / (np.linalg.norm(xf) * np.linalg.norm(yf)))
+    want = 1.0 - theta / math.pi
+    rng = np.random.default_rng(11)
+    same = 0
+    for _ in range(trials):
+        g = rng.standard_normal((M, B)).astype(np.float32)
+        _, sig = orc.lsh_build(orc.RPCOS, M, 2, B, 8, u, it, rc, g, 1)
+        same += 64 - bin((int(sig[0, 0]) ^ int(sig[1, 0])) | ((int(sig[0, 1]) ^ int(sig[1, 1])) << 32)).count("1")
+    n = trials * B
+    rate = same / n
+    assert abs(rate - want) <= 4 * math.sqrt(want * (1 - want) / n), (rate, want)
+
+
+def test_minhash_hand_example():
+    # item 0 rated by users 0, 2; item 1 by user 1; item 2 by nobody
+    v = np.array([[7, 100], [3, 5], [9, 1]], np.uint32)
+    u = np.array([0, 2, 1], np.int32)
+    it = np.array([0, 0, 1], np.int32)
+    mins, sig = orc.lsh_build(orc.MINHASH, 3, 3, 2 * 8, 8, u, it, np.ones(3, np.uint8), v, 1)
+    assert mins.tolist() == [[min(7, 9), min(100, 1)], [3, 5], [0xFFFFFFFF, 0xFFFFFFFF]]
+    # G = 8: hash h is the low byte of the minimum, at bits [8h, 8h + 8)
+    assert sig[:, 0].tolist() == [7 | (1 << 8), 3 | (5 << 8), 0xFFFF]
+
+
+def test_minhash_collision_rate_is_jaccard():
+    # P(min over A == min over B) = |A & B| / |A | B| for a random order of the
+    # users; with only the low G bits kept, J + (1 - J) 2^-G (b-bit minwise)
+    A = [0, 1, 2, 3, 5, 8, 13]
+    Bs = [1, 2, 3, 4, 8, 9]
+    J = len(set(A) & set(Bs)) / len(set(A) | set(Bs))
+    M, nh, trials = 16, 64, 300
+    u = np.array(A + Bs, np.int32)
+    it = np.array([0] * len(A) + [1] * len(Bs), np.int32)
+    rng = np.random.default_rng(5)
+    full = low = 0
+    for _ in range(trials):
+        v = rng.integers(0, 2**32, size=(M, nh), dtype=np.uint64).astype(np.uint32)
+        mins, sig = orc.lsh_build(orc.MINHASH, M, 2, nh * 2, 2, u, it, np.ones(u.size, np.uint8), v, 1)
+        full += int(np.sum(mins[0] == mins[1]))
+        low += int(np.sum((mins[0] & 3) == (mins[1] & 3)))
+    n = trials * nh
+    for rate, want in ((full / n, J), (low / n, J + (1 - J) / 4)):
+        assert abs(rate - want) <= 4 * math.sqrt(want * (1 - want) / n), (rate, want)
 
 
 def test_lsh_neighbours_not_worse_than_random():
@@ -588,3 +722,51 @@ def test_online_learns_new_users():
     before = np.sqrt(np.mean((src[test] / w.rscale - m2.mu) ** 2))
     after = m2.rmse(su[test], si[test], src[test])
     assert after < before
+
+
+def test_online_rebuild_of_unchanged_store_is_identity():
+    # searching every list again over an unchanged store finds the same lists,
+    # so every w and c stays where it was, bit for bit
+    w, d, sp, m, acc, sig, _ = _online_setup()
+    e = np.zeros(0, np.int32)
+    m2, _, _ = orc.online_update(m, acc, sig, w.B, w.G, w.p, w.q, 9, e, e, e.astype(np.uint8),
+                                 d["H"], np.zeros((0, w.F)), np.zeros((0, w.F)), w.n_strata,
+                                 w.alpha, w.lam, w.beta, 1, rebuild=True)
+    for k in ("U", "V", "bu", "bv", "W", "C", "JK"):
+        assert np.array_equal(getattr(m2, k), getattr(m, k)), k
+
+
+def test_online_rebuild_moves_weights_with_their_neighbours():
+    # a batch that changes signatures, no SGD pass: after the rebuild every
+    # neighbour an item kept carries its old w and c, every new one has 0
+    w, d, sp, m, acc, sig, (bu_, bi_, brc) = _online_setup()
+    rng = np.random.default_rng(3)
+    m.W[...] = rng.normal(size=m.W.shape)
+    m.C[...] = rng.normal(size=m.C.shape)
+    m2, _, sig2 = orc.online_update(m, acc, sig, w.B, w.G, w.p, w.q, 9, bu_, bi_, brc, d["H"],
+                                    d["U0"][m.M:], d["V0"][m.N:], w.n_strata, w.alpha, w.lam,
+                                    w.beta, 1, passes=0, rebuild=True)
+    assert np.array_equal(m2.JK, orc.topk(sig2, w.B, w.G, w.p, w.q, w.K, 9))
+    changed = kept = 0
+    for j in range(m.N):
+        old = {int(n): k for k, n in enumerate(m.JK[j])}
+        for k, n in enumerate(m2.JK[j]):
+            if int(n) in old:
+                kept += 1
+                assert m2.W[j, k] == m.W[j, old[int(n)]] and m2.C[j, k] == m.C[j, old[int(n)]]
+            else:
+                changed += 1
+                assert m2.W[j, k] == 0.0 and m2.C[j, k] == 0.0
+    assert kept > 0 and changed > 0
+    assert not np.any(m2.W[m.N:]) and not np.any(m2.C[m.N:])
+
+
+def test_sgd_strata_compose_to_the_epoch():
+    # running strata [0, s) then [s, P) is the epoch itself, bit for bit
+    w, d, m1 = _model_for("small")
+    _, _, m2 = _model_for("small")
+    m1.sgd_epoch(w.n_strata, w.alpha, w.lam, w.beta, 0)
+    m2.sgd_strata(w.n_strata, 0, 3, w.alpha, w.lam, w.beta, 0)
+    m2.sgd_strata(w.n_strata, 3, w.n_strata, w.alpha, w.lam, w.beta, 0)
+    for a in ("U", "V", "bu", "bv", "W", "C"):
+        assert np.array_equal(getattr(m1, a), getattr(m2, a)), a
