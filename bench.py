@@ -1,18 +1,27 @@
 #!/usr/bin/env python
 """Benchmark: whole LSH-MF training job on one MI355X.
 
-One step = one full training pass of the hot path over the MovieLens-10M
-shaped workload (69,878 users x 10,677 items, 9.9M training ratings, F=64,
-K=50, 128 hash bits, 20 epochs):
+One step = one full training pass of the hot path over the Netflix-shaped
+workload (480,189 users x 17,770 items, 98,591,605 training ratings, F = 128,
+K = 100, 128 hash bits, 20 epochs, FP32):
   ingest + layout -> simLSH neighbours (projection, banding, top-K, neighbour
   codes) -> 20 SGD epochs with the K-neighbour term -> predictions and FP64
-  RMSE on the 100,000 held-out ratings.
+  RMSE on the 1,408,395 held-out ratings.
 The metric is rating SGD updates per second over the whole step
 (epochs * training ratings / step time), inputs already resident in HBM.
 
-Prints ONE JSON line.  The roofline object covers the dominant kernel
-(k_sgd_stratum): algorithmic bytes of one launch (one stratum) over the
-measured average launch time, against the 8 TB/s HBM peak.
+Prints ONE JSON line.  Besides the contract fields it carries
+  roofline      the dominant kernel (k_sgd_stratum): algorithmic bytes of one
+                launch (one stratum) over its mean launch time, against the
+                8 TB/s HBM peak; traffic = measured HBM bytes per launch from
+                the committed counter summary while the kernel's sources match
+  lsh_phases_ms the neighbour search of the last step, by phase
+  serving       the serving loop on the MovieLens-10M shaped online stream
+                (p50 / p99 latency at offered loads, online updates/s)
+  cpu_baseline  the FP64 oracle on a bounded sample, 1 thread and all threads
+
+--mode lsh times the neighbour search alone (the paper's simLSH settings),
+--mode serve the serving loop alone.
 """
 import argparse
 import hashlib
@@ -29,7 +38,7 @@ def log(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
 
 
-def sgd_bytes_per_epoch(nnz, nseg, F, K, nstride, storage="fp32"):
+def sgd_bytes_per_epoch(nnz, nseg, F, K, nstride):
     """Algorithmic HBM bytes of one epoch of k_sgd_stratum.
 
     Per rating: packed (user, code) 4 + hand-over word 4 + neighbour codes
@@ -44,12 +53,10 @@ def sgd_bytes_per_epoch(nnz, nseg, F, K, nstride, storage="fp32"):
     return nnz * per_rating + nseg * per_seg
 
 
-SHAPE_NAMES = {"ml10m": "MovieLens-10M", "netflix": "Netflix", "ml100k": "MovieLens-100K",
-               "ml10m_k0": "MovieLens-10M", "ml100k_k0": "MovieLens-100K"}
+SHAPE_NAMES = {"ml10m": "MovieLens-10M", "netflix": "Netflix", "ml100k": "MovieLens-100K"}
 
-KERNEL_SOURCES = ("paper_2111_11682_amd/csrc/sgd.hip", "paper_2111_11682_amd/csrc/common.hpp",
-                  "include/lshmf.h")
-PROFILE = os.path.join(ROOT, "profiles", "k_sgd_stratum_ml10m.md")
+KERNEL_SOURCES = ("paper_2111_11682_amd/csrc/sgd.hip", "paper_2111_11682_amd/csrc/wave.hpp",
+                  "paper_2111_11682_amd/csrc/common.hpp")
 
 
 def kernel_fingerprint():
@@ -60,13 +67,15 @@ def kernel_fingerprint():
     return h.hexdigest()
 
 
-def profiled_traffic():
-    """HBM bytes per k_sgd_stratum launch from the committed counter summary,
-    or None when the kernel's sources changed since the counters were taken."""
-    if not os.path.exists(PROFILE):
+def profiled_traffic(workload):
+    """HBM bytes per k_sgd_stratum launch from the committed counter summary
+    of this workload, or None when the kernel's sources changed since the
+    counters were taken."""
+    path = os.path.join(ROOT, "profiles", "k_sgd_stratum_%s.md" % workload)
+    if not os.path.exists(path):
         return None
     rec = None
-    for line in open(PROFILE):
+    for line in open(path):
         line = line.strip()
         if line.startswith("{") and "traffic_bytes_per_launch" in line:
             rec = json.loads(line)
@@ -75,31 +84,66 @@ def profiled_traffic():
     return int(rec["traffic_bytes_per_launch"])
 
 
-def cpu_baseline(w, d, P, epochs=4):
-    """The FP64 oracle's SGD on the same training set, a bounded number of epochs."""
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(w, d, P, stride=16, target_s=8.0):
+    """The FP64 oracle on a bounded sample of the same workload: the ratings of
+    every stride-th user (ids are a random permutation, so a random 1/stride
+    of the users with their whole rating rows), with the sample's own simLSH
+    neighbour lists.  Strata of one epoch run in order, first on one thread,
+    then on all threads, each until target_s seconds have passed."""
     import numpy as np
     from oracle import oracle as orc
-    u, it, rc = d["train_u"], d["train_i"], d["train_rc"]
-    _, sig = orc.simlsh(w.M, w.N, w.B, u, it, rc, d["H"])
-    JK = orc.topk(sig, w.B, w.G, w.p, w.q, w.K, 12345) if w.K > 0 else np.zeros((w.N, 0), np.int32)
-    m = orc.Model(w.M, w.N, w.F, w.K, w.rscale, u, it, rc, JK, d["U0"], d["V0"])
-    m._sched[P] = orc.schedule(P, u, it)             # the layout, untimed
+    sel = d["train_u"] % stride == 0
+    u = (d["train_u"][sel] // stride).astype(np.int32)
+    it = d["train_i"][sel]
+    rc = d["train_rc"][sel]
+    Ms = (w.M + stride - 1) // stride
+    H = d["H"][::stride]
     t0 = time.perf_counter()
-    for t in range(epochs):
-        m.sgd_epoch(P, w.alpha, w.lam, w.beta, t)
-    dt = time.perf_counter() - t0
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": float(epochs * u.size / dt), "unit": "updates/s", "cores": cores, "kind": "oracle",
-            "sample": "%d FP64 oracle SGD epochs (%s, P=%d strata, OpenMP over the blocks "
-                      "of a stratum) over all %d training ratings, %.1f s"
-                      % (epochs, "K-neighbour term" if w.K > 0 else "K = 0, no neighbour term", P, u.size, dt)}
+    _, sig = orc.simlsh(Ms, w.N, w.B, u, it, rc, H)
+    JK = orc.topk(sig, w.B, w.G, w.p, w.q, w.K, 12345) if w.K > 0 else np.zeros((w.N, 0), np.int32)
+    m = orc.Model(Ms, w.N, w.F, w.K, w.rscale, u, it, rc, JK, d["U0"][::stride], d["V0"])
+    order, blk = orc.schedule(P, u, it)
+    m._sched[P] = (order, blk)
+    log("oracle sample: %d users, %d ratings, set up in %.1f s" % (Ms, u.size, time.perf_counter() - t0))
+    all_threads = orc.max_threads()
+    rates = {}
+    s = 0
+    for threads in (1, all_threads):
+        orc.set_threads(threads)
+        done = 0
+        t0 = time.perf_counter()
+        while s < P and time.perf_counter() - t0 < target_s:
+            m.sgd_strata(P, s, s + 1, w.alpha, w.lam, w.beta, 0)
+            done += int(blk[(s + 1) * P] - blk[s * P])
+            s += 1
+        dt = time.perf_counter() - t0
+        rates[threads] = (done / dt, done, dt)
+    orc.set_threads(all_threads)
+    rN, nN, tN = rates[all_threads]
+    r1, n1, t1 = rates[1]
+    return {"value": round(rN, 1), "unit": "updates/s", "cores": all_threads, "kind": "oracle",
+            "value_1thread": round(r1, 1), "cpu_model": cpu_model(), "host_cpus": os.cpu_count(),
+            "sample": "FP64 oracle SGD (K-neighbour term, P=%d strata in schedule order) on the ratings of every "
+                      "%dth user of the %s-shaped set (%d users, %d ratings, own simLSH lists): %d updates in "
+                      "%.1f s on %d threads, %d updates in %.1f s on 1 thread"
+                      % (P, stride, SHAPE_NAMES.get(w.name, w.name), Ms, u.size, nN, tN, all_threads, n1, t1)}
 
 
-def serve_main(args, w, d):
-    """Serving loop on the online split of the same workload: pre-train on
-    80%, stream the rest as update batches (log-uniform 1k-1M ratings) mixed
-    1:4 with query requests (log-uniform 1-10k pairs); Poisson arrivals at
-    0.3, 0.6 and 0.9 of the capacity measured back to back."""
+def serve_runs(w, d, storage, loads=(0.3, 0.6, 0.9), log_fn=log):
+    """Serving loop on the online split of the workload: pre-train on 80%,
+    stream the rest as update batches (log-uniform 1k-1M ratings) mixed 1:4
+    with query requests (log-uniform 1-10k pairs); back to back, then Poisson
+    arrivals at fractions of the capacity measured back to back."""
     import numpy as np
     import torch
     from paper_2111_11682_amd import lshmf, synth
@@ -117,13 +161,13 @@ def serve_main(args, w, d):
     H = torch.from_numpy(d["H"].view(np.int32)).to(dev)
     pre = [torch.from_numpy(sp[k]).to(dev) for k in ("pretrain_u", "pretrain_i", "pretrain_rc")]
     batch_cap = int(req["n"][req["kind"] == 0].max())
-    log("serve: %d requests (%d updates, %d update ratings, %d query pairs), batch_cap %d" %
-        (req.size, int((req["kind"] == 0).sum()), L["upd_u"].size, L["q_u"].size, batch_cap))
+    log_fn("serve: %d requests (%d updates, %d update ratings, %d query pairs), batch_cap %d" %
+           (req.size, int((req["kind"] == 0).sum()), L["upd_u"].size, L["q_u"].size, batch_cap))
 
     def run(arrival):
         m = lshmf.LshMF(M0, N0, w.F, w.K, w.G, w.p, w.q, w.rscale, pre[0].numel(), n_strata=w.n_strata,
                         device=dev, M_cap=w.M, N_cap=w.N, nnz_cap=d["train_u"].size,
-                        batch_cap=batch_cap, storage=args.storage)
+                        batch_cap=batch_cap, storage=storage)
         m.ingest(*pre)
         m.set_factors(U0[:M0], V0[:N0])
         m.build_lsh_neighbours(H, 12345)
@@ -134,7 +178,7 @@ def serve_main(args, w, d):
         r["arrival"] = arrival
         _, start, done, status = m.serve(r, upd, qry, U0, V0, H, 12345, w.alpha, w.lam, w.beta, w.epochs, 1,
                                          max_query_batch=65536)
-        assert m.device_status() == 0
+        m.check()
         m.close()
         return start, done, status
 
@@ -152,19 +196,72 @@ def serve_main(args, w, d):
     start, done, status = run(zero)
     makespan = float(done.max())
     capacity = req.size / makespan
-    log("back to back: %.3f s for %d requests (%.1f requests/s)" % (makespan, req.size, capacity))
-    loads = {"back_to_back": dict(summary(zero, start, done, status), makespan_s=round(makespan, 4))}
-    for rho in (0.3, 0.6, 0.9):
+    upd_sel = (req["kind"] == 0) & (status == 0)
+    upd_time = float(np.sum(done[upd_sel] - start[upd_sel]))
+    online_rate = float(np.sum(req["n"][upd_sel])) / upd_time if upd_time > 0 else 0.0
+    log_fn("back to back: %.3f s for %d requests (%.1f requests/s), online %.0f rating updates/s"
+           % (makespan, req.size, capacity, online_rate))
+    res = {"back_to_back": dict(summary(zero, start, done, status), makespan_s=round(makespan, 4))}
+    for rho in loads:
         arr = synth.poisson_arrivals(req.size, rho * capacity)
         start, done, status = run(arr)
-        loads["load_%.1f" % rho] = summary(arr, start, done, status)
-        log("load %.1f: %s" % (rho, loads["load_%.1f" % rho]))
-    out = {"metric": "serving query latency p99 at 0.6 of capacity", "value": loads["load_0.6"]["query_p99_ms"],
+        res["load_%.1f" % rho] = summary(arr, start, done, status)
+        log_fn("load %.1f: %s" % (rho, res["load_%.1f" % rho]))
+    return {"workload": "%s-shaped online stream (1%% new users and items, 20%% of ratings streamed)"
+                        % SHAPE_NAMES.get(w.name, w.name),
+            "requests": int(req.size), "update_ratings": int(L["upd_u"].size), "query_pairs": int(L["q_u"].size),
+            "storage": storage, "capacity_requests_per_s": round(capacity, 2),
+            "online_updates_per_s": round(online_rate, 1), "loads": res}
+
+
+def serve_main(args, w, d):
+    res = serve_runs(w, d, args.storage)
+    out = {"metric": "serving query latency p99 at 0.6 of capacity", "value": res["loads"]["load_0.6"]["query_p99_ms"],
            "unit": "ms", "n_gpus": 1, "higher_is_better": False, "vs_baseline": None, "dtype": "f32",
-           "data": "synthetic (MovieLens-10M shape, 1% new users and items, 20% of ratings streamed)",
-           "config": {"workload": "ml10m-shaped online stream", "requests": int(req.size),
-                      "update_ratings": int(L["upd_u"].size), "query_pairs": int(L["q_u"].size),
-                      "capacity_requests_per_s": round(capacity, 2), "storage": args.storage, "loads": loads}}
+           "data": "synthetic (%s shape, 1%% new users and items, 20%% of ratings streamed)"
+                   % SHAPE_NAMES.get(w.name, w.name),
+           "config": dict(res, workload=res["workload"])}
+    print(json.dumps(out), flush=True)
+
+
+def lsh_main(args, w, d):
+    """The neighbour search alone at the workload's (G, p, q): time per call
+    and by phase, and the space of the hash table as the paper counts it
+    (one int32 per G-bit hash: N * p * q * 4 bytes)."""
+    import numpy as np
+    import torch
+    from paper_2111_11682_amd import lshmf, synth
+    dev = torch.device("cuda:0")
+    R = synth.family_rand(w)
+    Rt = torch.from_numpy(R.view(np.int32) if R.dtype == np.uint32 else R).to(dev)
+    m = lshmf.LshMF(w.M, w.N, w.F, w.K, w.G, w.p, w.q, w.rscale, d["train_u"].size, n_strata=w.n_strata,
+                    device=dev, hash_family=w.family)
+    m.ingest(*[torch.from_numpy(d[k]).to(dev) for k in ("train_u", "train_i", "train_rc")])
+    m.set_timing(True)
+    for _ in range(args.warmup):
+        m.build_lsh_neighbours(Rt, 12345)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    phases = []
+    e0.record()
+    for _ in range(args.steps):
+        m.build_lsh_neighbours(Rt, 12345)
+        phases.append(m.lsh_phase_ms())
+    e1.record()
+    torch.cuda.synchronize()
+    m.check()
+    ms = e0.elapsed_time(e1) / args.steps
+    ph = {k: round(float(np.mean([p[k] for p in phases])), 3) for k in phases[0]}
+    fam = {0: "simLSH", 1: "RP_cos", 2: "minHash"}[w.family]
+    out = {"metric": "top-K neighbour search time (%s, p=%d, q=%d)" % (fam, w.p, w.q), "value": round(ms, 3),
+           "unit": "ms", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "higher_is_better": False,
+           "vs_baseline": None, "dtype": "int32" if w.family != 1 else "f32",
+           "data": "synthetic (%s shape)" % SHAPE_NAMES.get(w.name.split("_")[0], w.name),
+           "config": {"workload": "%s neighbour search on the %s-shaped training set" % (fam, w.name.split("_")[0]),
+                      "users": w.M, "items": w.N, "train_ratings": int(d["train_u"].size), "K": w.K, "G": w.G,
+                      "p": w.p, "q": w.q, "hash_bits": w.B,
+                      "space_mib": round(w.N * w.p * w.q * 4 / 2**20, 3)},
+           "lsh_phases_ms": ph}
     print(json.dumps(out), flush=True)
 
 
@@ -173,11 +270,12 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="ml10m")
+    ap.add_argument("--workload", default=None, help="default netflix (train), ml10m (serve), netflix_p3q100 (lsh)")
     ap.add_argument("--epochs", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--mode", choices=("train", "serve"), default="train",
-                    help="serve: the serving loop over an online stream instead of the training job")
+    ap.add_argument("--no-serve", action="store_true", help="leave the serving runs out of the training line")
+    ap.add_argument("--mode", choices=("train", "serve", "lsh"), default="train",
+                    help="serve: the serving loop alone; lsh: the neighbour search alone")
     ap.add_argument("--storage", choices=("fp32", "bf16"), default=None,
                     help="bf16: BF16 copies of U, V, W, C beside the FP32 masters "
                          "(default fp32 for training, bf16 for serving)")
@@ -186,6 +284,8 @@ def main():
     args = ap.parse_args()
     if args.storage is None:
         args.storage = "bf16" if args.mode == "serve" else "fp32"
+    if args.workload is None:
+        args.workload = {"train": "netflix", "serve": "ml10m", "lsh": "netflix_p3q100"}[args.mode]
     if args.gpus != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
@@ -207,12 +307,16 @@ def main():
     if args.mode == "serve":
         serve_main(args, w, d)
         return
+    if args.mode == "lsh":
+        lsh_main(args, w, d)
+        return
     g = {k: torch.from_numpy(v).to(dev) for k, v in d.items() if k != "H"}
     H = torch.from_numpy(d["H"].view(np.int32)).to(dev)
     nnz = d["train_u"].size
     P = w.n_strata
     m = lshmf.LshMF(w.M, w.N, w.F, w.K, w.G, w.p, w.q, w.rscale, nnz, n_strata=P, device=dev,
                     storage=args.storage)
+    m.set_timing(True)
     pred = torch.empty(d["test_u"].size, dtype=torch.float32, device=dev)
     rmse = torch.empty(1, dtype=torch.float64, device=dev)
     sgd_events = []
@@ -253,28 +357,38 @@ def main():
     stop.record()
     torch.cuda.synchronize()
     ms = start.elapsed_time(stop) / args.steps
-    assert m.device_status() == 0
+    m.check()
     final_rmse = rmse.item()
+    lsh_ms = m.lsh_phase_ms()
     sgd_ms_epoch = sum(a.elapsed_time(b) for a, b in sgd_events) / len(sgd_events)
-    log("step %.2f ms, SGD %.3f ms/epoch, RMSE %.5f" % (ms, sgd_ms_epoch, final_rmse))
+    log("step %.2f ms, SGD %.3f ms/epoch, RMSE %.5f, LSH phases %s" % (ms, sgd_ms_epoch, final_rmse, lsh_ms))
 
     lay = m.layout()
     nseg = int(m.arena_view(lay.blk_seg, P * P + 1, torch.int64)[-1].item())
-    epoch_bytes = sgd_bytes_per_epoch(nnz, nseg, w.F, w.K, lay.nstride, args.storage)
+    epoch_bytes = sgd_bytes_per_epoch(nnz, nseg, w.F, w.K, lay.nstride)
     launch_bytes = epoch_bytes / P
     launch_s = sgd_ms_epoch / 1e3 / P
     achieved = launch_bytes / launch_s / 1e9
-    traffic = profiled_traffic() if (args.workload == "ml10m" and args.storage == "fp32") else None
+    traffic = profiled_traffic(w.name) if args.storage == "fp32" else None
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": 8000.0, "unit": "GB/s",
                 "frac": round(achieved / 8000.0, 5), "traffic": traffic,
                 "kernel": "k_sgd_stratum", "launch_bytes": int(launch_bytes),
                 "launch_us": round(launch_s * 1e6, 3)}
+    m.close()
+    del m, g
+    torch.cuda.empty_cache()
+
+    serving = None
+    if not args.no_serve:
+        ws = synth.WORKLOADS["ml10m"]
+        serving = serve_runs(ws, synth.generate(ws), "bf16")
 
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the oracle on a sample")
         cpu = cpu_baseline(w, d, P)
-        log("oracle %.0f updates/s on %d cores" % (cpu["value"], cpu["cores"]))
+        log("oracle %.0f updates/s on %d threads, %.0f on 1 thread (%s)"
+            % (cpu["value"], cpu["cores"], cpu["value_1thread"], cpu["cpu_model"]))
 
     value = epochs * nnz / (ms / 1e3)
     out = {
@@ -290,15 +404,18 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
-        "data": "synthetic (seeded Zipf/lognormal ratings with planted structure, %s shape)" % SHAPE_NAMES.get(w.name, w.name),
-        "config": {"workload": ("%s-shaped LSH-MF training job" % w.name if w.K > 0
-                               else "%s-shaped biased-MF training job (K = 0)" % w.name[:-3]), "users": w.M, "items": w.N,
-                   "train_ratings": int(nnz), "test_ratings": int(d["test_u"].size), "F": w.F,
-                   "K": w.K, "hash_bits": w.B, "p": w.p, "q": w.q, "epochs": epochs,
+        "data": "synthetic (seeded Zipf/lognormal ratings with planted structure, %s shape)"
+                % SHAPE_NAMES.get(w.name.split("_")[0], w.name),
+        "config": {"workload": "%s-shaped LSH-MF training job (ingest, simLSH top-K, %d SGD epochs, held-out "
+                               "RMSE)" % (SHAPE_NAMES.get(w.name.split("_")[0], w.name), epochs),
+                   "users": w.M, "items": w.N, "train_ratings": int(nnz), "test_ratings": int(d["test_u"].size),
+                   "F": w.F, "K": w.K, "hash_bits": w.B, "p": w.p, "q": w.q, "epochs": epochs,
                    "n_strata": P, "storage": args.storage, "heldout_rmse": round(final_rmse, 6),
                    "sgd_ms_per_epoch": round(sgd_ms_epoch, 3),
                    "sgd_updates_per_s": round(nnz / (sgd_ms_epoch / 1e3), 1)},
         "roofline": roofline,
+        "lsh_phases_ms": {k: round(v, 3) for k, v in lsh_ms.items()},
+        "serving": serving,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

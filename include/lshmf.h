@@ -43,20 +43,28 @@ enum {
 
 enum { LSHMF_FP32 = 0, LSHMF_BF16 = 1 };
 
+/* Hash families of the neighbour search (Sec. 4.1 simLSH; RP_cos and minHash
+ * are the two other LSH families of the top-K comparison in Sec. 5.3). */
+enum { LSHMF_SIMLSH = 0, LSHMF_RPCOS = 1, LSHMF_MINHASH = 2 };
+
+/* online_update flags */
+enum { LSHMF_REBUILD_NBRS = 1 };
+
 typedef struct lshmf_dims {
     int32_t M, N;      /* users, items                                       */
     int32_t F;         /* rank of U (M x F) and V (N x F), 1..256            */
     int32_t K;         /* neighbours per item, 0..128, K <= N - 1; K = 0 is  */
                        /* biased MF without the neighbour term (no w, c)     */
-    int32_t G, p, q;   /* simLSH: G bits per hash, p hashes ANDed per band,
-                          q bands ORed (Sec. 4.1); B = G*p*q <= 256 bits,
-                          band width p*G <= 32                               */
+    int32_t G, p, q;   /* G bits per hash, p hashes ANDed per band, q bands
+                          ORed (Sec. 4.1 coarse- and fine-grained hashing);
+                          B = G*p*q <= 8192 bits, band width p*G <= 56 and
+                          p*G + ceil(log2 q) <= 64; minHash needs G <= 32    */
     int32_t rscale;    /* rating code scale, 1 or 2                          */
     int32_t psi_exp;   /* Psi(r) = rc^psi_exp in the hash sums (2: Psi = r^2) */
     int32_t n_strata;  /* P: users and items split into P blocks by id mod P */
     int32_t storage;   /* LSHMF_FP32, or LSHMF_BF16: BF16 copies of U, V, W, C
                           for serving next to the FP32 masters              */
-    int32_t reserved;
+    int32_t hash_family; /* LSHMF_SIMLSH, LSHMF_RPCOS or LSHMF_MINHASH       */
     int64_t nnz;       /* ratings of the initial training set                */
     /* Capacities for online learning (0: the initial size; batch_cap 0: no
      * online batches).  Tables and the arena are sized for them.            */
@@ -82,7 +90,10 @@ typedef struct lshmf_hparams {
  *   W  [N*K]   C  [N*K]          explicit / implicit influence w_j, c_j, slot k
  *                                 refers to neighbour JK[j*K + k]    (Eq. rr, parts 2, 3)
  *   JK [N*K]   int32             top-K neighbours, ascending ids per row
- *   acc[N*B]   int32             simLSH pre-sign sums (kept for online learning)
+ *   acc[N*B]   int32             per-item hash state, kept for online learning:
+ *                                simLSH pre-sign sums (int32); RP_cos FP32 sums
+ *                                (bit patterns); minHash minima (uint32, the
+ *                                first N*B/G entries)
  *   sig[N*ceil(B/32)] uint32     simLSH signatures, bit b at word b/32, bit b%32
  *   b0 [M]     bh0 [N]           fixed baseline deviations of the "simple case"
  *   mu [1]     double            global mean
@@ -129,25 +140,46 @@ int lshmf_arena_bytes(const lshmf_ctx* ctx, size_t* bytes);
 int lshmf_bind(lshmf_ctx* ctx, const lshmf_tables* tables, void* d_arena, size_t arena_bytes);
 
 /* Ingest and layout of the training ratings (COO, d_u[n], d_i[n], d_rc[n],
- * n <= dims.nnz_cap, each (u, i) pair at most once; resets the model to
- * dims.M x dims.N): CSR by user, CSC by item,
- * the stratified block stream and the fixed baselines mu, b0, bh0 (Sec. 3.2,
- * the "simple case" means, reduced in FP64).  Ids outside [0,M) x [0,N) give
- * LSHMF_EINVAL after a stream synchronisation. */
+ * n <= dims.nnz_cap; resets the model to dims.M x dims.N): CSR by user, CSC
+ * by item, the stratified block stream and the fixed baselines mu, b0, bh0
+ * (Sec. 3.2, the "simple case" means, reduced in FP64).  Ids outside
+ * [0,M) x [0,N), codes outside 1..15 and a (u, i) pair given twice (R holds
+ * one value per pair, Sec. 3.1) give LSHMF_EINVAL after a stream
+ * synchronisation, with nothing bound to the model. */
 int lshmf_ingest(lshmf_ctx* ctx, const int32_t* d_u, const int32_t* d_i, const uint8_t* d_rc,
                  int64_t n, lshmf_stream_t stream);
 
-/* simLSH neighbours without the N x N similarity matrix (Sec. 4.1, Eq.
- * item_hash and Alg. CULSH): pre-sign sums acc = sum Psi(r) (2 H_i - 1),
- * signatures, q band keys of p*G bits, bucket collisions counted per item,
- * the K most frequent partners (ties by smaller id), a seeded random
- * supplement when fewer than K exist (SplitMix64(seed_fill, j*2^32 + a + 1)
- * mod N, a = 0, 1, ...), rows stored by ascending id.  d_H holds the random
- * user strings H_i, M rows of ceil(B/32) uint32 words.  Also resolves, for
- * every training rating (i, j), which neighbours of j user i has rated.
- * With K = 0 only acc and sig are computed.  Requires lshmf_ingest. */
-int build_lsh_neighbours(lshmf_ctx* ctx, const uint32_t* d_H, uint64_t seed_fill,
+/* LSH neighbours without the N x N similarity matrix (Sec. 4.1, Eq.
+ * item_hash and Alg. CULSH): per-item hash state and B-bit signatures, q band
+ * keys of p*G bits, bucket collisions counted per item, the K most frequent
+ * partners (ties by smaller id), a seeded random supplement when fewer than
+ * K exist (SplitMix64(seed_fill, j*2^32 + a + 1) mod N, a = 0, 1, ...), rows
+ * stored by ascending id.  Also resolves, for every training rating (i, j),
+ * which neighbours of j user i has rated.  With K = 0 only acc and sig are
+ * computed.  Requires lshmf_ingest.
+ *
+ * d_rand holds the random draws of the family, one row per user (M rows;
+ * online batches read rows up to M_new):
+ *   LSHMF_SIMLSH   the strings H_i: ceil(B/32) uint32 words, bit b at word
+ *                  b/32, bit b%32; acc = sum Psi(r) (2 H_i - 1), bit = [acc >= 0]
+ *   LSHMF_RPCOS    B FP32 Gaussian directions g_i; acc = sum r g_i in FP32,
+ *                  raters of an item in ascending user id, one fused
+ *                  multiply-add each; bit = [acc >= 0]
+ *   LSHMF_MINHASH  B/G uint32 random values v_i (a random order of the
+ *                  users per hash); acc = minimum of v_i over the raters,
+ *                  hash h = its G low bits at signature bits [hG, (h+1)G)
+ */
+int build_lsh_neighbours(lshmf_ctx* ctx, const void* d_rand, uint64_t seed_fill,
                          lshmf_stream_t stream);
+
+/* The objective of Eq. (loss_r) on the current tables, in FP64:
+ * d_loss[0] = sum over the training ratings of (r - rhat)^2 (rhat of Eq. rr
+ * in FP32, squared and summed in FP64) + lambda_b |b|^2 + lambda_bh |bh|^2 +
+ * lambda_u |U|^2 + lambda_v |V|^2 + lambda_w |W|^2 + lambda_c |C|^2, with
+ * lambda from hp and the w, c norms over every stored slot.  The reduction
+ * order is fixed, so the value is reproducible.  Requires
+ * build_lsh_neighbours. */
+int lshmf_loss(lshmf_ctx* ctx, const lshmf_hparams* hp, double* d_loss, lshmf_stream_t stream);
 
 /* One SGD epoch t (0-based) over all training ratings in the stratified
  * order: stratum s = 0..P-1 runs the P blocks (b, (b+s) mod P) of users
@@ -158,16 +190,23 @@ int build_lsh_neighbours(lshmf_ctx* ctx, const uint32_t* d_H, uint64_t seed_fill
  * (sgd_update) with the prediction of Eq. (rr), N(i) the complement of R(i)
  * (the CULSH-MF adjustment), and the residual baseline of the w-term fixed to
  * the simple-case means.  Results do not depend on how blocks are scheduled.
- * Requires build_lsh_neighbours. */
-int sgd_epoch(lshmf_ctx* ctx, const lshmf_hparams* hp, int32_t epoch, lshmf_stream_t stream);
+ * When d_loss_or_null is not NULL, the objective after the epoch is written
+ * there as by lshmf_loss.  Requires build_lsh_neighbours. */
+int sgd_epoch(lshmf_ctx* ctx, const lshmf_hparams* hp, int32_t epoch, double* d_loss_or_null,
+              lshmf_stream_t stream);
 
 /* Online learning (Sec. 4.3, Alg. "Online Learning") of a batch of n new
- * ratings (d_u, d_i, d_rc as for lshmf_ingest, pairs not already in the
- * store) that may bring new users [M, M_new) and new items [N, N_new):
- *   - the saved pre-sign sums acc grow by the batch's terms (rows of new items
- *     start at zero) and every signature is re-signed (Eq. item_hash);
+ * ratings (d_u, d_i, d_rc as for lshmf_ingest) that may bring new users
+ * [M, M_new) and new items [N, N_new):
+ *   - the saved hash state acc grows by the batch's terms (rows of new items
+ *     start empty) and every signature is recomputed (Eq. item_hash);
  *   - existing items keep JK; each new item gets its top-K from the band
- *     collisions over all N_new items, exactly as build_lsh_neighbours;
+ *     collisions over all N_new items, exactly as build_lsh_neighbours.
+ *     With flags & LSHMF_REBUILD_NBRS every item's list is searched again
+ *     instead, and the w, c values of the existing items follow their
+ *     neighbour ids: a neighbour kept by the new list brings its values to
+ *     its new slot, a new neighbour starts at 0 (a periodic rebuild for long
+ *     streams; the paper keeps the old lists);
  *   - mu and the existing b0, bh0 stay; a new id's fixed baseline is the mean
  *     of its batch ratings minus mu;
  *   - `passes` rounds of three SGD phases at the rate of epoch `epoch`, each
@@ -178,12 +217,15 @@ int sgd_epoch(lshmf_ctx* ctx, const lshmf_hparams* hp, int32_t epoch, lshmf_stre
  * The caller writes U rows [M, M_new) and V rows [N, N_new) before the call;
  * the library zeroes bu, bv, W, C of the new ids.  d_H holds M_new rows.
  * The batch joins the training set of later sgd_epoch calls.  Exceeding a
- * capacity gives LSHMF_ECAPACITY, ids outside [0,M_new) x [0,N_new)
- * LSHMF_EINVAL, both before any table is touched.  Requires
- * build_lsh_neighbours. */
+ * capacity, or a batch phase too large for one SGD block (raise n_strata),
+ * gives LSHMF_ECAPACITY; ids outside [0,M_new) x [0,N_new), bad codes, a
+ * pair given twice in the batch or already in the store give LSHMF_EINVAL;
+ * all before any table or the store is touched.  d_rand as for
+ * build_lsh_neighbours, M_new rows.  Requires build_lsh_neighbours. */
 int online_update(lshmf_ctx* ctx, const int32_t* d_u, const int32_t* d_i, const uint8_t* d_rc, int64_t n,
-                  int32_t M_new, int32_t N_new, const uint32_t* d_H, uint64_t seed_fill,
-                  const lshmf_hparams* hp, int32_t epoch, int32_t passes, lshmf_stream_t stream);
+                  int32_t M_new, int32_t N_new, const void* d_rand, uint64_t seed_fill,
+                  const lshmf_hparams* hp, int32_t epoch, int32_t passes, uint32_t flags,
+                  lshmf_stream_t stream);
 
 /* ---- Serving loop: continuous batching of online updates and queries ----
  *
@@ -224,7 +266,7 @@ typedef struct lshmf_serve_io {
     float* h_pred;             /* host, answers at each query request's offset      */
     const float* d_U0;         /* device, initial rows of new users [M_cap*F]       */
     const float* d_V0;         /* device, initial rows of new items [N_cap*F]       */
-    const uint32_t* d_H;       /* device, user strings of M_cap users               */
+    const void* d_rand;        /* device, hash-family draws of M_cap users          */
     uint64_t seed_fill;
     lshmf_hparams hp;
     int32_t epoch, passes;     /* online_update's learning-rate epoch and passes    */
@@ -258,6 +300,23 @@ int lshmf_sync_storage(lshmf_ctx* ctx, lshmf_stream_t stream);
  * fixed order: d_out[0] = sqrt(sum (rc/rscale - pred)^2 / n). */
 int lshmf_rmse(lshmf_ctx* ctx, const float* d_pred, const uint8_t* d_rc, int64_t n,
                double* d_out, lshmf_stream_t stream);
+
+/* Phase timing of build_lsh_neighbours (diagnostics).  While enabled, the
+ * call records HIP events at its phase boundaries on its stream (the events
+ * are created here; nothing else changes).  lshmf_lsh_phase_ms waits for the
+ * last event and writes the milliseconds of the phases of the last call:
+ * out[0] hash state (projection, minima), out[1] signatures, out[2] band keys
+ * and buckets, out[3] top-K lists and neighbour baselines, out[4] neighbour
+ * codes of the training ratings.  LSHMF_ESTATE if nothing was timed. */
+int lshmf_set_timing(lshmf_ctx* ctx, int32_t enable);
+int lshmf_lsh_phase_ms(lshmf_ctx* ctx, double* out);
+
+/* Synchronises the stream and reports the device status word: LSHMF_OK, or
+ * LSHMF_EDEVICE when an SGD dependency wait gave up after its spin limit (a
+ * broken hand-over; the tables are then not those of the stated order).  The
+ * library's own synchronising calls (lshmf_ingest, online_update,
+ * lshmf_serve and sgd_epoch when it lays the stream out again) report it too. */
+int lshmf_check(lshmf_ctx* ctx, lshmf_stream_t stream);
 
 /* Read-only device pointers into the arena, for inspection and tests: the
  * stratified stream (pk = user << 4 | code, sj = item, dep = previous rating

@@ -76,18 +76,25 @@ static int hbit(const uint32_t* H, int words, int64_t i, int b)
     return (int)((H[i * words + b / 32] >> (b % 32)) & 1u);
 }
 
-/* acc[j][b] += Psi(r_ij) * Phi(H_i,b) over the given ratings (no reset). */
+/* acc[j][b] += Psi(r_ij) * Phi(H_i,b) over the given ratings (no reset).   */
+/* The sums are integers, so their order does not matter: OpenMP threads    */
+/* take disjoint ranges of bits b and each walks all ratings.               */
 int orc_simlsh_add(int M, int N, int B, int64_t nnz, const int32_t* u, const int32_t* it,
                    const uint8_t* rc, const uint32_t* H, int psi_exp, int64_t* acc /* N*B */)
 {
     if (M <= 0 || N <= 0 || B <= 0 || nnz < 0) return ORC_EINVAL;
+    for (int64_t e = 0; e < nnz; ++e)
+        if (u[e] < 0 || u[e] >= M || it[e] < 0 || it[e] >= N) return ORC_EINVAL;
     const int words = (B + 31) / 32;
-    for (int64_t e = 0; e < nnz; ++e) {
-        const int i = u[e], j = it[e];
-        if (i < 0 || i >= M || j < 0 || j >= N) return ORC_EINVAL;
-        const int64_t w = psi_of(rc[e], psi_exp);
-        for (int b = 0; b < B; ++b)
-            acc[(int64_t)j * B + b] += w * (2 * hbit(H, words, i, b) - 1);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int wd = 0; wd < words; ++wd) {
+        const int b1 = (wd + 1) * 32 < B ? (wd + 1) * 32 : B;
+        for (int64_t e = 0; e < nnz; ++e) {
+            const int i = u[e], j = it[e];
+            const int64_t w = psi_of(rc[e], psi_exp);
+            for (int b = wd * 32; b < b1; ++b)
+                acc[(int64_t)j * B + b] += w * (2 * hbit(H, words, i, b) - 1);
+        }
     }
     return ORC_OK;
 }

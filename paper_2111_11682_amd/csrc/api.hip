@@ -8,14 +8,15 @@
 namespace lshmf {
 const char* last_error();
 int ingest(lshmf_ctx* c, const int32_t* u, const int32_t* it, const uint8_t* rc, int64_t n, hipStream_t s);
-int build_neighbours(lshmf_ctx* c, const uint32_t* H, uint64_t seed_fill, hipStream_t s);
+int build_neighbours(lshmf_ctx* c, const void* R, uint64_t seed_fill, hipStream_t s);
 int build_stream(lshmf_ctx* c, Stream& st, const int32_t* u, const int32_t* it, const uint8_t* rc, int64_t n,
                  hipStream_t s);
 int stream_codes(lshmf_ctx* c, Stream& st, hipStream_t s);
 int run_sgd(lshmf_ctx* c, Stream& st, const lshmf_hparams* hp, int epoch, int upd, hipStream_t s);
 int run_online(lshmf_ctx* c, const int32_t* u, const int32_t* it, const uint8_t* rc, int64_t n, int32_t M_new,
-               int32_t N_new, const uint32_t* H, uint64_t seed_fill, const lshmf_hparams* hp, int epoch,
-               int passes, hipStream_t s);
+               int32_t N_new, const void* R, uint64_t seed_fill, const lshmf_hparams* hp, int epoch,
+               int passes, uint32_t flags, hipStream_t s);
+int run_loss(lshmf_ctx* c, const lshmf_hparams* hp, double* out, hipStream_t s);
 int run_predict(lshmf_ctx* c, const int32_t* qu, const int32_t* qi, int64_t n, float* out, hipStream_t s);
 int run_rmse(lshmf_ctx* c, const float* pred, const uint8_t* rc, int64_t n, double* out, hipStream_t s);
 int refresh_bf16(lshmf_ctx* c, int64_t m0, int64_t m1, int64_t n0, int64_t n1, hipStream_t s);
@@ -98,11 +99,15 @@ size_t carve(lshmf_ctx* c, char* base)
     const size_t scan_n2 = scan_tmp_elems(c->sort_n);
     if (scan_n2 > scan_n) scan_n = scan_n2;
     c->scan_tmp = k.take<int64_t>(scan_n);
-    c->red = k.take<double>(1024);
+    c->red = k.take<double>(8192);
     c->nbr_b0 = k.take<float>((size_t)Nc * d.K);
     c->bitem = k.take<int32_t>(nq);
     c->bbegin = k.take<int32_t>(nq + 1);
     c->bpos = k.take<int32_t>(nq);
+    const int64_t nk_old = Nc * (int64_t)d.K;  // a rebuild keeps the old lists, w and c here
+    c->old_jk = k.take<int32_t>(nk_old);
+    c->old_w = k.take<float>(nk_old);
+    c->old_c = k.take<float>(nk_old);
     c->err = k.take<int32_t>(64);
     return (k.off + 255) & ~size_t(255);
 }
@@ -126,8 +131,18 @@ int validate(const lshmf_dims* d)
         set_error("K=%d outside 0..min(128, N-1)", d->K);
         return LSHMF_EINVAL;
     }
-    if (d->G < 1 || d->p < 1 || d->q < 1 || B > 256 || (int64_t)d->G * d->p > 32 || d->q > 2048) {
-        set_error("simLSH shape G=%d p=%d q=%d: need G*p*q <= 256, G*p <= 32", d->G, d->p, d->q);
+    if (d->G < 1 || d->p < 1 || d->q < 1 || B > 8192 || (int64_t)d->G * d->p > 56 || d->q > 4096 ||
+        d->G * d->p + bits_for((uint64_t)d->q) > 64) {
+        set_error("hash shape G=%d p=%d q=%d: need G*p*q <= 8192, G*p <= 56, q <= 4096 and G*p + "
+                  "ceil(log2 q) <= 64", d->G, d->p, d->q);
+        return LSHMF_EINVAL;
+    }
+    if (d->hash_family != LSHMF_SIMLSH && d->hash_family != LSHMF_RPCOS && d->hash_family != LSHMF_MINHASH) {
+        set_error("hash_family=%d is none of LSHMF_SIMLSH, LSHMF_RPCOS, LSHMF_MINHASH", d->hash_family);
+        return LSHMF_EINVAL;
+    }
+    if (d->hash_family == LSHMF_MINHASH && d->G > 32) {
+        set_error("minHash keeps at most the 32 bits of a minimum per hash (G=%d)", d->G);
         return LSHMF_EINVAL;
     }
     if (d->rscale != 1 && d->rscale != 2) {
@@ -210,7 +225,45 @@ int lshmf_create(const lshmf_dims* dims, lshmf_ctx** out)
     return LSHMF_OK;
 }
 
-void lshmf_destroy(lshmf_ctx* ctx) { delete ctx; }
+void lshmf_destroy(lshmf_ctx* ctx)
+{
+    if (!ctx) return;
+    for (hipEvent_t& e : ctx->ev)
+        if (e) (void)hipEventDestroy(e);
+    delete ctx;
+}
+
+int lshmf_set_timing(lshmf_ctx* ctx, int32_t enable)
+{
+    if (!ctx) {
+        set_error("lshmf_set_timing: NULL context");
+        return LSHMF_EINVAL;
+    }
+    if (enable && !ctx->ev[0])
+        for (hipEvent_t& e : ctx->ev) LSHMF_HIP(hipEventCreate(&e));
+    ctx->timing = enable != 0;
+    ctx->timed = false;
+    return LSHMF_OK;
+}
+
+int lshmf_lsh_phase_ms(lshmf_ctx* ctx, double* out)
+{
+    if (!ctx || !out) {
+        set_error("lshmf_lsh_phase_ms: NULL argument");
+        return LSHMF_EINVAL;
+    }
+    if (!ctx->timed) {
+        set_error("lshmf_lsh_phase_ms: no timed neighbour search since timing was enabled");
+        return LSHMF_ESTATE;
+    }
+    LSHMF_HIP(hipEventSynchronize(ctx->ev[5]));
+    for (int k = 0; k < 5; ++k) {
+        float ms = 0.0f;
+        LSHMF_HIP(hipEventElapsedTime(&ms, ctx->ev[k], ctx->ev[k + 1]));
+        out[k] = ms;
+    }
+    return LSHMF_OK;
+}
 
 int lshmf_arena_bytes(const lshmf_ctx* ctx, size_t* bytes)
 {
@@ -279,24 +332,52 @@ int lshmf_ingest(lshmf_ctx* ctx, const int32_t* d_u, const int32_t* d_i, const u
     return LSHMF_OK;
 }
 
-int build_lsh_neighbours(lshmf_ctx* ctx, const uint32_t* d_H, uint64_t seed_fill, lshmf_stream_t stream)
+int build_lsh_neighbours(lshmf_ctx* ctx, const void* d_rand, uint64_t seed_fill, lshmf_stream_t stream)
 {
     if (!ctx || !ctx->ingested) {
         set_error("build_lsh_neighbours: ratings not ingested");
         return LSHMF_ESTATE;
     }
-    if (!d_H) {
-        set_error("build_lsh_neighbours: H is NULL");
+    if (!d_rand) {
+        set_error("build_lsh_neighbours: the random draws are NULL");
         return LSHMF_EINVAL;
     }
     const hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    LSHMF_TRY(build_neighbours(ctx, d_H, seed_fill, s));
+    LSHMF_TRY(build_neighbours(ctx, d_rand, seed_fill, s));
     LSHMF_TRY(refresh_bf16(ctx, 0, ctx->M, 0, ctx->N, s));
     ctx->neighbours = true;
     return LSHMF_OK;
 }
 
-int sgd_epoch(lshmf_ctx* ctx, const lshmf_hparams* hp, int32_t epoch, lshmf_stream_t stream)
+// The training stream of the whole store, laid out again when online batches
+// grew the store, with neighbour codes for the current lists.
+static int ensure_train(lshmf_ctx* ctx, hipStream_t s)
+{
+    if (ctx->train_stale) {
+        LSHMF_TRY(build_stream(ctx, ctx->train, ctx->coo_u, ctx->coo_i, ctx->coo_rc, ctx->nnz, s));
+        ctx->train_stale = false;
+    }
+    if (!ctx->train.codes) LSHMF_TRY(stream_codes(ctx, ctx->train, s));
+    return LSHMF_OK;
+}
+
+int lshmf_loss(lshmf_ctx* ctx, const lshmf_hparams* hp, double* d_loss, lshmf_stream_t stream)
+{
+    if (!ctx || !ctx->neighbours) {
+        set_error("lshmf_loss: neighbours not built");
+        return LSHMF_ESTATE;
+    }
+    if (!hp || !d_loss) {
+        set_error("lshmf_loss: NULL argument");
+        return LSHMF_EINVAL;
+    }
+    const hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    LSHMF_TRY(ensure_train(ctx, s));
+    return run_loss(ctx, hp, d_loss, s);
+}
+
+int sgd_epoch(lshmf_ctx* ctx, const lshmf_hparams* hp, int32_t epoch, double* d_loss_or_null,
+              lshmf_stream_t stream)
 {
     if (!ctx || !ctx->neighbours) {
         set_error("sgd_epoch: neighbours not built");
@@ -307,25 +388,32 @@ int sgd_epoch(lshmf_ctx* ctx, const lshmf_hparams* hp, int32_t epoch, lshmf_stre
         return LSHMF_EINVAL;
     }
     const hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    if (ctx->train_stale) {  // the store grew by online batches since the stream was laid out
-        LSHMF_TRY(build_stream(ctx, ctx->train, ctx->coo_u, ctx->coo_i, ctx->coo_rc, ctx->nnz, s));
-        ctx->train_stale = false;
-    }
-    if (!ctx->train.codes) LSHMF_TRY(stream_codes(ctx, ctx->train, s));
+    LSHMF_TRY(ensure_train(ctx, s));
     LSHMF_TRY(run_sgd(ctx, ctx->train, hp, epoch, 3, s));
     // the SGD writes only the FP32 masters; the BF16 copies follow in one pass
-    return refresh_bf16(ctx, 0, ctx->M, 0, ctx->N, s);
+    LSHMF_TRY(refresh_bf16(ctx, 0, ctx->M, 0, ctx->N, s));
+    return d_loss_or_null ? run_loss(ctx, hp, d_loss_or_null, s) : LSHMF_OK;
+}
+
+int lshmf_check(lshmf_ctx* ctx, lshmf_stream_t stream)
+{
+    if (!ctx || !ctx->bound) {
+        set_error("lshmf_check: context not bound");
+        return LSHMF_ESTATE;
+    }
+    return sync_status(ctx, reinterpret_cast<hipStream_t>(stream));
 }
 
 int online_update(lshmf_ctx* ctx, const int32_t* d_u, const int32_t* d_i, const uint8_t* d_rc, int64_t n,
-                  int32_t M_new, int32_t N_new, const uint32_t* d_H, uint64_t seed_fill, const lshmf_hparams* hp,
-                  int32_t epoch, int32_t passes, lshmf_stream_t stream)
+                  int32_t M_new, int32_t N_new, const void* d_rand, uint64_t seed_fill, const lshmf_hparams* hp,
+                  int32_t epoch, int32_t passes, uint32_t flags, lshmf_stream_t stream)
 {
     if (!ctx || !ctx->neighbours) {
         set_error("online_update: neighbours not built");
         return LSHMF_ESTATE;
     }
-    if (!hp || epoch < 0 || passes < 0 || !d_H || n < 0 || (n > 0 && (!d_u || !d_i || !d_rc))) {
+    if (!hp || epoch < 0 || passes < 0 || !d_rand || n < 0 || (n > 0 && (!d_u || !d_i || !d_rc)) ||
+        (flags & ~(uint32_t)LSHMF_REBUILD_NBRS)) {
         set_error("online_update: bad arguments");
         return LSHMF_EINVAL;
     }
@@ -339,7 +427,7 @@ int online_update(lshmf_ctx* ctx, const int32_t* d_u, const int32_t* d_i, const 
                   (long long)ctx->d.batch_cap, (long long)ctx->d.nnz_cap);
         return LSHMF_ECAPACITY;
     }
-    return run_online(ctx, d_u, d_i, d_rc, n, M_new, N_new, d_H, seed_fill, hp, epoch, passes,
+    return run_online(ctx, d_u, d_i, d_rc, n, M_new, N_new, d_rand, seed_fill, hp, epoch, passes, flags,
                       reinterpret_cast<hipStream_t>(stream));
 }
 

@@ -8,6 +8,8 @@
 
 #include "lshmf.h"
 
+struct lshmf_ctx;
+
 namespace lshmf {
 
 constexpr int kWave = 64;
@@ -58,6 +60,10 @@ int radix_sort(uint64_t* keys[2], uint32_t* vals[2], int64_t n, int bits, int64_
 
 // Per-bin counts of idx[0..n) into cnt[0..nbins) (cnt zeroed by the call).
 int count_bins(const int32_t* idx, int64_t n, int64_t* cnt, int64_t nbins, hipStream_t s);
+
+// Synchronises s and reports the SGD status word c->err[0]: LSHMF_EDEVICE
+// (with a message) when a dependency wait gave up, else LSHMF_OK.
+int sync_status(lshmf_ctx* c, hipStream_t s);
 
 // Fills.
 int fill_i64(int64_t* p, int64_t n, int64_t v, hipStream_t s);
@@ -147,5 +153,24 @@ struct lshmf_ctx {
     int32_t* bitem;            // q*N_cap  items sorted by (band, key)
     int32_t* bbegin;           // q*N_cap+1 bucket starts (by bucket id)
     int32_t* bpos;             // q*N_cap  bucket id of (band t, item j) at t*N + j
-    int32_t* err;              // device status word
+    int32_t* old_jk;           // N_cap*K  lists, w and c before a rebuild
+    float* old_w;
+    float* old_c;
+    int32_t* err;              // device status words: [0] SGD waits, [1] input checks
+
+    // phase timing of the neighbour search (diagnostics)
+    bool timing = false, timed = false;
+    hipEvent_t ev[6] = {};
 };
+
+namespace lshmf {
+// Records phase boundary k of the neighbour search when timing is on.
+inline int mark(lshmf_ctx* c, int k, hipStream_t s)
+{
+    if (c->timing) {
+        LSHMF_HIP(hipEventRecord(c->ev[k], s));
+        if (k == 5) c->timed = true;
+    }
+    return LSHMF_OK;
+}
+}  // namespace lshmf

@@ -24,6 +24,33 @@ __global__ void k_check_ids(const int32_t* u, const int32_t* it, const uint8_t* 
     }
 }
 
+// A (user, item) pair given twice: adjacent equal keys after a sort by pair.
+__global__ void k_dup_flags(const uint64_t* keys, int64_t n, int32_t* err)
+{
+    for (int64_t x = 1 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < n;
+         x += (int64_t)gridDim.x * blockDim.x)
+        if (keys[x] == keys[x - 1]) atomicOr(err, 2);
+}
+
+// A batch pair (u, i) already in the store: binary search of i in the CSR
+// row of u (users >= M_old have no row yet).
+__global__ void k_in_store(const int32_t* u, const int32_t* it, int64_t n, int32_t M_old, const int64_t* row_ptr,
+                           const int32_t* col, int32_t* err)
+{
+    for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < n;
+         x += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t i = u[x], j = it[x];
+        if (i >= M_old) continue;
+        int64_t l = row_ptr[i], r = row_ptr[i + 1];
+        while (l < r) {
+            const int64_t m = (l + r) >> 1;
+            if (col[m] < j) l = m + 1;
+            else r = m;
+        }
+        if (l < row_ptr[i + 1] && col[l] == j) atomicOr(err, 4);
+    }
+}
+
 // key = user * N + item  (CSR order)  or  item * M + user  (CSC order)
 __global__ void k_keys_pair(const int32_t* major, const int32_t* minor, int64_t n, int64_t nminor,
                             uint64_t* keys, uint32_t* vals)
@@ -269,6 +296,47 @@ static unsigned grid_for(int64_t n, int threads = 256, int64_t cap = 16384)
     return (unsigned)(b > cap ? cap : b);
 }
 
+int sync_status(lshmf_ctx* c, hipStream_t s)
+{
+    int32_t herr = 0;
+    LSHMF_HIP(hipMemcpyAsync(&herr, c->err, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    LSHMF_HIP(hipStreamSynchronize(s));
+    if (herr) {
+        set_error("an SGD dependency wait gave up after its spin limit (status word %#x): a broken hand-over, "
+                  "the tables do not follow the stated order", herr);
+        return LSHMF_EDEVICE;
+    }
+    return LSHMF_OK;
+}
+
+// Reads the input-check word c->err[1] (bit 0 ids or codes out of range, bit 1
+// a pair given twice, bit 2 a pair already in the store) after a
+// synchronisation; reports the SGD status word as sync_status does.
+static int input_status(lshmf_ctx* c, int32_t M, int32_t N, hipStream_t s)
+{
+    int32_t herr[2] = {0, 0};
+    LSHMF_HIP(hipMemcpyAsync(herr, c->err, sizeof(herr), hipMemcpyDeviceToHost, s));
+    LSHMF_HIP(hipStreamSynchronize(s));
+    if (herr[1] & 1) {
+        set_error("a rating has a user outside [0,%d), an item outside [0,%d) or a code outside 1..15", M, N);
+        return LSHMF_EINVAL;
+    }
+    if (herr[1] & 2) {
+        set_error("a (user, item) pair is given twice");
+        return LSHMF_EINVAL;
+    }
+    if (herr[1] & 4) {
+        set_error("a (user, item) pair of the batch is already in the store");
+        return LSHMF_EINVAL;
+    }
+    if (herr[0]) {
+        set_error("an SGD dependency wait gave up after its spin limit (status word %#x): a broken hand-over, "
+                  "the tables do not follow the stated order", herr[0]);
+        return LSHMF_EDEVICE;
+    }
+    return LSHMF_OK;
+}
+
 int check_ids(lshmf_ctx* c, const int32_t* u, const int32_t* it, const uint8_t* rc, int64_t n, int32_t M,
               int32_t N, hipStream_t s)
 {
@@ -278,20 +346,34 @@ int check_ids(lshmf_ctx* c, const int32_t* u, const int32_t* it, const uint8_t* 
         hipLaunchKernelGGL(k_check_ids, dim3(grid_for(n)), dim3(256), 0, s, u, it, rc, n, M, N, flag);
         LSHMF_LAUNCHED("k_check_ids");
     }
-    int32_t herr = 0;
-    LSHMF_HIP(hipMemcpyAsync(&herr, flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    LSHMF_HIP(hipStreamSynchronize(s));
-    if (herr) {
-        set_error("a rating has a user outside [0,%d), an item outside [0,%d) or a code outside 1..15", M, N);
-        return LSHMF_EINVAL;
-    }
-    return LSHMF_OK;
+    return input_status(c, M, N, s);
+}
+
+// Online batch: no pair twice in the batch and none already in the store.
+// Uses the sort buffers; the ids were checked before.
+int check_batch_pairs(lshmf_ctx* c, const int32_t* u, const int32_t* it, int64_t n, int32_t M_new, int32_t N_new,
+                      hipStream_t s)
+{
+    if (n <= 0) return LSHMF_OK;
+    int32_t* flag = c->err + 1;
+    LSHMF_TRY(fill_i32(flag, 1, 0, s));
+    hipLaunchKernelGGL(k_keys_pair, dim3(grid_for(n)), dim3(256), 0, s, u, it, n, (int64_t)N_new, c->sk[0], c->sv[0]);
+    LSHMF_LAUNCHED("k_keys_pair(batch)");
+    int ri = 0;
+    LSHMF_TRY(radix_sort(c->sk, c->sv, n, bits_for((uint64_t)M_new * (uint64_t)N_new), c->hist, c->scan_tmp, s,
+                         &ri));
+    hipLaunchKernelGGL(k_dup_flags, dim3(grid_for(n)), dim3(256), 0, s, c->sk[ri], n, flag);
+    LSHMF_LAUNCHED("k_dup_flags(batch)");
+    hipLaunchKernelGGL(k_in_store, dim3(grid_for(n)), dim3(256), 0, s, u, it, n, c->M, c->row_ptr, c->csr_col, flag);
+    LSHMF_LAUNCHED("k_in_store");
+    return input_status(c, M_new, N_new, s);
 }
 
 // Compressed copy of n ratings by `major` (ptr over n_major rows, minor ids
 // ascending inside a row).
 int compress(lshmf_ctx* c, const int32_t* major, const int32_t* minor, const uint8_t* rc, int64_t n,
-             int64_t n_major, int64_t n_minor, int64_t* ptr, int32_t* idx, uint8_t* rc_out, hipStream_t s)
+             int64_t n_major, int64_t n_minor, int64_t* ptr, int32_t* idx, uint8_t* rc_out, hipStream_t s,
+             int32_t* dup_flag)
 {
     int ri = 0;
     if (n > 0) {
@@ -300,6 +382,10 @@ int compress(lshmf_ctx* c, const int32_t* major, const int32_t* minor, const uin
         LSHMF_LAUNCHED("k_keys_pair");
         LSHMF_TRY(radix_sort(c->sk, c->sv, n, bits_for((uint64_t)n_major * (uint64_t)n_minor), c->hist,
                              c->scan_tmp, s, &ri));
+        if (dup_flag) {
+            hipLaunchKernelGGL(k_dup_flags, dim3(grid_for(n)), dim3(256), 0, s, c->sk[ri], n, dup_flag);
+            LSHMF_LAUNCHED("k_dup_flags");
+        }
         hipLaunchKernelGGL(k_gather_pair, dim3(grid_for(n)), dim3(256), 0, s, c->sv[ri], minor, rc, n, idx, rc_out);
         LSHMF_LAUNCHED("k_gather_pair");
     }
@@ -308,10 +394,13 @@ int compress(lshmf_ctx* c, const int32_t* major, const int32_t* minor, const uin
 }
 
 // CSR and CSC of the store's c->nnz ratings over c->M users and c->N items.
-int build_compressed(lshmf_ctx* c, hipStream_t s)
+// dup_flag: a word that gets bit 1 when a pair occurs twice (or NULL).
+int build_compressed(lshmf_ctx* c, hipStream_t s, int32_t* dup_flag)
 {
-    LSHMF_TRY(compress(c, c->coo_i, c->coo_u, c->coo_rc, c->nnz, c->N, c->M, c->col_ptr, c->csc_row, c->csc_rc, s));
-    return compress(c, c->coo_u, c->coo_i, c->coo_rc, c->nnz, c->M, c->N, c->row_ptr, c->csr_col, c->csr_rc, s);
+    LSHMF_TRY(compress(c, c->coo_i, c->coo_u, c->coo_rc, c->nnz, c->N, c->M, c->col_ptr, c->csc_row, c->csc_rc, s,
+                       nullptr));
+    return compress(c, c->coo_u, c->coo_i, c->coo_rc, c->nnz, c->M, c->N, c->row_ptr, c->csr_col, c->csr_rc, s,
+                    dup_flag);
 }
 
 // The stratified stream of n ratings (u, it, rc) over the current M x N.
@@ -401,11 +490,20 @@ int build_stream(lshmf_ctx* c, Stream& st, const int32_t* u, const int32_t* it, 
     hipError_t e = hipMemcpyAsync(hptr, st.blk_ptr, sizeof(int64_t) * nb, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipMemcpyAsync(hptr + nb, st.blk_seg, sizeof(int64_t) * nb, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipMemcpyAsync(hslots, st.blk_slots, sizeof(int32_t) * (nb - 1), hipMemcpyDeviceToHost, s);
+    int32_t herr = 0;
+    if (e == hipSuccess) e = hipMemcpyAsync(&herr, c->err, sizeof(int32_t), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
         delete[] hptr;
         delete[] hslots;
         return hip_fail(e, "stream block pointers");
+    }
+    if (herr) {
+        delete[] hptr;
+        delete[] hslots;
+        set_error("an SGD dependency wait gave up after its spin limit (status word %#x): a broken hand-over, "
+                  "the tables do not follow the stated order", herr);
+        return LSHMF_EDEVICE;
     }
     int64_t mx = 0, msl = 0;
     for (int64_t b = 0; b < P * P; ++b) {
@@ -469,7 +567,8 @@ int ingest(lshmf_ctx* c, const int32_t* u, const int32_t* it, const uint8_t* rc,
         LSHMF_HIP(hipMemcpyAsync(c->coo_rc, rc, n, hipMemcpyDeviceToDevice, s));
     }
     c->nnz = n;
-    LSHMF_TRY(build_compressed(c, s));
+    LSHMF_TRY(build_compressed(c, s, c->err + 1));
+    LSHMF_TRY(input_status(c, c->M, c->N, s));  // a pair given twice
     LSHMF_TRY(baselines_all(c, s));
     LSHMF_TRY(build_stream(c, c->train, c->coo_u, c->coo_i, c->coo_rc, n, s));
     c->train_stale = false;

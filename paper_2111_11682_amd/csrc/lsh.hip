@@ -4,6 +4,9 @@
 //                   (Eq. item_hash).  Integer arithmetic, so the sums are exact
 //                   and independent of the order of the atomic flushes.
 //   k_simlsh_sign   Upsilon: bit b of item j is set iff acc[j][b] >= 0.
+//   k_rpcos_*,      the two other families of the Sec. 5.3 comparison (sign
+//   k_minhash_*     random projection, b-bit minwise hashing) filling the
+//                   same signature layout.
 //   k_band_keys     q band keys of p*G bits (p hashes ANDed per band).
 //   k_bucket_*      one radix sort of (band, key) groups the items of every
 //                   bucket; a bucket id per (band, item).
@@ -18,19 +21,31 @@
 namespace lshmf {
 
 // ------------------------------------------------------------ projection
-constexpr int kAccChunk = 512;     // CSC positions per wave
-constexpr int kMaxBitsPerLane = 4; // B <= 256
+// A wave walks a chunk of CSC positions.  Lane (g, w) owns signature word w
+// of the current 64-word slice (32 bits) and takes the positions p of the
+// chunk with p = first + g (mod R), R = 64 / Wd rating groups, Wd the slice's
+// word count rounded up to a power of two.  Per rating it loads one word of
+// H_i and adds Psi(r) to the counters of its set bits, S_t += Psi * bit_t;
+// T sums Psi.  At a column change the lane adds its part of
+// acc[j][32w + t] = sum Psi (2 bit - 1) = 2 S_t - T with integer atomics, so
+// the sums are exact and independent of the order of the flushes (the
+// counters wrap modulo 2^32; the exact total fits int32).
+constexpr int kAccChunk = 1024;    // CSC positions per wave
 
 __global__ __launch_bounds__(256) void k_simlsh_acc(const int64_t* col_ptr, const int32_t* row,
                                                     const uint8_t* rc, int64_t nnz, int32_t N,
                                                     const uint32_t* H, int words, int B, int psi_exp,
-                                                    int32_t* acc)
+                                                    int wd_log2, int32_t* acc)
 {
     const int lane = threadIdx.x & (kWave - 1);
     const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kWave;
     const int64_t p0 = wave * kAccChunk;
     if (p0 >= nnz) return;
     const int64_t p1 = p0 + kAccChunk < nnz ? p0 + kAccChunk : nnz;
+    const int R = kWave >> wd_log2;
+    const int grp = lane >> wd_log2;
+    const int w = (int)blockIdx.y * kWave + (lane & ((1 << wd_log2) - 1));
+    const bool wok = w < words;
     // column containing p0: largest j with col_ptr[j] <= p0
     int32_t lo = 0, hi = N;  // invariant col_ptr[lo] <= p0 < col_ptr[hi]
     while (hi - lo > 1) {
@@ -40,37 +55,40 @@ __global__ __launch_bounds__(256) void k_simlsh_acc(const int64_t* col_ptr, cons
     }
     int32_t j = lo;
     int64_t jend = col_ptr[j + 1];
-    int32_t a[kMaxBitsPerLane] = {0, 0, 0, 0};
-    const int nsl = (B + kWave - 1) / kWave;
-    for (int64_t p = p0; p < p1; ++p) {
-        while (p >= jend) {
-            for (int sl = 0; sl < nsl; ++sl) {
-                const int b = lane + sl * kWave;
-                if (b < B && a[sl] != 0) atomicAdd(&acc[(int64_t)j * B + b], a[sl]);
-                a[sl] = 0;
+    uint32_t S[32];
+#pragma unroll
+    for (int t = 0; t < 32; ++t) S[t] = 0u;
+    uint32_t T = 0u;
+    auto flush = [&]() {
+        if (wok && T != 0u) {
+            int32_t* a = acc + (int64_t)j * B + 32 * w;
+#pragma unroll
+            for (int t = 0; t < 32; ++t) {
+                const int32_t v = (int32_t)(2u * S[t] - T);
+                if (32 * w + t < B && v != 0) atomicAdd(a + t, v);
+                S[t] = 0u;
             }
-            ++j;
-            jend = col_ptr[j + 1];
+        }
+        T = 0u;
+    };
+    for (int64_t p = p0 + grp; p < p1; p += R) {
+        if (p >= jend) {
+            flush();
+            do {
+                ++j;
+                jend = col_ptr[j + 1];
+            } while (p >= jend);
         }
         const int64_t i = row[p];
-        const int code = rc[p];
-        int32_t w = 1;
-        for (int e = 0; e < psi_exp; ++e) w *= code;
+        const uint32_t x = wok ? H[i * words + w] : 0u;
+        uint32_t psi = 1u;
+        const uint32_t code = rc[p];
+        for (int e = 0; e < psi_exp; ++e) psi *= code;
+        T += psi;
 #pragma unroll
-        for (int sl = 0; sl < kMaxBitsPerLane; ++sl) {
-            if (sl < nsl) {
-                const int b = lane + sl * kWave;
-                if (b < B) {
-                    const uint32_t hw = H[i * words + (b >> 5)];
-                    a[sl] += ((hw >> (b & 31)) & 1u) ? w : -w;
-                }
-            }
-        }
+        for (int t = 0; t < 32; ++t) S[t] += ((x >> t) & 1u) * psi;
     }
-    for (int sl = 0; sl < nsl; ++sl) {
-        const int b = lane + sl * kWave;
-        if (b < B && a[sl] != 0) atomicAdd(&acc[(int64_t)j * B + b], a[sl]);
-    }
+    flush();
 }
 
 __global__ void k_simlsh_sign(const int32_t* acc, int32_t N, int B, int words, uint32_t* sig)
@@ -88,6 +106,85 @@ __global__ void k_simlsh_sign(const int32_t* acc, int32_t N, int B, int words, u
     }
 }
 
+// RP_cos (sign random projection for the cosine similarity, the family of
+// the Sec. 5.3 comparison): acc[j][b] += r_ij g_ib in FP32.  The sign is an
+// integer decided by floating point, so the order is fixed: one wave per
+// (item, 64-bit slice), lane b sums the item's raters in CSC order (users
+// ascending) with one fused multiply-add each, continuing the stored sum.
+__global__ __launch_bounds__(256) void k_rpcos_acc(const int64_t* col_ptr, const int32_t* row, const uint8_t* rc,
+                                                   int32_t N, const float* g, int B, float inv_s, float* acc)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kWave;
+    const int slices = (B + kWave - 1) / kWave;
+    if (wave >= (int64_t)N * slices) return;
+    const int64_t j = wave / slices;
+    const int b = (int)(wave % slices) * kWave + lane;
+    const int64_t a = col_ptr[j], z = col_ptr[j + 1];
+    if (a == z) return;
+    const bool ok = b < B;
+    float s = ok ? acc[j * B + b] : 0.0f;
+    for (int64_t p = a; p < z; ++p) {
+        const float r = (float)rc[p] * inv_s;
+        const float gv = ok ? g[(int64_t)row[p] * B + b] : 0.0f;
+        s = __builtin_fmaf(r, gv, s);
+    }
+    if (ok) acc[j * B + b] = s;
+}
+
+__global__ void k_rpcos_sign(const float* acc, int32_t N, int B, int words, uint32_t* sig)
+{
+    for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < (int64_t)N * words;
+         x += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t j = x / words;
+        const int w = (int)(x % words);
+        uint32_t v = 0;
+        for (int t = 0; t < 32; ++t) {
+            const int b = w * 32 + t;
+            if (b < B && acc[j * B + b] >= 0.0f) v |= 1u << t;
+        }
+        sig[x] = v;
+    }
+}
+
+// minHash (b-bit minwise hashing of the rater sets): mins[j][h] = least random
+// value v_ih over the raters of item j; integer minima are exact and order-free.
+__global__ __launch_bounds__(256) void k_minhash_acc(const int64_t* col_ptr, const int32_t* row, int32_t N,
+                                                     const uint32_t* v, int nh, uint32_t* mins)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kWave;
+    const int slices = (nh + kWave - 1) / kWave;
+    if (wave >= (int64_t)N * slices) return;
+    const int64_t j = wave / slices;
+    const int h = (int)(wave % slices) * kWave + lane;
+    const int64_t a = col_ptr[j], z = col_ptr[j + 1];
+    if (a == z || h >= nh) return;
+    uint32_t m = mins[j * nh + h];
+    for (int64_t p = a; p < z; ++p) {
+        const uint32_t x = v[(int64_t)row[p] * nh + h];
+        m = x < m ? x : m;
+    }
+    mins[j * nh + h] = m;
+}
+
+// The G low bits of each minimum, hash h at bits [hG, (h+1)G) of the signature.
+__global__ void k_minhash_sign(const uint32_t* mins, int32_t N, int nh, int G, int words, uint32_t* sig)
+{
+    const int B = nh * G;
+    for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < (int64_t)N * words;
+         x += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t j = x / words;
+        const int w = (int)(x % words);
+        uint32_t v = 0;
+        for (int t = 0; t < 32; ++t) {
+            const int b = w * 32 + t;
+            if (b < B && ((mins[j * nh + b / G] >> (b % G)) & 1u)) v |= 1u << t;
+        }
+        sig[x] = v;
+    }
+}
+
 // --------------------------------------------------------------- banding
 __global__ void k_band_keys(const uint32_t* sig, int32_t N, int words, int pG, int q, uint64_t* keys,
                             uint32_t* vals)
@@ -98,11 +195,13 @@ __global__ void k_band_keys(const uint32_t* sig, int32_t N, int words, int pG, i
         const int t = (int)(x / N);
         const int64_t j = x % N;
         const int off = t * pG;
-        const int w0 = off >> 5, sh = off & 31;  // pG <= 32: two words suffice
-        uint64_t v = sig[j * words + w0];
-        if (w0 + 1 < words) v |= (uint64_t)sig[j * words + w0 + 1] << 32;
+        const int w0 = off >> 5, sh = off & 31;  // pG <= 56: three words suffice
+        const uint32_t* r = sig + j * words;
+        uint64_t v = r[w0];
+        if (w0 + 1 < words) v |= (uint64_t)r[w0 + 1] << 32;
         v >>= sh;
-        const uint64_t key = v & ((pG >= 64) ? ~0ull : ((1ull << pG) - 1ull));
+        if (sh > 0 && w0 + 2 < words) v |= (uint64_t)r[w0 + 2] << (64 - sh);
+        const uint64_t key = v & ((1ull << pG) - 1ull);
         keys[x] = ((uint64_t)t << pG) | key;
         vals[x] = (uint32_t)j;
     }
@@ -352,24 +451,65 @@ static unsigned grid_for(int64_t n, int threads = 256, int64_t cap = 16384)
     return (unsigned)(b > cap ? cap : b);
 }
 
-// acc += Psi(r)(2H-1) over the ratings of a CSC (col_ptr over c->N items).
+// Adds the ratings of a CSC (col_ptr over c->N items) to the per-item hash
+// state of the context's family: simLSH sums Psi(r)(2H-1) (R: bit strings
+// H, ceil(B/32) words per user), RP_cos sums r g (R: B Gaussians per user),
+// minHash minima (R: B/G random values per user).
 int hash_add(lshmf_ctx* c, const int64_t* col_ptr, const int32_t* row, const uint8_t* rc, int64_t nnz,
-             const uint32_t* H, hipStream_t s)
+             const void* R, hipStream_t s)
 {
-    const int64_t waves = ceil_div(nnz, kAccChunk);
-    if (waves > 0) {
-        hipLaunchKernelGGL(k_simlsh_acc, dim3((unsigned)ceil_div(waves * kWave, 256)), dim3(256), 0, s, col_ptr, row,
-                           rc, nnz, c->N, H, c->words, c->B, c->d.psi_exp, c->t.acc);
+    if (nnz <= 0) return LSHMF_OK;
+    const int fam = c->d.hash_family;
+    if (fam == LSHMF_SIMLSH) {
+        const int64_t waves = ceil_div(nnz, kAccChunk);
+        const int slices = (c->words + kWave - 1) / kWave;
+        const int in_slice = c->words < kWave ? c->words : kWave;
+        const int wd_log2 = bits_for((uint64_t)in_slice);  // smallest power of two >= the slice's words
+        hipLaunchKernelGGL(k_simlsh_acc, dim3((unsigned)ceil_div(waves * kWave, 256), (unsigned)slices), dim3(256), 0,
+                           s, col_ptr, row, rc, nnz, c->N, static_cast<const uint32_t*>(R), c->words, c->B,
+                           c->d.psi_exp, wd_log2, c->t.acc);
         LSHMF_LAUNCHED("k_simlsh_acc");
+    } else if (fam == LSHMF_RPCOS) {
+        const int64_t waves = (int64_t)c->N * ceil_div(c->B, kWave);
+        hipLaunchKernelGGL(k_rpcos_acc, dim3((unsigned)ceil_div(waves * kWave, 256)), dim3(256), 0, s, col_ptr, row, rc,
+                           c->N, static_cast<const float*>(R), c->B, 1.0f / (float)c->d.rscale,
+                           reinterpret_cast<float*>(c->t.acc));
+        LSHMF_LAUNCHED("k_rpcos_acc");
+    } else {
+        const int nh = c->B / c->d.G;
+        const int64_t waves = (int64_t)c->N * ceil_div(nh, kWave);
+        hipLaunchKernelGGL(k_minhash_acc, dim3((unsigned)ceil_div(waves * kWave, 256)), dim3(256), 0, s, col_ptr, row,
+                           c->N, static_cast<const uint32_t*>(R), nh, reinterpret_cast<uint32_t*>(c->t.acc));
+        LSHMF_LAUNCHED("k_minhash_acc");
     }
     return LSHMF_OK;
 }
 
+// Empty hash state of items [n0, n1): zero sums, or the all-ones minimum.
+int hash_clear(lshmf_ctx* c, int64_t n0, int64_t n1, hipStream_t s)
+{
+    if (c->d.hash_family == LSHMF_MINHASH) {
+        const int64_t nh = c->B / c->d.G;
+        return fill_i32(c->t.acc + n0 * nh, (n1 - n0) * nh, -1, s);
+    }
+    return fill_i32(c->t.acc + n0 * c->B, (n1 - n0) * c->B, 0, s);
+}
+
 int signs(lshmf_ctx* c, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_simlsh_sign, dim3(grid_for((int64_t)c->N * c->words)), dim3(256), 0, s, c->t.acc, c->N,
-                       c->B, c->words, c->t.sig);
-    LSHMF_LAUNCHED("k_simlsh_sign");
+    const unsigned g = grid_for((int64_t)c->N * c->words);
+    if (c->d.hash_family == LSHMF_SIMLSH) {
+        hipLaunchKernelGGL(k_simlsh_sign, dim3(g), dim3(256), 0, s, c->t.acc, c->N, c->B, c->words, c->t.sig);
+        LSHMF_LAUNCHED("k_simlsh_sign");
+    } else if (c->d.hash_family == LSHMF_RPCOS) {
+        hipLaunchKernelGGL(k_rpcos_sign, dim3(g), dim3(256), 0, s, reinterpret_cast<const float*>(c->t.acc), c->N,
+                           c->B, c->words, c->t.sig);
+        LSHMF_LAUNCHED("k_rpcos_sign");
+    } else {
+        hipLaunchKernelGGL(k_minhash_sign, dim3(g), dim3(256), 0, s, reinterpret_cast<const uint32_t*>(c->t.acc),
+                           c->N, c->B / c->d.G, c->d.G, c->words, c->t.sig);
+        LSHMF_LAUNCHED("k_minhash_sign");
+    }
     return LSHMF_OK;
 }
 
@@ -378,7 +518,11 @@ int signs(lshmf_ctx* c, hipStream_t s)
 int neighbours_for(lshmf_ctx* c, int32_t j_first, int32_t count, uint64_t seed_fill, hipStream_t s)
 {
     const lshmf_dims& d = c->d;
-    if (d.K == 0) return LSHMF_OK;  // no neighbour lists to find
+    if (d.K == 0) {  // no neighbour lists to find
+        LSHMF_TRY(mark(c, 3, s));
+        LSHMF_TRY(mark(c, 4, s));
+        return LSHMF_OK;
+    }
     const int64_t nq = (int64_t)d.q * c->N;
     hipLaunchKernelGGL(k_band_keys, dim3(grid_for(nq)), dim3(256), 0, s, c->t.sig, c->N, c->words, c->pG, d.q,
                        c->sk[0], c->sv[0]);
@@ -392,6 +536,7 @@ int neighbours_for(lshmf_ctx* c, int32_t j_first, int32_t count, uint64_t seed_f
     hipLaunchKernelGGL(k_bucket_fill, dim3(grid_for(nq)), dim3(256), 0, s, c->sk[ri], c->sv[ri], ex, nq, c->N,
                        c->pG, c->bitem, c->bbegin, c->bpos);
     LSHMF_LAUNCHED("k_bucket_fill");
+    LSHMF_TRY(mark(c, 3, s));
     for (int32_t j0 = 0; j0 < count; j0 += 65535) {
         const int32_t nj = count - j0 < 65535 ? count - j0 : 65535;
         hipLaunchKernelGGL(k_topk, dim3((unsigned)nj), dim3(kTopkThreads), 0, s, c->bitem, c->bbegin, c->bpos, c->N,
@@ -405,6 +550,7 @@ int neighbours_for(lshmf_ctx* c, int32_t j_first, int32_t count, uint64_t seed_f
                            c->t.bh0, nk, c->nbr_b0 + (int64_t)j_first * d.K);
         LSHMF_LAUNCHED("k_nbr_b0");
     }
+    LSHMF_TRY(mark(c, 4, s));
     return LSHMF_OK;
 }
 
@@ -420,13 +566,67 @@ int stream_codes(lshmf_ctx* c, Stream& st, hipStream_t s)
     return LSHMF_OK;
 }
 
-int build_neighbours(lshmf_ctx* c, const uint32_t* H, uint64_t seed_fill, hipStream_t s)
+// w, c of the old items after a rebuild of every list: a neighbour kept
+// across the rebuild brings its values to its new slot, a new one starts at
+// 0.  Both lists are sorted by id, so each lane finds its neighbour by binary
+// search in the old row.  One wave per item.
+__global__ __launch_bounds__(256) void k_remap_slots(const int32_t* JK_old, const float* W_old, const float* C_old,
+                                                     const int32_t* JK_new, int32_t n_old, int K, float* W, float* C)
 {
-    LSHMF_TRY(fill_i32(c->t.acc, (int64_t)c->N * c->B, 0, s));
-    LSHMF_TRY(hash_add(c, c->col_ptr, c->csc_row, c->csc_rc, c->nnz, H, s));
-    LSHMF_TRY(signs(c, s));
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t w0 = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kWave;
+    const int64_t nw = (int64_t)gridDim.x * blockDim.x / kWave;
+    for (int64_t j = w0; j < n_old; j += nw) {
+        const int32_t* old = JK_old + j * K;
+        for (int k = lane; k < K; k += kWave) {
+            const int32_t n = JK_new[j * K + k];
+            int l = 0, r = K;
+            while (l < r) {
+                const int m = (l + r) >> 1;
+                if (old[m] < n) l = m + 1;
+                else r = m;
+            }
+            const bool kept = l < K && old[l] == n;
+            W[j * K + k] = kept ? W_old[j * K + l] : 0.0f;
+            C[j * K + k] = kept ? C_old[j * K + l] : 0.0f;
+        }
+    }
+}
+
+// Every item's list searched again over the current signatures; W and C of
+// items [0, n_old) follow their neighbour ids (the rows of newer items must
+// already be zero).  The old lists and tables are kept in the arena.
+int rebuild_lists(lshmf_ctx* c, int32_t n_old, uint64_t seed_fill, hipStream_t s)
+{
+    const int64_t nk = (int64_t)n_old * c->d.K;
+    if (c->d.K == 0) return LSHMF_OK;
+    if (nk > 0) {
+        LSHMF_HIP(hipMemcpyAsync(c->old_jk, c->t.JK, sizeof(int32_t) * nk, hipMemcpyDeviceToDevice, s));
+        LSHMF_HIP(hipMemcpyAsync(c->old_w, c->t.W, sizeof(float) * nk, hipMemcpyDeviceToDevice, s));
+        LSHMF_HIP(hipMemcpyAsync(c->old_c, c->t.C, sizeof(float) * nk, hipMemcpyDeviceToDevice, s));
+    }
     LSHMF_TRY(neighbours_for(c, 0, c->N, seed_fill, s));
-    return stream_codes(c, c->train, s);
+    if (nk > 0) {
+        hipLaunchKernelGGL(k_remap_slots, dim3(grid_for((int64_t)n_old * kWave)), dim3(256), 0, s, c->old_jk,
+                           c->old_w, c->old_c, c->t.JK, n_old, c->d.K, c->t.W, c->t.C);
+        LSHMF_LAUNCHED("k_remap_slots");
+    }
+    return LSHMF_OK;
+}
+
+int build_neighbours(lshmf_ctx* c, const void* R, uint64_t seed_fill, hipStream_t s)
+{
+    c->timed = false;
+    LSHMF_TRY(mark(c, 0, s));
+    LSHMF_TRY(hash_clear(c, 0, c->N, s));
+    LSHMF_TRY(hash_add(c, c->col_ptr, c->csc_row, c->csc_rc, c->nnz, R, s));
+    LSHMF_TRY(mark(c, 1, s));
+    LSHMF_TRY(signs(c, s));
+    LSHMF_TRY(mark(c, 2, s));
+    LSHMF_TRY(neighbours_for(c, 0, c->N, seed_fill, s));
+    LSHMF_TRY(stream_codes(c, c->train, s));
+    LSHMF_TRY(mark(c, 5, s));
+    return LSHMF_OK;
 }
 
 }  // namespace lshmf

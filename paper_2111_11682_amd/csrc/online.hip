@@ -2,11 +2,13 @@
 // possibly from new users and on new items, is folded into a trained model
 // without rebuilding the similarity structure of the existing items.
 //
-//   1. the saved simLSH pre-sign sums (Eq. item_hash) of the items the batch
-//      touches grow by the batch's terms, new items starting from zero, and
-//      all signatures are re-signed;
+//   1. the saved hash state (simLSH pre-sign sums of Eq. item_hash, or the
+//      RP_cos sums / minHash minima) of the items the batch touches grows by
+//      the batch's terms, new items starting empty, and all signatures are
+//      recomputed;
 //   2. existing items keep their neighbour lists; each new item gets its
-//      top-K from the band collisions over all items;
+//      top-K from the band collisions over all items (with the rebuild flag,
+//      every list is searched again and w, c follow their neighbour ids);
 //   3. mu and the existing fixed baselines stay; a new user's or item's fixed
 //      baseline is the mean of its batch ratings minus mu;
 //   4. `passes` times, three SGD phases over the batch, each in the
@@ -14,25 +16,33 @@
 //      items update only the user side, ratings on new items only the item
 //      side, the rest both sides.
 // The caller writes the initial factor rows u_i, v_j of the new ids before
-// the call; the library zeroes their b_i, bh_j, w_j, c_j.
+// the call; the library zeroes their b_i, bh_j, w_j, c_j.  Every refusal
+// (ids, codes, repeated pairs, a phase too large for one SGD block) comes
+// before the store, the tables or the training stream change.
 #include "common.hpp"
 
 namespace lshmf {
 
 int check_ids(lshmf_ctx* c, const int32_t* u, const int32_t* it, const uint8_t* rc, int64_t n, int32_t M,
               int32_t N, hipStream_t s);
+int check_batch_pairs(lshmf_ctx* c, const int32_t* u, const int32_t* it, int64_t n, int32_t M_new, int32_t N_new,
+                      hipStream_t s);
 int compress(lshmf_ctx* c, const int32_t* major, const int32_t* minor, const uint8_t* rc, int64_t n,
-             int64_t n_major, int64_t n_minor, int64_t* ptr, int32_t* idx, uint8_t* rc_out, hipStream_t s);
-int build_compressed(lshmf_ctx* c, hipStream_t s);
+             int64_t n_major, int64_t n_minor, int64_t* ptr, int32_t* idx, uint8_t* rc_out, hipStream_t s,
+             int32_t* dup_flag);
+int build_compressed(lshmf_ctx* c, hipStream_t s, int32_t* dup_flag);
 int build_stream(lshmf_ctx* c, Stream& st, const int32_t* u, const int32_t* it, const uint8_t* rc, int64_t n,
                  hipStream_t s);
 int baselines_new(lshmf_ctx* c, const int32_t* id, const uint8_t* rc, int64_t n, int32_t first, int32_t count,
                   float* out, hipStream_t s);
 int hash_add(lshmf_ctx* c, const int64_t* col_ptr, const int32_t* row, const uint8_t* rc, int64_t nnz,
-             const uint32_t* H, hipStream_t s);
+             const void* R, hipStream_t s);
+int hash_clear(lshmf_ctx* c, int64_t n0, int64_t n1, hipStream_t s);
 int signs(lshmf_ctx* c, hipStream_t s);
 int neighbours_for(lshmf_ctx* c, int32_t j_first, int32_t count, uint64_t seed_fill, hipStream_t s);
+int rebuild_lists(lshmf_ctx* c, int32_t n_old, uint64_t seed_fill, hipStream_t s);
 int stream_codes(lshmf_ctx* c, Stream& st, hipStream_t s);
+int sgd_fits(const lshmf_ctx* c, const Stream& st);
 int run_sgd(lshmf_ctx* c, Stream& st, const lshmf_hparams* hp, int epoch, int upd, hipStream_t s);
 int refresh_bf16(lshmf_ctx* c, int64_t m0, int64_t m1, int64_t n0, int64_t n1, hipStream_t s);
 
@@ -73,51 +83,13 @@ unsigned grid_for(int64_t n, int threads = 256, int64_t cap = 16384)
 
 }  // namespace
 
-int run_online(lshmf_ctx* c, const int32_t* u, const int32_t* it, const uint8_t* rc, int64_t n, int32_t M_new,
-               int32_t N_new, const uint32_t* H, uint64_t seed_fill, const lshmf_hparams* hp, int epoch,
-               int passes, hipStream_t s)
+// The batch split into its three phases, each laid out as its own stratified
+// stream over the grown id ranges c->M x c->N (arena scratch only: the
+// store, the tables and the training stream are not touched), and each
+// checked against the SGD kernel's per-block limits.
+static int layout_phases(lshmf_ctx* c, const int32_t* u, const int32_t* it, const uint8_t* rc, int64_t n,
+                         int32_t M_old, int32_t N_old, hipStream_t s)
 {
-    LSHMF_TRY(check_ids(c, u, it, rc, n, M_new, N_new, s));
-    const int32_t M_old = c->M, N_old = c->N;
-    const int K = c->d.K, B = c->B;
-    c->M = M_new;
-    c->N = N_new;
-    // the model can no longer be trained or queried as before until this call succeeds
-    c->neighbours = false;
-    c->train_stale = true;
-    c->train.codes = false;
-
-    // append the batch to the rating store
-    if (n > 0) {
-        LSHMF_HIP(hipMemcpyAsync(c->coo_u + c->nnz, u, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, s));
-        LSHMF_HIP(hipMemcpyAsync(c->coo_i + c->nnz, it, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, s));
-        LSHMF_HIP(hipMemcpyAsync(c->coo_rc + c->nnz, rc, n, hipMemcpyDeviceToDevice, s));
-    }
-
-    // 1. incremental pre-sign sums over the batch, by item, then signatures
-    LSHMF_TRY(compress(c, it, u, rc, n, N_new, M_new, c->bcol_ptr, c->bcsc_row, c->bcsc_rc, s));
-    LSHMF_TRY(fill_i32(c->t.acc + (int64_t)N_old * B, (int64_t)(N_new - N_old) * B, 0, s));
-    LSHMF_TRY(hash_add(c, c->bcol_ptr, c->bcsc_row, c->bcsc_rc, n, H, s));
-    LSHMF_TRY(signs(c, s));
-
-    // learned parameters of the new ids start at zero
-    LSHMF_TRY(fill_f32(c->t.bu + M_old, M_new - M_old, 0.0f, s));
-    LSHMF_TRY(fill_f32(c->t.bv + N_old, N_new - N_old, 0.0f, s));
-    LSHMF_TRY(fill_f32(c->t.W + (int64_t)N_old * K, (int64_t)(N_new - N_old) * K, 0.0f, s));
-    LSHMF_TRY(fill_f32(c->t.C + (int64_t)N_old * K, (int64_t)(N_new - N_old) * K, 0.0f, s));
-
-    // 3. fixed baselines of the new ids (before the neighbour baselines read them)
-    LSHMF_TRY(baselines_new(c, u, rc, n, M_old, M_new - M_old, c->t.b0, s));
-    LSHMF_TRY(baselines_new(c, it, rc, n, N_old, N_new - N_old, c->t.bh0, s));
-
-    // R(i) now includes the batch
-    c->nnz += n;
-    LSHMF_TRY(build_compressed(c, s));
-
-    // 2. neighbour lists of the new items only
-    if (N_new > N_old) LSHMF_TRY(neighbours_for(c, N_old, N_new - N_old, seed_fill, s));
-
-    // 4. the batch split into its three phases, each laid out as a stream
     int64_t cnt[3] = {0, 0, 0};
     if (n > 0) {
         int32_t* phase = c->e2s;
@@ -136,9 +108,67 @@ int run_online(lshmf_ctx* c, const int32_t* u, const int32_t* it, const uint8_t*
     int64_t off = 0;
     for (int k = 0; k < 3; ++k) {
         LSHMF_TRY(build_stream(c, c->phase[k], c->bat_u + off, c->bat_i + off, c->bat_rc + off, cnt[k], s));
-        LSHMF_TRY(stream_codes(c, c->phase[k], s));
+        LSHMF_TRY(sgd_fits(c, c->phase[k]));
         off += cnt[k];
     }
+    return LSHMF_OK;
+}
+
+int run_online(lshmf_ctx* c, const int32_t* u, const int32_t* it, const uint8_t* rc, int64_t n, int32_t M_new,
+               int32_t N_new, const void* R, uint64_t seed_fill, const lshmf_hparams* hp, int epoch,
+               int passes, uint32_t flags, hipStream_t s)
+{
+    // every refusal comes before the model, the store or the training stream change
+    LSHMF_TRY(check_ids(c, u, it, rc, n, M_new, N_new, s));
+    LSHMF_TRY(check_batch_pairs(c, u, it, n, M_new, N_new, s));
+    const int32_t M_old = c->M, N_old = c->N;
+    const int K = c->d.K;
+    c->M = M_new;
+    c->N = N_new;
+    const int st = layout_phases(c, u, it, rc, n, M_old, N_old, s);
+    if (st != LSHMF_OK) {
+        c->M = M_old;
+        c->N = N_old;
+        return st;
+    }
+    // the model can no longer be trained or queried as before until this call succeeds
+    c->neighbours = false;
+    c->train_stale = true;
+    c->train.codes = false;
+
+    // append the batch to the rating store
+    if (n > 0) {
+        LSHMF_HIP(hipMemcpyAsync(c->coo_u + c->nnz, u, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, s));
+        LSHMF_HIP(hipMemcpyAsync(c->coo_i + c->nnz, it, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, s));
+        LSHMF_HIP(hipMemcpyAsync(c->coo_rc + c->nnz, rc, n, hipMemcpyDeviceToDevice, s));
+    }
+
+    // 1. the saved hash state grows by the batch, by item, then signatures
+    LSHMF_TRY(compress(c, it, u, rc, n, N_new, M_new, c->bcol_ptr, c->bcsc_row, c->bcsc_rc, s, nullptr));
+    LSHMF_TRY(hash_clear(c, N_old, N_new, s));
+    LSHMF_TRY(hash_add(c, c->bcol_ptr, c->bcsc_row, c->bcsc_rc, n, R, s));
+    LSHMF_TRY(signs(c, s));
+
+    // learned parameters of the new ids start at zero
+    LSHMF_TRY(fill_f32(c->t.bu + M_old, M_new - M_old, 0.0f, s));
+    LSHMF_TRY(fill_f32(c->t.bv + N_old, N_new - N_old, 0.0f, s));
+    LSHMF_TRY(fill_f32(c->t.W + (int64_t)N_old * K, (int64_t)(N_new - N_old) * K, 0.0f, s));
+    LSHMF_TRY(fill_f32(c->t.C + (int64_t)N_old * K, (int64_t)(N_new - N_old) * K, 0.0f, s));
+
+    // 3. fixed baselines of the new ids (before the neighbour baselines read them)
+    LSHMF_TRY(baselines_new(c, u, rc, n, M_old, M_new - M_old, c->t.b0, s));
+    LSHMF_TRY(baselines_new(c, it, rc, n, N_old, N_new - N_old, c->t.bh0, s));
+
+    // R(i) now includes the batch
+    c->nnz += n;
+    LSHMF_TRY(build_compressed(c, s, nullptr));
+
+    // 2. neighbour lists of the new items only, or of every item on a rebuild
+    if (flags & LSHMF_REBUILD_NBRS) LSHMF_TRY(rebuild_lists(c, N_old, seed_fill, s));
+    else if (N_new > N_old) LSHMF_TRY(neighbours_for(c, N_old, N_new - N_old, seed_fill, s));
+
+    // 4. the three phases of the batch
+    for (int k = 0; k < 3; ++k) LSHMF_TRY(stream_codes(c, c->phase[k], s));
     static const int kUpd[3] = {1, 2, 3};  // user side, item side, both
     for (int p = 0; p < passes; ++p)
         for (int k = 0; k < 3; ++k) LSHMF_TRY(run_sgd(c, c->phase[k], hp, epoch, kUpd[k], s));

@@ -195,9 +195,9 @@ int lshmf_serve(lshmf_ctx* ctx, const lshmf_serve_io* io, lshmf_stream_t compute
                     break;
                 }
                 io->h_start[next] = seconds_since(t0);
-                const int st = online_update(ctx, su, si, src, q.n, q.M_new, q.N_new, io->d_H, io->seed_fill, &io->hp,
-                                             io->epoch, io->passes, compute_);
-                if (st == LSHMF_EINVAL) {  // ids out of range: nothing was changed
+                const int st = online_update(ctx, su, si, src, q.n, q.M_new, q.N_new, io->d_rand, io->seed_fill,
+                                             &io->hp, io->epoch, io->passes, 0u, compute_);
+                if (st == LSHMF_EINVAL || st == LSHMF_ECAPACITY) {  // refused before anything changed
                     io->h_done[next] = seconds_since(t0);
                     io->h_status[next] = st;
                     ++retired;
@@ -300,6 +300,7 @@ int lshmf_serve(lshmf_ctx* ctx, const lshmf_serve_io* io, lshmf_stream_t compute
     for (int k = 0; k < kEvents; ++k) (void)hipEventDestroy(pool[k]);
     if (status == LSHMF_OK && e1 != hipSuccess) status = hip_fail(e1, "hipStreamSynchronize(compute)");
     if (status == LSHMF_OK && e2 != hipSuccess) status = hip_fail(e2, "hipStreamSynchronize(copy)");
+    if (status == LSHMF_OK) status = sync_status(ctx, cs);  // an SGD wait that gave up
     return status;
 }
 

@@ -17,6 +17,7 @@
 #include <cmath>
 
 #include "common.hpp"
+#include "wave.hpp"
 
 namespace lshmf {
 
@@ -64,37 +65,6 @@ struct SgdArgs {
     float inv_s;
     float g[6], l[6];
 };
-
-template <int CTRL, int ROW_MASK, bool BOUND_ZERO>
-__device__ inline float dpp_f32(float x)
-{
-    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), CTRL, ROW_MASK,
-                                                                 0xF, BOUND_ZERO));
-}
-
-// FP32 -> BF16 with round-to-nearest-even on the dropped 16 bits (NaN stays
-// a quiet NaN).
-__device__ inline uint16_t to_bf16(float x)
-{
-    const uint32_t u = __float_as_uint(x);
-    if ((u & 0x7FFFFFFFu) > 0x7F800000u) return (uint16_t)0x7FC0u;
-    return (uint16_t)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
-}
-
-__device__ inline float from_bf16(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
-
-// Full 64-lane sum with DPP row operations; the total ends in lane 63 and is
-// broadcast through a scalar register.  Fixed association order.
-__device__ inline float wave_sum(float v)
-{
-    v += dpp_f32<0xB1, 0xF, true>(v);    // quad_perm [1,0,3,2]
-    v += dpp_f32<0x4E, 0xF, true>(v);    // quad_perm [2,3,0,1]
-    v += dpp_f32<0x141, 0xF, true>(v);   // row_half_mirror
-    v += dpp_f32<0x140, 0xF, true>(v);   // row_mirror: every lane holds its row's sum
-    v += dpp_f32<0x142, 0xA, false>(v);  // row_bcast:15 into rows 1 and 3
-    v += dpp_f32<0x143, 0xC, false>(v);  // row_bcast:31 into rows 2 and 3
-    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 63));
-}
 
 // User-side HBM inputs of one group of ratings, loaded a group ahead of use.
 // A user rated earlier in the same block is read from the block's LDS mailbox
@@ -732,35 +702,6 @@ __global__ __launch_bounds__(kSgdWaves* kWave) void k_sgd_stratum(SgdArgs a, con
     }
 }
 
-// BF16 copies of n FP32 values.
-__global__ void k_to_bf16(const float* src, uint16_t* dst, int64_t n)
-{
-    for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < n;
-         x += (int64_t)gridDim.x * blockDim.x)
-        dst[x] = to_bf16(src[x]);
-}
-
-int to_bf16_rows(const float* src, uint16_t* dst, int64_t n, hipStream_t s)
-{
-    if (n <= 0) return LSHMF_OK;
-    int64_t b = ceil_div(n, 256);
-    if (b > 16384) b = 16384;
-    hipLaunchKernelGGL(k_to_bf16, dim3((unsigned)b), dim3(256), 0, s, src, dst, n);
-    LSHMF_LAUNCHED("k_to_bf16");
-    return LSHMF_OK;
-}
-
-// BF16 copies of the rows [m0, m1) of U and [n0, n1) of V, W, C.
-int refresh_bf16(lshmf_ctx* c, int64_t m0, int64_t m1, int64_t n0, int64_t n1, hipStream_t s)
-{
-    if (c->d.storage != LSHMF_BF16) return LSHMF_OK;
-    const int64_t F = c->d.F, K = c->d.K;
-    LSHMF_TRY(to_bf16_rows(c->t.U + m0 * F, c->t.U16 + m0 * F, (m1 - m0) * F, s));
-    LSHMF_TRY(to_bf16_rows(c->t.V + n0 * F, c->t.V16 + n0 * F, (n1 - n0) * F, s));
-    LSHMF_TRY(to_bf16_rows(c->t.W + n0 * K, c->t.W16 + n0 * K, (n1 - n0) * K, s));
-    return to_bf16_rows(c->t.C + n0 * K, c->t.C16 + n0 * K, (n1 - n0) * K, s);
-}
-
 // Dynamic LDS of one block: the mailbox (slots + 1 rows of F floats, b_i and
 // a sequence word) and the gang rings.
 static size_t sgd_lds_bytes(const SgdArgs& args)
@@ -790,18 +731,26 @@ static int launch_sgd_k(const SgdArgs& args, const uint32_t* pk, const uint32_t*
     return args.K <= kWave ? launch_sgd<FP, 1>(args, pk, link, s) : launch_sgd<FP, 2>(args, pk, link, s);
 }
 
-// One SGD pass over a stream; upd selects the parameter sides to update.
-int run_sgd(lshmf_ctx* c, Stream& st, const lshmf_hparams* hp, int epoch, int upd, hipStream_t s)
+// Can k_sgd_stratum run this stream: the mailbox of every block in LDS and
+// its chain positions and slots inside the hand-over word's fields?
+int sgd_fits(const lshmf_ctx* c, const Stream& st)
 {
-    const lshmf_dims& d = c->d;
-    if (st.n == 0) return LSHMF_OK;
-    const size_t lds = (size_t)(st.max_block_slots + 1) * (d.F + 2) * sizeof(float);
+    const size_t lds = (size_t)(st.max_block_slots + 1) * (c->d.F + 2) * sizeof(float);
     if (st.max_block_slots > kMaxSlots || lds > (size_t)kMaxMailboxBytes || st.max_block_nnz > kMaxChainPos) {
         set_error("sgd: a block needs %lld mailbox slots (%zu bytes of LDS, limit %d) or holds %lld "
                   "ratings (limit %d); raise n_strata",
                   (long long)st.max_block_slots, lds, kMaxMailboxBytes, (long long)st.max_block_nnz, kMaxChainPos);
         return LSHMF_ECAPACITY;
     }
+    return LSHMF_OK;
+}
+
+// One SGD pass over a stream; upd selects the parameter sides to update.
+int run_sgd(lshmf_ctx* c, Stream& st, const lshmf_hparams* hp, int epoch, int upd, hipStream_t s)
+{
+    const lshmf_dims& d = c->d;
+    if (st.n == 0) return LSHMF_OK;
+    LSHMF_TRY(sgd_fits(c, st));
     SgdArgs a;
     // K = 0: no codes; the kernel's clamped code reads then land on the sink
     a.nib = c->nstride > 0 ? st.nib : reinterpret_cast<const uint8_t*>(c->trash);
@@ -848,183 +797,6 @@ int run_sgd(lshmf_ctx* c, Stream& st, const lshmf_hparams* hp, int epoch, int up
             default: LSHMF_TRY(launch_sgd_k<4>(a, st.pk, st.link, s)); break;
         }
     }
-    return LSHMF_OK;
-}
-
-// ---------------------------------------------------------------- predict
-struct PredArgs {
-    const int32_t* JK;
-    const float* b0;
-    const float* bh0;
-    const double* mu;
-    const void* U;    // float, or BF16 bits in storage mode BF16
-    const void* V;
-    const float* bu;
-    const float* bv;
-    const void* W;
-    const void* C;
-    const int64_t* row_ptr;
-    const int32_t* csr_col;
-    const uint8_t* csr_rc;
-    int M, N, F, K;
-    float inv_s;
-};
-
-__device__ inline float ld_tab(const float* p, int64_t x) { return p[x]; }
-__device__ inline float ld_tab(const uint16_t* p, int64_t x) { return from_bf16(p[x]); }
-
-// One wave per query: Eq. (rr) with R^K / N^K resolved by binary search of
-// each neighbour in the user's training row.  T: storage type of U, V, W, C.
-template <int FP, int KP, typename T>
-__global__ __launch_bounds__(256) void k_predict(PredArgs a, const int32_t* qu, const int32_t* qi, int64_t n,
-                                                 float* out)
-{
-    const T* U = static_cast<const T*>(a.U);
-    const T* V = static_cast<const T*>(a.V);
-    const T* W = static_cast<const T*>(a.W);
-    const T* C = static_cast<const T*>(a.C);
-    const int lane = threadIdx.x & (kWave - 1);
-    const int64_t w0 = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kWave;
-    const int64_t nw = (int64_t)gridDim.x * blockDim.x / kWave;
-    const float mu = (float)(*a.mu);
-    const int F = a.F, K = a.K;
-    for (int64_t x = w0; x < n; x += nw) {
-        const int64_t i = qu[x], j = qi[x];
-        if (i < 0 || i >= a.M || j < 0 || j >= a.N) {
-            if (lane == 0) out[x] = __int_as_float(0x7fc00000);
-            continue;
-        }
-        const int64_t ra = a.row_ptr[i], rz = a.row_ptr[i + 1];
-        float part = 0.0f;
-#pragma unroll
-        for (int y = 0; y < FP; ++y) {
-            const int f = lane + y * kWave;
-            if (f < F) part += ld_tab(U, i * F + f) * ld_tab(V, j * F + f);
-        }
-        int code[KP];
-        int nb[KP];
-        int nR = 0;
-#pragma unroll
-        for (int y = 0; y < KP; ++y) {
-            const int k = lane + y * kWave;
-            code[y] = 0;
-            nb[y] = 0;
-            if (k < K) {
-                nb[y] = a.JK[j * K + k];
-                int64_t l = ra, r = rz;
-                while (l < r) {
-                    const int64_t m = (l + r) >> 1;
-                    if (a.csr_col[m] < nb[y]) l = m + 1;
-                    else r = m;
-                }
-                code[y] = (l < rz && a.csr_col[l] == nb[y]) ? a.csr_rc[l] : 0;
-            }
-            nR += __popcll(__ballot(code[y] != 0));
-        }
-        const int nN = K - nR;
-        const float sR = nR > 0 ? 1.0f / sqrtf((float)nR) : 0.0f;
-        const float sN = nN > 0 ? 1.0f / sqrtf((float)nN) : 0.0f;
-        const float base_i = mu + a.b0[i];
-#pragma unroll
-        for (int y = 0; y < KP; ++y) {
-            const int k = lane + y * kWave;
-            if (k < K) {
-                if (code[y]) part += ((float)code[y] * a.inv_s - base_i - a.bh0[nb[y]]) * ld_tab(W, j * K + k) * sR;
-                else part += ld_tab(C, j * K + k) * sN;
-            }
-        }
-        const float tot = wave_sum(part);
-        if (lane == 0) out[x] = mu + a.bu[i] + a.bv[j] + tot;
-    }
-}
-
-template <int FP, typename T>
-static void launch_predict_t(const PredArgs& a, const int32_t* qu, const int32_t* qi, int64_t n, float* out,
-                             unsigned grid, hipStream_t s)
-{
-    if (a.K <= kWave)
-        hipLaunchKernelGGL((k_predict<FP, 1, T>), dim3(grid), dim3(256), 0, s, a, qu, qi, n, out);
-    else
-        hipLaunchKernelGGL((k_predict<FP, 2, T>), dim3(grid), dim3(256), 0, s, a, qu, qi, n, out);
-}
-
-template <int FP>
-static void launch_predict_k(const PredArgs& a, bool bf, const int32_t* qu, const int32_t* qi, int64_t n,
-                             float* out, unsigned grid, hipStream_t s)
-{
-    if (bf) launch_predict_t<FP, uint16_t>(a, qu, qi, n, out, grid, s);
-    else launch_predict_t<FP, float>(a, qu, qi, n, out, grid, s);
-}
-
-int run_predict(lshmf_ctx* c, const int32_t* qu, const int32_t* qi, int64_t n, float* out, hipStream_t s)
-{
-    if (n <= 0) return LSHMF_OK;
-    const lshmf_dims& d = c->d;
-    const bool bf = d.storage == LSHMF_BF16;
-    PredArgs a{c->t.JK, c->t.b0, c->t.bh0, c->t.mu,
-               bf ? (const void*)c->t.U16 : (const void*)c->t.U, bf ? (const void*)c->t.V16 : (const void*)c->t.V,
-               c->t.bu, c->t.bv,
-               bf ? (const void*)c->t.W16 : (const void*)c->t.W, bf ? (const void*)c->t.C16 : (const void*)c->t.C,
-               c->row_ptr, c->csr_col, c->csr_rc, c->M, c->N, d.F, d.K, 1.0f / (float)d.rscale};
-    int64_t blocks = ceil_div(n * kWave, 256);
-    if (blocks > 65536) blocks = 65536;
-    const int fp = (d.F + kWave - 1) / kWave;
-    switch (fp) {
-        case 1: launch_predict_k<1>(a, bf, qu, qi, n, out, (unsigned)blocks, s); break;
-        case 2: launch_predict_k<2>(a, bf, qu, qi, n, out, (unsigned)blocks, s); break;
-        case 3: launch_predict_k<3>(a, bf, qu, qi, n, out, (unsigned)blocks, s); break;
-        default: launch_predict_k<4>(a, bf, qu, qi, n, out, (unsigned)blocks, s); break;
-    }
-    LSHMF_LAUNCHED("k_predict");
-    return LSHMF_OK;
-}
-
-// ------------------------------------------------------------------- RMSE
-constexpr int kSseBlocks = 512;
-
-__device__ inline double block_sum_f64(double v, double* scratch)
-{
-#pragma unroll
-    for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_down(v, o, kWave);
-    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
-    if (lane == 0) scratch[wave] = v;
-    __syncthreads();
-    double t = 0.0;
-    if (threadIdx.x == 0)
-        for (int x = 0; x < (int)(blockDim.x / kWave); ++x) t += scratch[x];
-    return t;
-}
-
-__global__ __launch_bounds__(256) void k_sse_partial(const float* pred, const uint8_t* rc, int64_t n,
-                                                     double inv_s, double* partial)
-{
-    __shared__ double scratch[256 / kWave];
-    double s = 0.0;
-    for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < n;
-         x += (int64_t)gridDim.x * blockDim.x) {
-        const double dlt = (double)rc[x] * inv_s - (double)pred[x];
-        s += dlt * dlt;
-    }
-    const double t = block_sum_f64(s, scratch);
-    if (threadIdx.x == 0) partial[blockIdx.x] = t;
-}
-
-__global__ __launch_bounds__(256) void k_sse_final(const double* partial, int nparts, int64_t n, double* out)
-{
-    __shared__ double scratch[256 / kWave];
-    double s = 0.0;
-    for (int x = threadIdx.x; x < nparts; x += blockDim.x) s += partial[x];
-    const double t = block_sum_f64(s, scratch);
-    if (threadIdx.x == 0) *out = n > 0 ? sqrt(t / (double)n) : 0.0;
-}
-
-int run_rmse(lshmf_ctx* c, const float* pred, const uint8_t* rc, int64_t n, double* out, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_sse_partial, dim3(kSseBlocks), dim3(256), 0, s, pred, rc, n,
-                       1.0 / (double)c->d.rscale, c->red);
-    LSHMF_LAUNCHED("k_sse_partial");
-    hipLaunchKernelGGL(k_sse_final, dim3(1), dim3(256), 0, s, c->red, kSseBlocks, n, out);
-    LSHMF_LAUNCHED("k_sse_final");
     return LSHMF_OK;
 }
 

@@ -21,6 +21,8 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "lshmf.h")
 
 LSHMF_OK = 0
 LSHMF_FP32, LSHMF_BF16 = 0, 1
+SIMLSH, RPCOS, MINHASH = 0, 1, 2
+REBUILD_NBRS = 1
 STATUS = {0: "LSHMF_OK", -1: "LSHMF_EINVAL", -2: "LSHMF_ESTATE", -3: "LSHMF_ECAPACITY",
           -4: "LSHMF_EDEVICE"}
 
@@ -35,7 +37,7 @@ class Dims(C.Structure):
     _fields_ = [("M", C.c_int32), ("N", C.c_int32), ("F", C.c_int32), ("K", C.c_int32),
                 ("G", C.c_int32), ("p", C.c_int32), ("q", C.c_int32), ("rscale", C.c_int32),
                 ("psi_exp", C.c_int32), ("n_strata", C.c_int32), ("storage", C.c_int32),
-                ("reserved", C.c_int32), ("nnz", C.c_int64), ("M_cap", C.c_int32),
+                ("hash_family", C.c_int32), ("nnz", C.c_int64), ("M_cap", C.c_int32),
                 ("N_cap", C.c_int32), ("nnz_cap", C.c_int64), ("batch_cap", C.c_int64)]
 
 
@@ -69,7 +71,7 @@ class ServeIO(C.Structure):
     _fields_ = [("req", C.c_void_p), ("n_req", C.c_int64),
                 ("h_u", C.c_void_p), ("h_i", C.c_void_p), ("h_rc", C.c_void_p),
                 ("h_qu", C.c_void_p), ("h_qi", C.c_void_p), ("h_pred", C.c_void_p),
-                ("d_U0", C.c_void_p), ("d_V0", C.c_void_p), ("d_H", C.c_void_p),
+                ("d_U0", C.c_void_p), ("d_V0", C.c_void_p), ("d_rand", C.c_void_p),
                 ("seed_fill", C.c_uint64), ("hp", HParams), ("epoch", C.c_int32), ("passes", C.c_int32),
                 ("max_query_batch", C.c_int64), ("d_stage", C.c_void_p), ("stage_bytes", C.c_size_t),
                 ("h_start", C.c_void_p), ("h_done", C.c_void_p), ("h_status", C.c_void_p)]
@@ -96,9 +98,13 @@ def lib():
             L.lshmf_bind.argtypes = [vp, C.POINTER(Tables), vp, C.c_size_t]
             L.lshmf_ingest.argtypes = [vp, vp, vp, vp, i64, vp]
             L.build_lsh_neighbours.argtypes = [vp, vp, u64, vp]
-            L.sgd_epoch.argtypes = [vp, C.POINTER(HParams), i32, vp]
+            L.sgd_epoch.argtypes = [vp, C.POINTER(HParams), i32, vp, vp]
+            L.lshmf_loss.argtypes = [vp, C.POINTER(HParams), vp, vp]
+            L.lshmf_check.argtypes = [vp, vp]
+            L.lshmf_set_timing.argtypes = [vp, i32]
+            L.lshmf_lsh_phase_ms.argtypes = [vp, C.POINTER(C.c_double)]
             L.online_update.argtypes = [vp, vp, vp, vp, i64, i32, i32, vp, u64, C.POINTER(HParams),
-                                        i32, i32, vp]
+                                        i32, i32, C.c_uint32, vp]
             L.predict.argtypes = [vp, vp, vp, i64, vp, vp]
             L.lshmf_rmse.argtypes = [vp, vp, vp, i64, vp, vp]
             L.lshmf_export_layout.argtypes = [vp, C.POINTER(Layout)]
@@ -137,15 +143,17 @@ class LshMF:
     def __init__(self, M: int, N: int, F: int, K: int, G: int, p: int, q: int, rscale: int,
                  nnz: int, psi_exp: int = 2, n_strata: int = 256, device="cuda",
                  M_cap: int = 0, N_cap: int = 0, nnz_cap: int = 0, batch_cap: int = 0,
-                 storage: str = "fp32"):
+                 storage: str = "fp32", hash_family: int = SIMLSH):
         """Tables are allocated for the capacities (0: the initial M, N, nnz);
         batch_cap > 0 enables online_update batches of up to that many ratings.
-        storage "bf16" adds BF16 copies U16, V16, W16, C16 that predict reads."""
+        storage "bf16" adds BF16 copies U16, V16, W16, C16 that predict reads.
+        hash_family: SIMLSH, RPCOS or MINHASH (the neighbour search's hash)."""
         self.device = torch.device(device)
         assert storage in ("fp32", "bf16")
         self.storage = storage
+        self.hash_family = hash_family
         self.dims = Dims(M, N, F, K, G, p, q, rscale, psi_exp, n_strata,
-                         LSHMF_BF16 if storage == "bf16" else LSHMF_FP32, 0, nnz,
+                         LSHMF_BF16 if storage == "bf16" else LSHMF_FP32, hash_family, nnz,
                          M_cap, N_cap, nnz_cap, batch_cap)
         M, N = max(M, M_cap), max(N, N_cap)
         self.B = G * p * q
@@ -215,26 +223,63 @@ class LshMF:
         _check(lib().lshmf_ingest(self._h, _ptr(u), _ptr(i), _ptr(rc), u.numel(),
                                   _stream(self.device)))
 
-    def build_lsh_neighbours(self, H: torch.Tensor, seed_fill: int):
-        assert H.dtype in (torch.int32,) and H.is_contiguous()
-        assert H.dim() == 2 and H.shape[1] == self.words and H.shape[0] >= self.dims.M
-        _check(lib().build_lsh_neighbours(self._h, _ptr(H), C.c_uint64(seed_fill & (2**64 - 1)),
+    def rand_cols(self) -> int:
+        """Columns per user of the hash family's random draws."""
+        return {SIMLSH: self.words, RPCOS: self.B, MINHASH: self.B // self.dims.G}[self.hash_family]
+
+    def _check_rand(self, R: torch.Tensor, rows: int):
+        want = torch.float32 if self.hash_family == RPCOS else torch.int32
+        assert R.dtype == want and R.is_contiguous() and R.dim() == 2
+        assert R.shape[1] == self.rand_cols() and R.shape[0] >= rows
+
+    def build_lsh_neighbours(self, R: torch.Tensor, seed_fill: int):
+        """R: the family's random draws per user -- simLSH bit strings H
+        (int32 words), RP_cos Gaussians (float32, B per user), minHash random
+        values (int32 bit patterns of uint32, B/G per user)."""
+        self._check_rand(R, self.dims.M)
+        _check(lib().build_lsh_neighbours(self._h, _ptr(R), C.c_uint64(seed_fill & (2**64 - 1)),
                                           _stream(self.device)))
 
-    def sgd_epoch(self, alpha, lam, beta: float, epoch: int):
+    def sgd_epoch(self, alpha, lam, beta: float, epoch: int, loss_out: Optional[torch.Tensor] = None):
+        """One epoch; loss_out (float64 [1] on the device) receives Eq. (loss_r)
+        after it when given."""
         hp = HParams((C.c_float * 6)(*alpha), (C.c_float * 6)(*lam), beta, 0)
-        _check(lib().sgd_epoch(self._h, C.byref(hp), epoch, _stream(self.device)))
+        _check(lib().sgd_epoch(self._h, C.byref(hp), epoch, _ptr(loss_out), _stream(self.device)))
+
+    def loss(self, lam, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """Eq. (loss_r) on the current tables (FP64, device)."""
+        if out is None:
+            out = torch.empty(1, dtype=torch.float64, device=self.device)
+        hp = HParams((C.c_float * 6)(*([0.0] * 6)), (C.c_float * 6)(*lam), 0.0, 0)
+        _check(lib().lshmf_loss(self._h, C.byref(hp), _ptr(out), _stream(self.device)))
+        return out
+
+    def set_timing(self, enable: bool = True):
+        """Phase timing of build_lsh_neighbours (HIP events at its phase boundaries)."""
+        _check(lib().lshmf_set_timing(self._h, int(bool(enable))))
+
+    def lsh_phase_ms(self):
+        """Milliseconds of the last timed neighbour search: hash state,
+        signatures, band keys and buckets, top-K, neighbour codes."""
+        out = (C.c_double * 5)()
+        _check(lib().lshmf_lsh_phase_ms(self._h, out))
+        return dict(zip(("hash_state", "signatures", "banding", "topk", "codes"), list(out)))
+
+    def check(self):
+        """Synchronises and raises LSHMF_EDEVICE if an SGD wait gave up."""
+        _check(lib().lshmf_check(self._h, _stream(self.device)))
 
     def online_update(self, u: torch.Tensor, i: torch.Tensor, rc: torch.Tensor, M_new: int, N_new: int,
                       H: torch.Tensor, seed_fill: int, alpha, lam, beta: float, epoch: int,
                       passes: int = 1, U_new: Optional[torch.Tensor] = None,
-                      V_new: Optional[torch.Tensor] = None):
+                      V_new: Optional[torch.Tensor] = None, rebuild: bool = False):
         """Folds a batch of ratings into the model (Sec. 4.3); U_new / V_new
-        are the initial factor rows of the new users / items."""
+        are the initial factor rows of the new users / items; H the family's
+        random draws (as for build_lsh_neighbours); rebuild searches every
+        neighbour list again (LSHMF_REBUILD_NBRS)."""
         assert u.dtype == torch.int32 and i.dtype == torch.int32 and rc.dtype == torch.uint8
         assert u.is_contiguous() and i.is_contiguous() and rc.is_contiguous()
-        assert H.dtype == torch.int32 and H.is_contiguous() and H.shape[1] == self.words
-        assert H.shape[0] >= M_new
+        self._check_rand(H, M_new)
         lay = self.layout()
         # rows beyond the capacity are left to the library to reject
         if lay.M < M_new <= self.U.shape[0]:
@@ -246,7 +291,8 @@ class LshMF:
         hp = HParams((C.c_float * 6)(*alpha), (C.c_float * 6)(*lam), beta, 0)
         _check(lib().online_update(self._h, _ptr(u), _ptr(i), _ptr(rc), u.numel(), M_new, N_new,
                                    _ptr(H), C.c_uint64(seed_fill & (2**64 - 1)), C.byref(hp),
-                                   epoch, passes, _stream(self.device)))
+                                   epoch, passes, REBUILD_NBRS if rebuild else 0,
+                                   _stream(self.device)))
 
     def sync_storage(self):
         """BF16 mode: rewrite the BF16 copies from the FP32 masters."""

@@ -59,6 +59,7 @@ class Workload:
     lam: Tuple[float, ...]     # regularisers    (b, bh, u, v, w, c)
     beta: float                # learning-rate decay, Eq. learn_rate
     n_strata: int = 256
+    family: int = 0            # hash family: 0 simLSH, 1 RP_cos, 2 minHash
 
     @property
     def B(self) -> int:
@@ -113,6 +114,31 @@ WORKLOADS: Dict[str, Workload] = {
 for _name in ("tiny", "ml100k", "ml10m"):
     WORKLOADS[_name + "_k0"] = dataclasses.replace(WORKLOADS[_name], name=_name + "_k0", K=0)
 
+# Other hash shapes and families on the same data (the data depend only on the
+# shape fields, not on G, p, q or the family):
+#   p = 2 and p = 3 coarse bands; (8, 3, 100) is the paper's simLSH setting of
+#   Sec. 5.3 (B = 2400 bits over two 64-word slices); (8, 7, 4) has 56-bit
+#   bands, whose keys straddle three signature words; (8, 2, 16) is B = 256.
+_SHAPES = {
+    "small_p2": ("small", dict(p=2, q=16)),
+    "small_p7": ("small", dict(p=7, q=4)),
+    "small_p3q100": ("small", dict(p=3, q=100)),
+    "ml100k_p3q100": ("ml100k", dict(p=3, q=100)),
+    "nfsmall_p3q100": ("nfsmall", dict(p=3, q=100)),
+    "ml10m_p3q100": ("ml10m", dict(p=3, q=100)),
+    "ml10m_p3q200": ("ml10m", dict(p=3, q=200)),
+    "netflix_p3q100": ("netflix", dict(p=3, q=100)),
+    # RP_cos and minHash (Sec. 5.3 top-K comparison)
+    "small_rpcos": ("small", dict(family=1)),
+    "small_minhash": ("small", dict(family=2)),
+    "ml100k_rpcos_p3": ("ml100k", dict(family=1, p=3, q=16)),
+    "ml100k_minhash_p3": ("ml100k", dict(family=2, p=3, q=16)),
+    "ml10m_rpcos": ("ml10m", dict(family=1)),
+    "ml10m_minhash": ("ml10m", dict(family=2)),
+}
+for _name, (_base, _kw) in _SHAPES.items():
+    WORKLOADS[_name] = dataclasses.replace(WORKLOADS[_base], name=_name, **_kw)
+
 
 def derive_seed(*parts: int) -> int:
     """Independent sub-stream seeds from the master seed (numpy SeedSequence)."""
@@ -162,17 +188,10 @@ def user_degrees(w: Workload, rng: np.random.Generator, M: Optional[int] = None,
     return base
 
 
-def sample_items(deg: np.ndarray, N: int, s: float, rng: np.random.Generator
-                 ) -> Tuple[np.ndarray, np.ndarray]:
-    """Successive sampling without replacement from Zipf(s) popularity ranks.
-
-    Returns (user, rank) pairs, users ascending, ranks in draw order per user.
-    """
-    w = np.arange(1, N + 1, dtype=np.float64) ** (-s)
-    cdf = np.cumsum(w)
-    cdf /= cdf[-1]
-    M = deg.shape[0]
-    need = deg.astype(np.int64).copy()
+def _sample_chunk(need: np.ndarray, cdf: np.ndarray, N: int, rng: np.random.Generator
+                  ) -> Tuple[np.ndarray, np.ndarray]:
+    """Successive sampling for one chunk of users (local ids 0..len(need)-1)."""
+    need = need.astype(np.int64).copy()
     got_u = []
     got_r = []
     chosen = np.empty(0, dtype=np.int64)          # sorted keys user*N + rank
@@ -209,6 +228,41 @@ def sample_items(deg: np.ndarray, N: int, s: float, rng: np.random.Generator
     r = np.concatenate(got_r) if got_r else np.empty(0, np.int64)
     order = np.argsort(u, kind="stable")
     return u[order], r[order]
+
+
+CHUNK_USERS = 16384
+
+
+def sample_items(deg: np.ndarray, N: int, s: float, rng: np.random.Generator
+                 ) -> Tuple[np.ndarray, np.ndarray]:
+    """Successive sampling without replacement from Zipf(s) popularity ranks.
+
+    Users are drawn in fixed chunks of CHUNK_USERS, each chunk from its own
+    generator seeded from `rng`, so the result does not depend on how many
+    threads draw the chunks.  Returns (user, rank) pairs, users ascending,
+    ranks in draw order per user.
+    """
+    import concurrent.futures
+    import os
+    w = np.arange(1, N + 1, dtype=np.float64) ** (-s)
+    cdf = np.cumsum(w)
+    cdf /= cdf[-1]
+    M = deg.shape[0]
+    n_chunks = (M + CHUNK_USERS - 1) // CHUNK_USERS
+    root = int(rng.integers(0, 2**63))
+
+    def chunk(k):
+        lo = k * CHUNK_USERS
+        g = np.random.Generator(np.random.PCG64(np.random.SeedSequence([root, k])))
+        u, r = _sample_chunk(deg[lo: lo + CHUNK_USERS], cdf, N, g)
+        return u + lo, r
+
+    workers = max(1, min(16, os.cpu_count() or 1, n_chunks))
+    with concurrent.futures.ThreadPoolExecutor(max_workers=workers) as ex:
+        parts = list(ex.map(chunk, range(n_chunks)))
+    u = np.concatenate([p[0] for p in parts]) if parts else np.empty(0, np.int64)
+    r = np.concatenate([p[1] for p in parts]) if parts else np.empty(0, np.int64)
+    return u, r
 
 
 def planted_ratings(u: np.ndarray, item: np.ndarray, M: int, N: int, rscale: int,
@@ -294,6 +348,21 @@ def generate(w: Workload, seed: int = MASTER_SEED, with_tables: bool = True) -> 
         out["U0"] = init_table(w.M, w.F, rng_init)
         out["V0"] = init_table(w.N, w.F, rng_init)
     return out
+
+
+def family_rand(w: Workload, M: Optional[int] = None, seed: int = MASTER_SEED) -> np.ndarray:
+    """The random draws per user of the workload's hash family (an input of
+    the neighbour search, like the strings H_i of simLSH):
+      simLSH   uint32 [M, ceil(B/32)]  the bit strings H_i (as generate's "H")
+      RP_cos   float32 [M, B]          standard Gaussian directions
+      minHash  uint32 [M, B/G]         uniform 32-bit values (a random order
+                                       of the users per hash)"""
+    M = w.M if M is None else M
+    if w.family == 0:
+        return hash_strings(M, w.B, _rng(seed, 6))
+    if w.family == 1:
+        return _rng(seed, 8).standard_normal((M, w.B), dtype=np.float32)
+    return _rng(seed, 9).integers(0, 1 << 32, size=(M, w.B // w.G), dtype=np.uint64).astype(np.uint32)
 
 
 def online_split(w: Workload, d: Dict[str, np.ndarray], frac_new: float = 0.01,

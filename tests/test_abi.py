@@ -15,14 +15,14 @@ def test_library_exports_every_header_function():
     L = lshmf.lib()
     names = lshmf.header_functions()
     assert {"build_lsh_neighbours", "sgd_epoch", "predict", "online_update", "lshmf_ingest",
-            "lshmf_rmse"} <= set(names)
+            "lshmf_rmse", "lshmf_loss", "lshmf_check"} <= set(names)
     for n in names:
         assert hasattr(L, n), n
 
 
 def _create(**kw):
     base = dict(M=943, N=1682, F=32, K=10, G=8, p=1, q=8, rscale=1, psi_exp=2, n_strata=16,
-                storage=0, reserved=0, nnz=90000, M_cap=0, N_cap=0, nnz_cap=0, batch_cap=0)
+                storage=0, hash_family=0, nnz=90000, M_cap=0, N_cap=0, nnz_cap=0, batch_cap=0)
     base.update(kw)
     d = lshmf.Dims(*[base[f] for f, _ in lshmf.Dims._fields_])
     h = C.c_void_p()
@@ -31,7 +31,9 @@ def _create(**kw):
 
 
 @pytest.mark.parametrize("bad", [dict(K=-1), dict(K=1682), dict(K=129), dict(F=0), dict(F=257),
-                                 dict(G=8, p=5, q=1), dict(G=8, p=1, q=33), dict(rscale=3),
+                                 dict(G=8, p=8, q=1), dict(G=8, p=1, q=1025), dict(G=8, p=7, q=512),
+                                 dict(G=40, p=1, q=4, hash_family=2), dict(hash_family=3),
+                                 dict(rscale=3),
                                  dict(psi_exp=0), dict(n_strata=0), dict(storage=2),
                                  dict(nnz=-1), dict(M=0), dict(N=1), dict(M_cap=900),
                                  dict(N_cap=1000), dict(nnz_cap=100), dict(batch_cap=-1)])
@@ -60,8 +62,9 @@ def test_arena_size_and_bind_checks():
     assert lshmf.lib().lshmf_bind(h2, C.byref(t), C.c_void_p(4096), n2.value) == -1
     lshmf.lib().lshmf_destroy(h2)
     # calls out of order report ESTATE without touching the device
-    assert lshmf.lib().sgd_epoch(h, None, 0, None) == -2
-    assert lshmf.lib().online_update(h, None, None, None, 0, 943, 1682, None, 0, None, 0, 1,
+    assert lshmf.lib().sgd_epoch(h, None, 0, None, None) == -2
+    assert lshmf.lib().lshmf_loss(h, None, None, None) == -2
+    assert lshmf.lib().online_update(h, None, None, None, 0, 943, 1682, None, 0, None, 0, 1, 0,
                                      None) == -2
     lshmf.lib().lshmf_destroy(h)
 
@@ -131,3 +134,13 @@ def test_request_record_layout():
     assert np.dtype(synth.REQUEST_FIELDS, align=True) == lshmf.REQUEST_DTYPE
     for name, _ in Req._fields_:
         assert lshmf.REQUEST_DTYPE.fields[name][1] == getattr(Req, name).offset
+
+
+@pytest.mark.parametrize("ok", [dict(G=8, p=3, q=100), dict(G=8, p=3, q=200), dict(G=8, p=2, q=16),
+                                dict(G=8, p=7, q=128), dict(G=8, p=1, q=16, hash_family=1),
+                                dict(G=8, p=3, q=16, hash_family=2)])
+def test_create_accepts_the_papers_hash_shapes(ok):
+    # Sec. 5.3 runs simLSH with G = 8, p = 3 and q = 100 or 200 (B = 2400, 4800)
+    st, h = _create(**ok)
+    assert st == 0, lshmf.lib().lshmf_last_error()
+    lshmf.lib().lshmf_destroy(h)

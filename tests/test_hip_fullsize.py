@@ -3,8 +3,9 @@ launch configuration bench.py times (P = 256 strata, needs an MI355X).
 
 69,878 users x 10,677 items, 9.9M training ratings, F = 64, K = 50, 128 hash
 bits.  Hash sums, signatures, neighbour lists and the whole stratified stream
-must match bit for bit; one SGD epoch over all ratings within 1e-4
-(normwise relative per table); predictions on sampled pairs within 1e-5.
+must match bit for bit; one SGD epoch over all ratings within 1e-4 element
+by element (tablecmp.py); predictions on sampled pairs within 1e-5; the
+held-out RMSE after all 20 epochs within 0.5% of the oracle's.
 """
 import sys
 
@@ -15,6 +16,7 @@ torch = pytest.importorskip("torch")
 
 from oracle import oracle as orc
 from paper_2111_11682_amd import synth
+from tablecmp import compare_tables
 
 pytestmark = pytest.mark.gpu
 
@@ -86,13 +88,8 @@ def test_fullsize_one_epoch_and_predictions():
     torch.cuda.synchronize()
     assert m.device_status() == 0
     o.sgd_epoch(w.n_strata, w.alpha, w.lam, w.beta, 0)
-    worst = {}
-    for k in ("U", "V", "bu", "bv", "W", "C"):
-        r = getattr(o, k)
-        g = getattr(m, k).double().cpu().numpy().reshape(r.shape)
-        worst[k] = float(np.abs(g - r).max() / max(np.abs(r).max(), 1e-3))
-    _say("[gpu] ml10m one epoch worst rel %s" % worst)
-    assert all(v <= 1e-4 for v in worst.values()), worst
+    compare_tables({k: (getattr(m, k).double().cpu().numpy().reshape(getattr(o, k).shape), getattr(o, k))
+                    for k in ("U", "V", "bu", "bv", "W", "C")}, 1e-4, _say, "ml10m one epoch")
     # Eq. (rr) on sampled pairs, both sides holding the same seeded tables
     rng = np.random.default_rng(17)
     tabs = dict(U=rng.normal(0, 0.3, (w.M, w.F)), V=rng.normal(0, 0.3, (w.N, w.F)),
@@ -108,3 +105,24 @@ def test_fullsize_one_epoch_and_predictions():
     got = m.predict(torch.from_numpy(qu).cuda(), torch.from_numpy(qi).cuda()).cpu().numpy()
     ref = o.predict(qu, qi)
     assert np.all(np.abs(got - ref) <= 1e-5 * np.maximum(1.0, np.abs(ref)))
+
+
+def test_fullsize_rmse_after_all_epochs():
+    # the whole 20-epoch job from the initial tables, both sides
+    w, d, m = _setup()
+    _, _, JK = _oracle_neighbours()
+    dev = m.device
+    m.set_factors(torch.from_numpy(d["U0"]).to(dev), torch.from_numpy(d["V0"]).to(dev))
+    o = orc.Model(w.M, w.N, w.F, w.K, w.rscale, d["train_u"], d["train_i"], d["train_rc"], JK,
+                  d["U0"], d["V0"])
+    if "sched" in _c:
+        o._sched[w.n_strata] = _c["sched"]
+    for t in range(w.epochs):
+        m.sgd_epoch(w.alpha, w.lam, w.beta, t)
+        o.sgd_epoch(w.n_strata, w.alpha, w.lam, w.beta, t)
+    m.check()
+    tu, ti, trc = (torch.from_numpy(d[k]).to(dev) for k in ("test_u", "test_i", "test_rc"))
+    r_gpu = m.rmse(m.predict(tu, ti), trc).item()
+    r_orc = o.rmse(d["test_u"], d["test_i"], d["test_rc"])
+    _say("[gpu] ml10m RMSE after %d epochs: gpu %.6f oracle %.6f" % (w.epochs, r_gpu, r_orc))
+    assert abs(r_gpu - r_orc) <= 0.005 * r_orc
