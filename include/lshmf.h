@@ -50,6 +50,11 @@ enum { LSHMF_SIMLSH = 0, LSHMF_RPCOS = 1, LSHMF_MINHASH = 2 };
 /* online_update flags */
 enum { LSHMF_REBUILD_NBRS = 1 };
 
+/* Models (Sec. 4.2): the neighbourhood model of Eq. (rr) -- with K = 0 it is
+ * biased MF -- or plain MF, rhat = u_i . v_j with only U and V learned, the
+ * model of Alg. CUSGD++ (requires K = 0; mu, b, bh, b0, bh0 stay zero). */
+enum { LSHMF_NEIGHBOURHOOD = 0, LSHMF_PLAIN_MF = 1 };
+
 typedef struct lshmf_dims {
     int32_t M, N;      /* users, items                                       */
     int32_t F;         /* rank of U (M x F) and V (N x F), 1..256            */
@@ -65,6 +70,8 @@ typedef struct lshmf_dims {
     int32_t storage;   /* LSHMF_FP32, or LSHMF_BF16: BF16 copies of U, V, W, C
                           for serving next to the FP32 masters              */
     int32_t hash_family; /* LSHMF_SIMLSH, LSHMF_RPCOS or LSHMF_MINHASH       */
+    int32_t model;     /* LSHMF_NEIGHBOURHOOD or LSHMF_PLAIN_MF              */
+    int32_t reserved;  /* 0                                                  */
     int64_t nnz;       /* ratings of the initial training set                */
     /* Capacities for online learning (0: the initial size; batch_cap 0: no
      * online batches).  Tables and the arena are sized for them.            */

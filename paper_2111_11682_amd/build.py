@@ -16,8 +16,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 OBJDIR = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "liblshmf.so")
-SOURCES = ["primitives.hip", "layout.hip", "lsh.hip", "sgd.hip", "predict.hip", "online.hip", "serve.hip",
-           "api.hip"]
+SOURCES = sorted(f for f in os.listdir(CSRC) if f.endswith(".hip"))
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-fvisibility=hidden", "-Wall",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

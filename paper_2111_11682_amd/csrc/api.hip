@@ -141,6 +141,10 @@ int validate(const lshmf_dims* d)
         set_error("hash_family=%d is none of LSHMF_SIMLSH, LSHMF_RPCOS, LSHMF_MINHASH", d->hash_family);
         return LSHMF_EINVAL;
     }
+    if ((d->model != LSHMF_NEIGHBOURHOOD && d->model != LSHMF_PLAIN_MF) || (d->model == LSHMF_PLAIN_MF && d->K != 0)) {
+        set_error("model=%d: LSHMF_NEIGHBOURHOOD, or LSHMF_PLAIN_MF with K = 0 (K=%d)", d->model, d->K);
+        return LSHMF_EINVAL;
+    }
     if (d->hash_family == LSHMF_MINHASH && d->G > 32) {
         set_error("minHash keeps at most the 32 bits of a minimum per hash (G=%d)", d->G);
         return LSHMF_EINVAL;

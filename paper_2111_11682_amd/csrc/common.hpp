@@ -65,6 +65,12 @@ int count_bins(const int32_t* idx, int64_t n, int64_t* cnt, int64_t nbins, hipSt
 // (with a message) when a dependency wait gave up, else LSHMF_OK.
 int sync_status(lshmf_ctx* c, hipStream_t s);
 
+// RMSE of n predictions against rating codes (Sec. 5.1), reduced in FP64 in a
+// fixed order through kRmsePartials per-block partial sums kept in `partial`.
+constexpr int kRmsePartials = 512;
+int rmse_with(const float* pred, const uint8_t* rc, int64_t n, int rscale, double* partial, double* out,
+              hipStream_t s);
+
 // Fills.
 int fill_i64(int64_t* p, int64_t n, int64_t v, hipStream_t s);
 int fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);

@@ -523,6 +523,11 @@ int build_stream(lshmf_ctx* c, Stream& st, const int32_t* u, const int32_t* it, 
 // mu, b0_i, bh0_j of the simple case (Sec. 3.2) over the whole store.
 int baselines_all(lshmf_ctx* c, hipStream_t s)
 {
+    if (c->d.model == LSHMF_PLAIN_MF) {  // rhat = u . v: no mean, no baselines
+        LSHMF_TRY(fill_i64(reinterpret_cast<int64_t*>(c->t.mu), 1, 0, s));
+        LSHMF_TRY(fill_f32(c->t.b0, c->M, 0.0f, s));
+        return fill_f32(c->t.bh0, c->N, 0.0f, s);
+    }
     const int64_t n = c->nnz;
     unsigned long long* total = reinterpret_cast<unsigned long long*>(c->cnt);
     LSHMF_TRY(fill_i64(c->cnt, 1, 0, s));
@@ -544,6 +549,7 @@ int baselines_new(lshmf_ctx* c, const int32_t* id, const uint8_t* rc, int64_t n,
                   float* out, hipStream_t s)
 {
     if (count <= 0) return LSHMF_OK;
+    if (c->d.model == LSHMF_PLAIN_MF) return fill_f32(out + first, count, 0.0f, s);
     unsigned long long* sum = reinterpret_cast<unsigned long long*>(c->cnt);
     unsigned long long* cn = sum + count;
     LSHMF_TRY(fill_i64(c->cnt, 2 * (int64_t)count, 0, s));

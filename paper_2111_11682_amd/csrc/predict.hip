@@ -165,7 +165,6 @@ int run_predict(lshmf_ctx* c, const int32_t* qu, const int32_t* qi, int64_t n, f
 }
 
 // ------------------------------------------------------------------- RMSE
-constexpr int kSseBlocks = 512;
 
 __device__ inline double block_sum_f64(double v, double* scratch)
 {
@@ -378,14 +377,21 @@ int run_loss(lshmf_ctx* c, const lshmf_hparams* hp, double* out, hipStream_t s)
     return LSHMF_OK;
 }
 
-int run_rmse(lshmf_ctx* c, const float* pred, const uint8_t* rc, int64_t n, double* out, hipStream_t s)
+// The RMSE reduction with its kRmsePartials per-block partial sums in `partial`.
+int rmse_with(const float* pred, const uint8_t* rc, int64_t n, int rscale, double* partial, double* out,
+              hipStream_t s)
 {
-    hipLaunchKernelGGL(k_sse_partial, dim3(kSseBlocks), dim3(256), 0, s, pred, rc, n,
-                       1.0 / (double)c->d.rscale, c->red);
+    hipLaunchKernelGGL(k_sse_partial, dim3(kRmsePartials), dim3(256), 0, s, pred, rc, n, 1.0 / (double)rscale,
+                       partial);
     LSHMF_LAUNCHED("k_sse_partial");
-    hipLaunchKernelGGL(k_sse_final, dim3(1), dim3(256), 0, s, c->red, kSseBlocks, n, out);
+    hipLaunchKernelGGL(k_sse_final, dim3(1), dim3(256), 0, s, partial, kRmsePartials, n, out);
     LSHMF_LAUNCHED("k_sse_final");
     return LSHMF_OK;
+}
+
+int run_rmse(lshmf_ctx* c, const float* pred, const uint8_t* rc, int64_t n, double* out, hipStream_t s)
+{
+    return rmse_with(pred, rc, n, c->d.rscale, c->red, out, s);
 }
 
 }  // namespace lshmf

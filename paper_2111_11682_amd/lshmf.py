@@ -22,6 +22,7 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "lshmf.h")
 LSHMF_OK = 0
 LSHMF_FP32, LSHMF_BF16 = 0, 1
 SIMLSH, RPCOS, MINHASH = 0, 1, 2
+NEIGHBOURHOOD, PLAIN_MF = 0, 1
 REBUILD_NBRS = 1
 STATUS = {0: "LSHMF_OK", -1: "LSHMF_EINVAL", -2: "LSHMF_ESTATE", -3: "LSHMF_ECAPACITY",
           -4: "LSHMF_EDEVICE"}
@@ -37,7 +38,8 @@ class Dims(C.Structure):
     _fields_ = [("M", C.c_int32), ("N", C.c_int32), ("F", C.c_int32), ("K", C.c_int32),
                 ("G", C.c_int32), ("p", C.c_int32), ("q", C.c_int32), ("rscale", C.c_int32),
                 ("psi_exp", C.c_int32), ("n_strata", C.c_int32), ("storage", C.c_int32),
-                ("hash_family", C.c_int32), ("nnz", C.c_int64), ("M_cap", C.c_int32),
+                ("hash_family", C.c_int32), ("model", C.c_int32), ("reserved", C.c_int32),
+                ("nnz", C.c_int64), ("M_cap", C.c_int32),
                 ("N_cap", C.c_int32), ("nnz_cap", C.c_int64), ("batch_cap", C.c_int64)]
 
 
@@ -143,17 +145,18 @@ class LshMF:
     def __init__(self, M: int, N: int, F: int, K: int, G: int, p: int, q: int, rscale: int,
                  nnz: int, psi_exp: int = 2, n_strata: int = 256, device="cuda",
                  M_cap: int = 0, N_cap: int = 0, nnz_cap: int = 0, batch_cap: int = 0,
-                 storage: str = "fp32", hash_family: int = SIMLSH):
+                 storage: str = "fp32", hash_family: int = SIMLSH, model: int = NEIGHBOURHOOD):
         """Tables are allocated for the capacities (0: the initial M, N, nnz);
         batch_cap > 0 enables online_update batches of up to that many ratings.
         storage "bf16" adds BF16 copies U16, V16, W16, C16 that predict reads.
-        hash_family: SIMLSH, RPCOS or MINHASH (the neighbour search's hash)."""
+        hash_family: SIMLSH, RPCOS or MINHASH (the neighbour search's hash);
+        model: NEIGHBOURHOOD (Eq. rr) or PLAIN_MF (u . v only, K = 0)."""
         self.device = torch.device(device)
         assert storage in ("fp32", "bf16")
         self.storage = storage
         self.hash_family = hash_family
         self.dims = Dims(M, N, F, K, G, p, q, rscale, psi_exp, n_strata,
-                         LSHMF_BF16 if storage == "bf16" else LSHMF_FP32, hash_family, nnz,
+                         LSHMF_BF16 if storage == "bf16" else LSHMF_FP32, hash_family, model, 0, nnz,
                          M_cap, N_cap, nnz_cap, batch_cap)
         M, N = max(M, M_cap), max(N, N_cap)
         self.B = G * p * q

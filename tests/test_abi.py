@@ -22,7 +22,7 @@ def test_library_exports_every_header_function():
 
 def _create(**kw):
     base = dict(M=943, N=1682, F=32, K=10, G=8, p=1, q=8, rscale=1, psi_exp=2, n_strata=16,
-                storage=0, hash_family=0, nnz=90000, M_cap=0, N_cap=0, nnz_cap=0, batch_cap=0)
+                storage=0, hash_family=0, model=0, reserved=0, nnz=90000, M_cap=0, N_cap=0, nnz_cap=0, batch_cap=0)
     base.update(kw)
     d = lshmf.Dims(*[base[f] for f, _ in lshmf.Dims._fields_])
     h = C.c_void_p()
@@ -33,6 +33,7 @@ def _create(**kw):
 @pytest.mark.parametrize("bad", [dict(K=-1), dict(K=1682), dict(K=129), dict(F=0), dict(F=257),
                                  dict(G=8, p=8, q=1), dict(G=8, p=1, q=1025), dict(G=8, p=7, q=512),
                                  dict(G=40, p=1, q=4, hash_family=2), dict(hash_family=3),
+                                 dict(model=1), dict(model=2, K=0),
                                  dict(rscale=3),
                                  dict(psi_exp=0), dict(n_strata=0), dict(storage=2),
                                  dict(nnz=-1), dict(M=0), dict(N=1), dict(M_cap=900),

@@ -4,7 +4,7 @@ With K = 0 the model is biased MF without the neighbour term: Eq. (rr) keeps
 mu + b_i + bh_j + u_i . v_j and Eq. (sgd_update) moves only b, bh, u, v.  The
 same kernels run it; the bars are those of the K > 0 parity tests: hash sums
 and signatures bit for bit, predictions within 1e-5 relative, one epoch within
-1e-4 normwise relative per table, held-out RMSE within 0.5%.
+1e-4 element by element (tablecmp.py), held-out RMSE within 0.5%.
 """
 import sys
 
@@ -15,6 +15,7 @@ torch = pytest.importorskip("torch")
 
 from oracle import oracle as orc
 from paper_2111_11682_amd import synth
+from tablecmp import compare_tables
 
 pytestmark = pytest.mark.gpu
 
@@ -45,13 +46,9 @@ def _models(name, P=None):
     return w, d, m, o
 
 
-def _worst(m, o):
-    out = {}
-    for k in ("U", "V", "bu", "bv"):
-        g = getattr(m, k).double().cpu().numpy().reshape(getattr(o, k).shape)
-        r = getattr(o, k)
-        out[k] = float(np.abs(g - r).max() / max(np.abs(r).max(), 1e-3))
-    return out
+def _worst(m, o, label):
+    return compare_tables({k: (getattr(m, k).double().cpu().numpy().reshape(getattr(o, k).shape), getattr(o, k))
+                           for k in ("U", "V", "bu", "bv")}, 1e-4, _say, label)
 
 
 @pytest.mark.parametrize("name", ["tiny_k0", "ml100k_k0"])
@@ -78,9 +75,7 @@ def test_k0_one_epoch_parity(name):
     torch.cuda.synchronize()
     assert m.device_status() == 0
     o.sgd_epoch(w.n_strata, w.alpha, w.lam, w.beta, 0)
-    worst = _worst(m, o)
-    _say("[gpu] K=0 one epoch %s worst rel %s" % (name, worst))
-    assert all(v <= 1e-4 for v in worst.values()), worst
+    _worst(m, o, "K=0 one epoch " + name)
 
 
 def test_k0_full_run_rmse_ml100k():
@@ -154,10 +149,36 @@ def test_k0_online_update():
     assert m.device_status() == 0
     assert np.array_equal(m.acc[:Nn].cpu().numpy().astype(np.int64), acc)
     assert np.array_equal(m.sig[:Nn].cpu().numpy().view(np.uint32), sig)
-    worst = {}
-    for k in ("U", "V", "bu", "bv"):
-        r = getattr(o, k)
-        g = getattr(m, k)[: r.shape[0]].double().cpu().numpy().reshape(r.shape)
-        worst[k] = float(np.abs(g - r).max() / max(np.abs(r).max(), 1e-3))
-    _say("[gpu] K=0 online worst rel %s" % worst)
-    assert all(v <= 1e-4 for v in worst.values()), worst
+    compare_tables({k: (getattr(m, k)[: getattr(o, k).shape[0]].double().cpu().numpy().reshape(getattr(o, k).shape),
+                        getattr(o, k)) for k in ("U", "V", "bu", "bv")}, 1e-4, _say, "K=0 online")
+
+
+def test_plain_mf_cusgd_parity():
+    # Alg. CUSGD++'s model: rhat = u . v, only U and V learned (LSHMF_PLAIN_MF).
+    # The oracle runs the same as K = 0 with mu, b0, bh0 and the bias rates zero.
+    from paper_2111_11682_amd import lshmf
+    w = synth.WORKLOADS["ml100k_k0"]
+    d = synth.generate(w)
+    m = lshmf.LshMF(w.M, w.N, w.F, 0, w.G, w.p, w.q, w.rscale, d["train_u"].size, n_strata=w.n_strata,
+                    model=lshmf.PLAIN_MF)
+    dev = m.device
+    m.ingest(*[torch.from_numpy(d[k]).to(dev) for k in ("train_u", "train_i", "train_rc")])
+    m.set_factors(torch.from_numpy(d["U0"]).to(dev), torch.from_numpy(d["V0"]).to(dev))
+    m.build_lsh_neighbours(torch.from_numpy(d["H"].view(np.int32)).to(dev), SEED_FILL)
+    assert m.mu.item() == 0.0
+    o = orc.Model(w.M, w.N, w.F, 0, w.rscale, d["train_u"], d["train_i"], d["train_rc"],
+                  np.zeros((w.N, 0), np.int32), d["U0"], d["V0"],
+                  fixed_baselines=(0.0, np.zeros(w.M), np.zeros(w.N)))
+    alpha0 = (0.0, 0.0) + tuple(w.alpha[2:])
+    lam0 = (0.0, 0.0) + tuple(w.lam[2:])
+    for t in range(2):
+        m.sgd_epoch(w.alpha, w.lam, w.beta, t)     # the library ignores the bias rates
+        o.sgd_epoch(w.n_strata, alpha0, lam0, w.beta, t)
+    m.check()
+    assert not m.bu.any().item() and not m.bv.any().item()
+    compare_tables({k: (getattr(m, k).double().cpu().numpy().reshape(getattr(o, k).shape), getattr(o, k))
+                    for k in ("U", "V")}, 1e-4, _say, "plain MF two epochs")
+    qu, qi = synth.random_queries(w.M, w.N, 2000, 7)
+    got = m.predict(torch.from_numpy(qu).cuda(), torch.from_numpy(qi).cuda()).cpu().numpy()
+    ref = np.einsum("nf,nf->n", o.U[qu], o.V[qi])
+    assert np.all(np.abs(got - ref) <= 1e-4 * np.maximum(1.0, np.abs(ref)))

@@ -770,3 +770,21 @@ def test_sgd_strata_compose_to_the_epoch():
     m2.sgd_strata(w.n_strata, 3, w.n_strata, w.alpha, w.lam, w.beta, 0)
     for a in ("U", "V", "bu", "bv", "W", "C"):
         assert np.array_equal(getattr(m1, a), getattr(m2, a)), a
+
+
+def test_plain_mf_is_u_dot_v_and_its_step():
+    # Alg. CUSGD++: rhat = u_i . v_j, only u and v learned.  In the oracle that
+    # is K = 0 with mu, b0, bh0 fixed to zero and the bias rates zero.
+    u = np.array([0, 0, 1, 1], np.int32)
+    it = np.array([0, 1, 1, 2], np.int32)
+    rc = np.array([4, 2, 5, 3], np.uint8)
+    U0 = np.array([[1.0, 2.0], [0.5, -1.0]])
+    V0 = np.array([[0.2, 0.1], [-0.3, 0.4], [0.0, 0.5]])
+    m = orc.Model(2, 3, 2, 0, 1, u, it, rc, np.zeros((3, 0), np.int32), U0, V0,
+                  fixed_baselines=(0.0, np.zeros(2), np.zeros(3)))
+    assert np.allclose(m.predict([0, 0, 1], [0, 1, 2]), [0.4, 0.5, -0.5], rtol=0, atol=1e-15)
+    # (u0, i1, r = 2): e = 2 - 0.5 = 1.5; rates 0.1, regularisers 0.2 for u and v
+    m.sgd_one(0, 1, 2, [0.0, 0.0, 0.1, 0.1, 0.0, 0.0], [0.0, 0.0, 0.2, 0.2, 0.0, 0.0])
+    assert np.allclose(m.U[0], [0.935, 2.02], rtol=0, atol=1e-15)
+    assert np.allclose(m.V[1], [-0.144, 0.692], rtol=0, atol=1e-15)
+    assert not m.bu.any() and not m.bv.any()
