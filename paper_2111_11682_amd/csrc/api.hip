@@ -49,6 +49,7 @@ void carve_stream(Carver& k, Stream& st, int64_t cap, int64_t P, int nstride)
     st.seg_col = k.take<int32_t>(cap);
     st.seg_start = k.take<int64_t>(cap + 1);
     st.blk_slots = k.take<int32_t>(P * P);
+    st.stats = k.take<int64_t>(4);
 }
 
 int64_t max3(int64_t a, int64_t b, int64_t c)
@@ -74,6 +75,14 @@ size_t carve(lshmf_ctx* c, char* base)
     c->col_ptr = k.take<int64_t>(Nc + 1);
     c->csc_row = k.take<int32_t>(nz);
     c->csc_rc = k.take<uint8_t>(nz);
+    // the second buffers are needed only when online batches grow the store
+    const int64_t nz2 = bc > 0 ? nz : 0;
+    c->row_ptr_alt = k.take<int64_t>(bc > 0 ? Mc + 1 : 0);
+    c->csr_col_alt = k.take<int32_t>(nz2);
+    c->csr_rc_alt = k.take<uint8_t>(nz2);
+    c->col_ptr_alt = k.take<int64_t>(bc > 0 ? Nc + 1 : 0);
+    c->csc_row_alt = k.take<int32_t>(nz2);
+    c->csc_rc_alt = k.take<uint8_t>(nz2);
     carve_stream(k, c->train, nz, P, c->nstride);
     for (Stream& st : c->phase) carve_stream(k, st, bc, P, c->nstride);
     c->bat_u = k.take<int32_t>(bc);
@@ -82,6 +91,9 @@ size_t carve(lshmf_ctx* c, char* base)
     c->bcol_ptr = k.take<int64_t>(Nc + 1);
     c->bcsc_row = k.take<int32_t>(bc);
     c->bcsc_rc = k.take<uint8_t>(bc);
+    c->brow_ptr = k.take<int64_t>(Mc + 1);
+    c->bcsr_col = k.take<int32_t>(bc);
+    c->bcsr_rc = k.take<uint8_t>(bc);
     c->irank = k.take<int32_t>(Nc);
     c->urank = k.take<int32_t>(Mc);
     c->e2s = k.take<int32_t>(nz > bc ? nz : bc);

@@ -102,6 +102,8 @@ struct Stream {
     int64_t max_block_nnz = 0;
     int64_t max_block_slots = 0;
     int64_t nseg = 0;
+    int64_t* stats;            // 4 (device) largest block, most slots, runs
+    int64_t pending = 0;       // ratings laid out, statistics not read yet
     bool codes = false;        // nib valid for the current neighbour lists
 };
 
@@ -131,6 +133,13 @@ struct lshmf_ctx {
     int64_t* col_ptr;          // N_cap+1   CSC by item
     int32_t* csc_row;          // nnz_cap   users, ascending per item
     uint8_t* csc_rc;           // nnz_cap
+    // second buffers of both: an online batch merges into them, then they swap
+    int64_t* row_ptr_alt;
+    int32_t* csr_col_alt;
+    uint8_t* csr_rc_alt;
+    int64_t* col_ptr_alt;
+    int32_t* csc_row_alt;
+    uint8_t* csc_rc_alt;
 
     lshmf::Stream train;       // all ratings of the store
     lshmf::Stream phase[3];    // online batch: new users / new items / the rest
@@ -140,9 +149,12 @@ struct lshmf_ctx {
     int32_t* bat_u;            // batch_cap  batch ratings grouped by phase
     int32_t* bat_i;
     uint8_t* bat_rc;
-    int64_t* bcol_ptr;         // N_cap+1    CSC of the batch (hash sums)
+    int64_t* bcol_ptr;         // N_cap+1    CSC of the batch (hash sums, merge)
     int32_t* bcsc_row;         // batch_cap
     uint8_t* bcsc_rc;
+    int64_t* brow_ptr;         // M_cap+1    CSR of the batch (merge)
+    int32_t* bcsr_col;         // batch_cap
+    uint8_t* bcsr_rc;
 
     // shared scratch
     int32_t* irank;            // N_cap   item order of the stream being built

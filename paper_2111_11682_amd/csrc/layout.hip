@@ -10,6 +10,8 @@
 //     ordering constraint between the waves that share a block);
 //   * mu, b0_i, bh0_j: the "simple case" means of Sec. 3.2, exact integer sums
 //     reduced and divided in FP64.
+#include <utility>
+
 #include "common.hpp"
 
 namespace lshmf {
@@ -40,7 +42,7 @@ __global__ void k_in_store(const int32_t* u, const int32_t* it, int64_t n, int32
     for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < n;
          x += (int64_t)gridDim.x * blockDim.x) {
         const int32_t i = u[x], j = it[x];
-        if (i >= M_old) continue;
+        if (i < 0 || i >= M_old || j < 0) continue;  // out-of-range ids are reported apart
         int64_t l = row_ptr[i], r = row_ptr[i + 1];
         while (l < r) {
             const int64_t m = (l + r) >> 1;
@@ -290,6 +292,76 @@ __global__ void k_row_means(const int64_t* ptr, const uint8_t* rc, int64_t rows,
     }
 }
 
+// Largest block, most mailbox slots in a block and the number of item runs
+// of a stream, for the SGD kernel's limits: stats[0..2] (zeroed before).
+__global__ void k_stream_stats(const int64_t* blk_ptr, const int64_t* blk_seg, const int32_t* blk_slots,
+                               int64_t nblk, int64_t* stats)
+{
+    unsigned long long mx = 0, msl = 0;
+    for (int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; b < nblk;
+         b += (int64_t)gridDim.x * blockDim.x) {
+        const unsigned long long len = (unsigned long long)(blk_ptr[b + 1] - blk_ptr[b]);
+        mx = len > mx ? len : mx;
+        msl = (unsigned long long)blk_slots[b] > msl ? (unsigned long long)blk_slots[b] : msl;
+    }
+    atomicMax(reinterpret_cast<unsigned long long*>(stats), mx);
+    atomicMax(reinterpret_cast<unsigned long long*>(stats + 1), msl);
+    if (blockIdx.x == 0 && threadIdx.x == 0) stats[2] = blk_seg[nblk];
+}
+
+// Compressed rows after an online batch: row r of the merged copy holds the
+// old row (rows r >= n_old are empty) and the batch's row, minor ids
+// ascending.  new_ptr[r] = old_ptr[min(r, n_old)] + b_ptr[r].
+__global__ void k_merged_ptr(const int64_t* old_ptr, int64_t n_old, const int64_t* b_ptr, int64_t n_new,
+                             int64_t* new_ptr)
+{
+    for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r <= n_new;
+         r += (int64_t)gridDim.x * blockDim.x)
+        new_ptr[r] = old_ptr[r < n_old ? r : n_old] + b_ptr[r];
+}
+
+// One wave per row: every element goes to its place in the merged row, found
+// by a binary search in the other list (no pair is in both).
+__global__ __launch_bounds__(256) void k_merge_rows(const int64_t* old_ptr, const int32_t* old_idx,
+                                                    const uint8_t* old_rc, int64_t n_old, const int64_t* b_ptr,
+                                                    const int32_t* b_idx, const uint8_t* b_rc, int64_t n_new,
+                                                    const int64_t* new_ptr, int32_t* new_idx, uint8_t* new_rc)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t w0 = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kWave;
+    const int64_t nw = (int64_t)gridDim.x * blockDim.x / kWave;
+    for (int64_t r = w0; r < n_new; r += nw) {
+        const int64_t oa = old_ptr[r < n_old ? r : n_old];
+        const int64_t oz = r < n_old ? old_ptr[r + 1] : oa;
+        const int64_t ba = b_ptr[r], bz = b_ptr[r + 1];
+        const int64_t base = new_ptr[r];
+        for (int64_t x = oa + lane; x < oz; x += kWave) {
+            const int32_t key = old_idx[x];
+            int64_t l = ba, h = bz;
+            while (l < h) {
+                const int64_t m = (l + h) >> 1;
+                if (b_idx[m] < key) l = m + 1;
+                else h = m;
+            }
+            const int64_t dst = base + (x - oa) + (l - ba);
+            new_idx[dst] = key;
+            new_rc[dst] = old_rc[x];
+        }
+        for (int64_t y = ba + lane; y < bz; y += kWave) {
+            const int32_t key = b_idx[y];
+            int64_t l = oa, h = oz;
+            while (l < h) {
+                const int64_t m = (l + h) >> 1;
+                if (old_idx[m] < key) l = m + 1;
+                else h = m;
+            }
+            const int64_t dst = base + (y - ba) + (l - oa);
+            new_idx[dst] = key;
+            new_rc[dst] = b_rc[y];
+        }
+    }
+}
+
 static unsigned grid_for(int64_t n, int threads = 256, int64_t cap = 16384)
 {
     int64_t b = ceil_div(n > 0 ? n : 1, threads);
@@ -312,7 +384,7 @@ int sync_status(lshmf_ctx* c, hipStream_t s)
 // Reads the input-check word c->err[1] (bit 0 ids or codes out of range, bit 1
 // a pair given twice, bit 2 a pair already in the store) after a
 // synchronisation; reports the SGD status word as sync_status does.
-static int input_status(lshmf_ctx* c, int32_t M, int32_t N, hipStream_t s)
+int input_status(lshmf_ctx* c, int32_t M, int32_t N, hipStream_t s)
 {
     int32_t herr[2] = {0, 0};
     LSHMF_HIP(hipMemcpyAsync(herr, c->err, sizeof(herr), hipMemcpyDeviceToHost, s));
@@ -337,36 +409,39 @@ static int input_status(lshmf_ctx* c, int32_t M, int32_t N, hipStream_t s)
     return LSHMF_OK;
 }
 
+int launch_id_checks(lshmf_ctx* c, const int32_t* u, const int32_t* it, const uint8_t* rc, int64_t n, int32_t M,
+                     int32_t N, hipStream_t s, bool check_pairs = false);
+
 int check_ids(lshmf_ctx* c, const int32_t* u, const int32_t* it, const uint8_t* rc, int64_t n, int32_t M,
               int32_t N, hipStream_t s)
 {
-    int32_t* flag = c->err + 1;  // a word of its own: c->err[0] is the SGD status word
-    LSHMF_TRY(fill_i32(flag, 1, 0, s));
-    if (n > 0) {
-        hipLaunchKernelGGL(k_check_ids, dim3(grid_for(n)), dim3(256), 0, s, u, it, rc, n, M, N, flag);
-        LSHMF_LAUNCHED("k_check_ids");
-    }
+    LSHMF_TRY(launch_id_checks(c, u, it, rc, n, M, N, s));
     return input_status(c, M, N, s);
 }
 
-// Online batch: no pair twice in the batch and none already in the store.
-// Uses the sort buffers; the ids were checked before.
-int check_batch_pairs(lshmf_ctx* c, const int32_t* u, const int32_t* it, int64_t n, int32_t M_new, int32_t N_new,
-                      hipStream_t s)
+// Launches the input checks of n ratings into c->err[1] (cleared first):
+// ids and codes in range; with check_pairs also no pair twice and none in
+// the store (the online batch).  The caller reads the word with input_status
+// after a synchronisation.
+int launch_id_checks(lshmf_ctx* c, const int32_t* u, const int32_t* it, const uint8_t* rc, int64_t n, int32_t M,
+                     int32_t N, hipStream_t s, bool check_pairs)
 {
-    if (n <= 0) return LSHMF_OK;
-    int32_t* flag = c->err + 1;
+    int32_t* flag = c->err + 1;  // a word of its own: c->err[0] is the SGD status word
     LSHMF_TRY(fill_i32(flag, 1, 0, s));
-    hipLaunchKernelGGL(k_keys_pair, dim3(grid_for(n)), dim3(256), 0, s, u, it, n, (int64_t)N_new, c->sk[0], c->sv[0]);
+    if (n <= 0) return LSHMF_OK;
+    hipLaunchKernelGGL(k_check_ids, dim3(grid_for(n)), dim3(256), 0, s, u, it, rc, n, M, N, flag);
+    LSHMF_LAUNCHED("k_check_ids");
+    if (!check_pairs) return LSHMF_OK;
+    // keys of out-of-range ids are garbage but stay inside the sort buffers
+    hipLaunchKernelGGL(k_keys_pair, dim3(grid_for(n)), dim3(256), 0, s, u, it, n, (int64_t)N, c->sk[0], c->sv[0]);
     LSHMF_LAUNCHED("k_keys_pair(batch)");
     int ri = 0;
-    LSHMF_TRY(radix_sort(c->sk, c->sv, n, bits_for((uint64_t)M_new * (uint64_t)N_new), c->hist, c->scan_tmp, s,
-                         &ri));
+    LSHMF_TRY(radix_sort(c->sk, c->sv, n, bits_for((uint64_t)M * (uint64_t)N), c->hist, c->scan_tmp, s, &ri));
     hipLaunchKernelGGL(k_dup_flags, dim3(grid_for(n)), dim3(256), 0, s, c->sk[ri], n, flag);
     LSHMF_LAUNCHED("k_dup_flags(batch)");
     hipLaunchKernelGGL(k_in_store, dim3(grid_for(n)), dim3(256), 0, s, u, it, n, c->M, c->row_ptr, c->csr_col, flag);
     LSHMF_LAUNCHED("k_in_store");
-    return input_status(c, M_new, N_new, s);
+    return LSHMF_OK;
 }
 
 // Compressed copy of n ratings by `major` (ptr over n_major rows, minor ids
@@ -403,15 +478,46 @@ int build_compressed(lshmf_ctx* c, hipStream_t s, int32_t* dup_flag)
                     dup_flag);
 }
 
-// The stratified stream of n ratings (u, it, rc) over the current M x N.
-int build_stream(lshmf_ctx* c, Stream& st, const int32_t* u, const int32_t* it, const uint8_t* rc, int64_t n,
-                 hipStream_t s)
+// CSR and CSC of the store grown by a batch, merged from the previous copies
+// and the batch's own CSR and CSC (no pair in both) into the second buffers,
+// which then become current: O(store) copying, no sort of the store.
+int merge_compressed(lshmf_ctx* c, int32_t M_old, int32_t N_old, const int64_t* b_rptr, const int32_t* b_col,
+                     const uint8_t* b_rrc, const int64_t* b_cptr, const int32_t* b_row, const uint8_t* b_crc,
+                     hipStream_t s)
+{
+    const int64_t M = c->M, N = c->N;
+    hipLaunchKernelGGL(k_merged_ptr, dim3(grid_for(M + 1)), dim3(256), 0, s, c->row_ptr, (int64_t)M_old, b_rptr, M,
+                       c->row_ptr_alt);
+    LSHMF_LAUNCHED("k_merged_ptr(rows)");
+    hipLaunchKernelGGL(k_merge_rows, dim3(grid_for(M * kWave)), dim3(256), 0, s, c->row_ptr, c->csr_col, c->csr_rc,
+                       (int64_t)M_old, b_rptr, b_col, b_rrc, M, c->row_ptr_alt, c->csr_col_alt, c->csr_rc_alt);
+    LSHMF_LAUNCHED("k_merge_rows(rows)");
+    hipLaunchKernelGGL(k_merged_ptr, dim3(grid_for(N + 1)), dim3(256), 0, s, c->col_ptr, (int64_t)N_old, b_cptr, N,
+                       c->col_ptr_alt);
+    LSHMF_LAUNCHED("k_merged_ptr(cols)");
+    hipLaunchKernelGGL(k_merge_rows, dim3(grid_for(N * kWave)), dim3(256), 0, s, c->col_ptr, c->csc_row, c->csc_rc,
+                       (int64_t)N_old, b_cptr, b_row, b_crc, N, c->col_ptr_alt, c->csc_row_alt, c->csc_rc_alt);
+    LSHMF_LAUNCHED("k_merge_rows(cols)");
+    std::swap(c->row_ptr, c->row_ptr_alt);
+    std::swap(c->csr_col, c->csr_col_alt);
+    std::swap(c->csr_rc, c->csr_rc_alt);
+    std::swap(c->col_ptr, c->col_ptr_alt);
+    std::swap(c->csc_row, c->csc_row_alt);
+    std::swap(c->csc_rc, c->csc_rc_alt);
+    return LSHMF_OK;
+}
+
+// The stratified stream of n ratings (u, it, rc) over the current M x N,
+// laid out on the device; its block statistics follow into st.stats.  The
+// stream is usable after stream_finish (a synchronisation later).
+int build_stream_async(lshmf_ctx* c, Stream& st, const int32_t* u, const int32_t* it, const uint8_t* rc,
+                       int64_t n, hipStream_t s)
 {
     if (n > st.cap) {
         set_error("a stream of %lld ratings exceeds its capacity %lld", (long long)n, (long long)st.cap);
         return LSHMF_ECAPACITY;
     }
-    st.n = st.max_block_nnz = st.max_block_slots = st.nseg = 0;
+    st.n = st.max_block_nnz = st.max_block_slots = st.nseg = st.pending = 0;
     st.codes = false;
     if (n == 0) return LSHMF_OK;
     const int64_t P = c->P;
@@ -483,40 +589,37 @@ int build_stream(lshmf_ctx* c, Stream& st, const int32_t* u, const int32_t* it, 
     LSHMF_TRY(fill_i32(reinterpret_cast<int32_t*>(st.pk) + n, kStreamPad, 0, s));
     LSHMF_TRY(fill_i32(reinterpret_cast<int32_t*>(st.link) + n, kStreamPad, 0, s));
 
-    // largest block and most mailbox slots in a block, for the SGD kernel's limits
-    const int64_t nb = P * P + 1;
-    int64_t* hptr = new int64_t[2 * nb];
-    int32_t* hslots = new int32_t[nb];
-    hipError_t e = hipMemcpyAsync(hptr, st.blk_ptr, sizeof(int64_t) * nb, hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(hptr + nb, st.blk_seg, sizeof(int64_t) * nb, hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(hslots, st.blk_slots, sizeof(int32_t) * (nb - 1), hipMemcpyDeviceToHost, s);
-    int32_t herr = 0;
-    if (e == hipSuccess) e = hipMemcpyAsync(&herr, c->err, sizeof(int32_t), hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
-    if (e != hipSuccess) {
-        delete[] hptr;
-        delete[] hslots;
-        return hip_fail(e, "stream block pointers");
-    }
-    if (herr) {
-        delete[] hptr;
-        delete[] hslots;
-        set_error("an SGD dependency wait gave up after its spin limit (status word %#x): a broken hand-over, "
-                  "the tables do not follow the stated order", herr);
-        return LSHMF_EDEVICE;
-    }
-    int64_t mx = 0, msl = 0;
-    for (int64_t b = 0; b < P * P; ++b) {
-        mx = hptr[b + 1] - hptr[b] > mx ? hptr[b + 1] - hptr[b] : mx;
-        msl = hslots[b] > msl ? hslots[b] : msl;
-    }
-    st.nseg = hptr[nb + P * P];
-    delete[] hptr;
-    delete[] hslots;
-    st.n = n;
-    st.max_block_nnz = mx;
-    st.max_block_slots = msl;
+    // largest block, most mailbox slots in a block and the run count
+    LSHMF_TRY(fill_i64(st.stats, 4, 0, s));
+    hipLaunchKernelGGL(k_stream_stats, dim3(grid_for(P * P, 256, 1024)), dim3(256), 0, s, st.blk_ptr, st.blk_seg,
+                       st.blk_slots, P * P, st.stats);
+    LSHMF_LAUNCHED("k_stream_stats");
+    st.pending = n;
+    return LSHMF_OK;
+}
+
+// After a synchronisation: the host copy of the stream's statistics (hstats,
+// copied from st.stats) makes the stream usable.
+void stream_finish(Stream& st, const int64_t* hstats)
+{
+    if (st.pending == 0) return;
+    st.n = st.pending;
+    st.pending = 0;
+    st.max_block_nnz = hstats[0];
+    st.max_block_slots = hstats[1];
+    st.nseg = hstats[2];
     st.codes = false;
+}
+
+int build_stream(lshmf_ctx* c, Stream& st, const int32_t* u, const int32_t* it, const uint8_t* rc, int64_t n,
+                 hipStream_t s)
+{
+    LSHMF_TRY(build_stream_async(c, st, u, it, rc, n, s));
+    if (n == 0) return LSHMF_OK;
+    int64_t h[4] = {0, 0, 0, 0};
+    LSHMF_HIP(hipMemcpyAsync(h, st.stats, sizeof(h), hipMemcpyDeviceToHost, s));
+    LSHMF_TRY(sync_status(c, s));
+    stream_finish(st, h);
     return LSHMF_OK;
 }
 

@@ -23,16 +23,18 @@
 
 namespace lshmf {
 
-int check_ids(lshmf_ctx* c, const int32_t* u, const int32_t* it, const uint8_t* rc, int64_t n, int32_t M,
-              int32_t N, hipStream_t s);
-int check_batch_pairs(lshmf_ctx* c, const int32_t* u, const int32_t* it, int64_t n, int32_t M_new, int32_t N_new,
-                      hipStream_t s);
+int launch_id_checks(lshmf_ctx* c, const int32_t* u, const int32_t* it, const uint8_t* rc, int64_t n, int32_t M,
+                     int32_t N, hipStream_t s, bool check_pairs);
+int input_status(lshmf_ctx* c, int32_t M, int32_t N, hipStream_t s);
 int compress(lshmf_ctx* c, const int32_t* major, const int32_t* minor, const uint8_t* rc, int64_t n,
              int64_t n_major, int64_t n_minor, int64_t* ptr, int32_t* idx, uint8_t* rc_out, hipStream_t s,
              int32_t* dup_flag);
-int build_compressed(lshmf_ctx* c, hipStream_t s, int32_t* dup_flag);
-int build_stream(lshmf_ctx* c, Stream& st, const int32_t* u, const int32_t* it, const uint8_t* rc, int64_t n,
-                 hipStream_t s);
+int merge_compressed(lshmf_ctx* c, int32_t M_old, int32_t N_old, const int64_t* b_rptr, const int32_t* b_col,
+                     const uint8_t* b_rrc, const int64_t* b_cptr, const int32_t* b_row, const uint8_t* b_crc,
+                     hipStream_t s);
+int build_stream_async(lshmf_ctx* c, Stream& st, const int32_t* u, const int32_t* it, const uint8_t* rc,
+                       int64_t n, hipStream_t s);
+void stream_finish(Stream& st, const int64_t* hstats);
 int baselines_new(lshmf_ctx* c, const int32_t* id, const uint8_t* rc, int64_t n, int32_t first, int32_t count,
                   float* out, hipStream_t s);
 int hash_add(lshmf_ctx* c, const int64_t* col_ptr, const int32_t* row, const uint8_t* rc, int64_t nnz,
@@ -45,6 +47,7 @@ int stream_codes(lshmf_ctx* c, Stream& st, hipStream_t s);
 int sgd_fits(const lshmf_ctx* c, const Stream& st);
 int run_sgd(lshmf_ctx* c, Stream& st, const lshmf_hparams* hp, int epoch, int upd, hipStream_t s);
 int refresh_bf16(lshmf_ctx* c, int64_t m0, int64_t m1, int64_t n0, int64_t n1, hipStream_t s);
+int refresh_bf16_touched(lshmf_ctx* c, const int64_t* b_rptr, const int64_t* b_cptr, hipStream_t s);
 
 namespace {
 
@@ -83,13 +86,17 @@ unsigned grid_for(int64_t n, int threads = 256, int64_t cap = 16384)
 
 }  // namespace
 
-// The batch split into its three phases, each laid out as its own stratified
-// stream over the grown id ranges c->M x c->N (arena scratch only: the
-// store, the tables and the training stream are not touched), and each
-// checked against the SGD kernel's per-block limits.
-static int layout_phases(lshmf_ctx* c, const int32_t* u, const int32_t* it, const uint8_t* rc, int64_t n,
-                         int32_t M_old, int32_t N_old, hipStream_t s)
+// Checks the batch (ids and codes in range, no pair twice, none in the
+// store) and splits it into its three phases, each laid out as its own
+// stratified stream over the grown id ranges M_new x N_new, then checks each
+// against the SGD kernel's per-block limits.  Arena scratch only: the store,
+// the tables and the training stream are not touched.  Two synchronisations:
+// the check word with the phase sizes, then the three streams' statistics.
+static int check_and_layout(lshmf_ctx* c, const int32_t* u, const int32_t* it, const uint8_t* rc, int64_t n,
+                            int32_t M_new, int32_t N_new, hipStream_t s)
 {
+    const int32_t M_old = c->M, N_old = c->N;
+    LSHMF_TRY(launch_id_checks(c, u, it, rc, n, M_new, N_new, s, true));
     int64_t cnt[3] = {0, 0, 0};
     if (n > 0) {
         int32_t* phase = c->e2s;
@@ -103,34 +110,46 @@ static int layout_phases(lshmf_ctx* c, const int32_t* u, const int32_t* it, cons
         LSHMF_LAUNCHED("k_gather3");
         LSHMF_TRY(count_bins(phase, n, c->cnt, 3, s));
         LSHMF_HIP(hipMemcpyAsync(cnt, c->cnt, sizeof(cnt), hipMemcpyDeviceToHost, s));
-        LSHMF_HIP(hipStreamSynchronize(s));
     }
+    LSHMF_TRY(input_status(c, M_new, N_new, s));
+    // the phase streams are laid out over the grown ranges
+    c->M = M_new;
+    c->N = N_new;
+    int status = LSHMF_OK;
+    int64_t stats[3][4] = {};
     int64_t off = 0;
-    for (int k = 0; k < 3; ++k) {
-        LSHMF_TRY(build_stream(c, c->phase[k], c->bat_u + off, c->bat_i + off, c->bat_rc + off, cnt[k], s));
-        LSHMF_TRY(sgd_fits(c, c->phase[k]));
+    for (int k = 0; k < 3 && status == LSHMF_OK; ++k) {
+        status = build_stream_async(c, c->phase[k], c->bat_u + off, c->bat_i + off, c->bat_rc + off, cnt[k], s);
+        if (status == LSHMF_OK && cnt[k] > 0) {
+            const hipError_t e = hipMemcpyAsync(stats[k], c->phase[k].stats, sizeof(stats[k]),
+                                                hipMemcpyDeviceToHost, s);
+            if (e != hipSuccess) status = hip_fail(e, "hipMemcpyAsync(stream stats)");
+        }
         off += cnt[k];
     }
-    return LSHMF_OK;
+    if (status == LSHMF_OK) {
+        const hipError_t e = hipStreamSynchronize(s);
+        if (e != hipSuccess) status = hip_fail(e, "hipStreamSynchronize(phase streams)");
+    }
+    for (int k = 0; k < 3 && status == LSHMF_OK; ++k) {
+        stream_finish(c->phase[k], stats[k]);
+        status = sgd_fits(c, c->phase[k]);
+    }
+    if (status != LSHMF_OK) {
+        c->M = M_old;
+        c->N = N_old;
+    }
+    return status;
 }
 
 int run_online(lshmf_ctx* c, const int32_t* u, const int32_t* it, const uint8_t* rc, int64_t n, int32_t M_new,
                int32_t N_new, const void* R, uint64_t seed_fill, const lshmf_hparams* hp, int epoch,
                int passes, uint32_t flags, hipStream_t s)
 {
-    // every refusal comes before the model, the store or the training stream change
-    LSHMF_TRY(check_ids(c, u, it, rc, n, M_new, N_new, s));
-    LSHMF_TRY(check_batch_pairs(c, u, it, n, M_new, N_new, s));
     const int32_t M_old = c->M, N_old = c->N;
     const int K = c->d.K;
-    c->M = M_new;
-    c->N = N_new;
-    const int st = layout_phases(c, u, it, rc, n, M_old, N_old, s);
-    if (st != LSHMF_OK) {
-        c->M = M_old;
-        c->N = N_old;
-        return st;
-    }
+    // every refusal comes before the model, the store or the training stream change
+    LSHMF_TRY(check_and_layout(c, u, it, rc, n, M_new, N_new, s));
     // the model can no longer be trained or queried as before until this call succeeds
     c->neighbours = false;
     c->train_stale = true;
@@ -142,9 +161,11 @@ int run_online(lshmf_ctx* c, const int32_t* u, const int32_t* it, const uint8_t*
         LSHMF_HIP(hipMemcpyAsync(c->coo_i + c->nnz, it, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, s));
         LSHMF_HIP(hipMemcpyAsync(c->coo_rc + c->nnz, rc, n, hipMemcpyDeviceToDevice, s));
     }
+    // the batch's own CSC (hash sums, merge) and CSR (merge)
+    LSHMF_TRY(compress(c, it, u, rc, n, N_new, M_new, c->bcol_ptr, c->bcsc_row, c->bcsc_rc, s, nullptr));
+    LSHMF_TRY(compress(c, u, it, rc, n, M_new, N_new, c->brow_ptr, c->bcsr_col, c->bcsr_rc, s, nullptr));
 
     // 1. the saved hash state grows by the batch, by item, then signatures
-    LSHMF_TRY(compress(c, it, u, rc, n, N_new, M_new, c->bcol_ptr, c->bcsc_row, c->bcsc_rc, s, nullptr));
     LSHMF_TRY(hash_clear(c, N_old, N_new, s));
     LSHMF_TRY(hash_add(c, c->bcol_ptr, c->bcsc_row, c->bcsc_rc, n, R, s));
     LSHMF_TRY(signs(c, s));
@@ -159,9 +180,10 @@ int run_online(lshmf_ctx* c, const int32_t* u, const int32_t* it, const uint8_t*
     LSHMF_TRY(baselines_new(c, u, rc, n, M_old, M_new - M_old, c->t.b0, s));
     LSHMF_TRY(baselines_new(c, it, rc, n, N_old, N_new - N_old, c->t.bh0, s));
 
-    // R(i) now includes the batch
+    // R(i) now includes the batch: merged, not sorted again
     c->nnz += n;
-    LSHMF_TRY(build_compressed(c, s, nullptr));
+    LSHMF_TRY(merge_compressed(c, M_old, N_old, c->brow_ptr, c->bcsr_col, c->bcsr_rc, c->bcol_ptr, c->bcsc_row,
+                               c->bcsc_rc, s));
 
     // 2. neighbour lists of the new items only, or of every item on a rebuild
     if (flags & LSHMF_REBUILD_NBRS) LSHMF_TRY(rebuild_lists(c, N_old, seed_fill, s));
@@ -172,8 +194,14 @@ int run_online(lshmf_ctx* c, const int32_t* u, const int32_t* it, const uint8_t*
     static const int kUpd[3] = {1, 2, 3};  // user side, item side, both
     for (int p = 0; p < passes; ++p)
         for (int k = 0; k < 3; ++k) LSHMF_TRY(run_sgd(c, c->phase[k], hp, epoch, kUpd[k], s));
-    // BF16 copies of the FP32 masters, in one pass after the SGD
-    LSHMF_TRY(refresh_bf16(c, 0, M_new, 0, N_new, s));
+    // BF16 copies: every row after a rebuild (w, c moved with their ids), else
+    // the rows the SGD changed (the batch's users and items) and the new ids
+    if (flags & LSHMF_REBUILD_NBRS) {
+        LSHMF_TRY(refresh_bf16(c, 0, M_new, 0, N_new, s));
+    } else {
+        LSHMF_TRY(refresh_bf16_touched(c, c->brow_ptr, c->bcol_ptr, s));
+        LSHMF_TRY(refresh_bf16(c, M_old, M_new, N_old, N_new, s));
+    }
     c->neighbours = true;
     return LSHMF_OK;
 }

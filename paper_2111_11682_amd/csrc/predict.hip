@@ -25,6 +25,49 @@ int to_bf16_rows(const float* src, uint16_t* dst, int64_t n, hipStream_t s)
     return LSHMF_OK;
 }
 
+// BF16 copies of the rows r < n_rows with ptr[r+1] > ptr[r] (the rows a batch
+// touched) of up to two FP32 tables of `width` floats a row; a wave per row.
+__global__ __launch_bounds__(256) void k_bf16_touched(const int64_t* ptr, int64_t n_rows, const float* a,
+                                                      uint16_t* a16, int64_t wa, const float* b, uint16_t* b16,
+                                                      int64_t wb)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t w0 = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kWave;
+    const int64_t nw = (int64_t)gridDim.x * blockDim.x / kWave;
+    for (int64_t r = w0; r < n_rows; r += nw) {
+        if (ptr[r + 1] == ptr[r]) continue;
+        for (int64_t k = lane; k < wa; k += kWave) a16[r * wa + k] = to_bf16(a[r * wa + k]);
+        if (b)
+            for (int64_t k = lane; k < wb; k += kWave) b16[r * wb + k] = to_bf16(b[r * wb + k]);
+    }
+}
+
+// BF16 copies of the user rows with ratings in a batch (its CSR row_ptr over
+// c->M users) and of the item rows with ratings in it (its CSC col_ptr).
+int refresh_bf16_touched(lshmf_ctx* c, const int64_t* b_rptr, const int64_t* b_cptr, hipStream_t s)
+{
+    if (c->d.storage != LSHMF_BF16) return LSHMF_OK;
+    const int64_t F = c->d.F, K = c->d.K, M = c->M, N = c->N;
+    auto grid = [](int64_t rows) {
+        int64_t b = ceil_div(rows > 0 ? rows * kWave : 1, 256);
+        return (unsigned)(b > 16384 ? 16384 : b);
+    };
+    if (M > 0) {
+        hipLaunchKernelGGL(k_bf16_touched, dim3(grid(M)), dim3(256), 0, s, b_rptr, M, c->t.U, c->t.U16, F,
+                           (const float*)nullptr, (uint16_t*)nullptr, (int64_t)0);
+        LSHMF_LAUNCHED("k_bf16_touched(users)");
+    }
+    if (N > 0) {
+        hipLaunchKernelGGL(k_bf16_touched, dim3(grid(N)), dim3(256), 0, s, b_cptr, N, c->t.V, c->t.V16, F, c->t.W,
+                           c->t.W16, K);
+        LSHMF_LAUNCHED("k_bf16_touched(items V,W)");
+        hipLaunchKernelGGL(k_bf16_touched, dim3(grid(N)), dim3(256), 0, s, b_cptr, N, c->t.C, c->t.C16, K,
+                           (const float*)nullptr, (uint16_t*)nullptr, (int64_t)0);
+        LSHMF_LAUNCHED("k_bf16_touched(items C)");
+    }
+    return LSHMF_OK;
+}
+
 // BF16 copies of the rows [m0, m1) of U and [n0, n1) of V, W, C.
 int refresh_bf16(lshmf_ctx* c, int64_t m0, int64_t m1, int64_t n0, int64_t n1, hipStream_t s)
 {

@@ -100,6 +100,15 @@ def _check_state(m, o, acc, sig, Mc, Nc, tol):
     assert np.array_equal(m.acc[:Nc].cpu().numpy().astype(np.int64), acc)
     assert np.array_equal(m.sig[:Nc].cpu().numpy().view(np.uint32), sig)
     assert np.array_equal(m.JK[:Nc].cpu().numpy(), o.JK)
+    # CSR and CSC of the grown store (merged with the batch, not sorted again)
+    nnz = o.u.size
+    for major, minor, n_major, ptr, idx, code in ((o.u, o.i, Mc, lay.row_ptr, lay.csr_col, lay.csr_rc),
+                                                 (o.i, o.u, Nc, lay.col_ptr, lay.csc_row, lay.csc_rc)):
+        order = np.lexsort((minor, major))
+        want_ptr = np.concatenate([[0], np.cumsum(np.bincount(major, minlength=n_major))])
+        assert np.array_equal(m.arena_view(ptr, n_major + 1, torch.int64).cpu().numpy(), want_ptr)
+        assert np.array_equal(m.arena_view(idx, nnz, torch.int32).cpu().numpy(), minor[order])
+        assert np.array_equal(m.arena_view(code, nnz, torch.uint8).cpu().numpy(), o.rc[order])
     assert m.mu.item() == pytest.approx(o.mu, rel=1e-12)
     for k in ("b0", "bh0"):
         g = getattr(m, k)[: (Mc if k == "b0" else Nc)].double().cpu().numpy()
