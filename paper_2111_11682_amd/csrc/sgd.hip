@@ -1,39 +1,20 @@
-// Neighbourhood-MF SGD over the stratified block stream (Alg. CULSH-MF,
-// Eq. sgd_update with the prediction of Eq. rr).
+// Neighbourhood-MF SGD over the stratified block stream, prediction and the
+// FP64 RMSE reduction.
 //
-// k_sgd_stratum: one workgroup per block of the stratum, kSgdWaves waves.
-// Blocks of a stratum share no user and no item; inside a block a rating
-// waits (LDS mailbox with sequence numbers) for the previous rating of the
-// same user, which makes the result that of running the block's ratings in
-// stream order.  The item state {v_j, bh_j, w_j, c_j} of a run stays in
-// registers; lanes own features f = lane + 64x and neighbour slots
-// k = lane + 64y.
-//
-// Group recurrence.  The ratings of one item run are taken G at a time.  With
-// the decays a = 1 - gamma * lambda of Eq. (sgd_update) and the item state at
-// the group's start, rating t of the group predicts
-//     rhat_t = P_t + sum_{s<t} Q_ts e_s
-//     P_t  = mu + b_i + a_b^t bh + a_v^t u_t.v
-//            + sum_k x_tk (a_w^{n_k(t)} w_k  or  a_c^{m_k(t)} c_k)
-//     Q_ts = g_b a_b^{t-1-s} + g_v a_v^{t-1-s} u_t.u_s
-//            + sum_k x_tk x_sk g a^{n_k(t)-n_k(s)-1}   (slots on the same side)
-// where x_tk is the neighbour coefficient of slot k for rating t
-// (|R^K|^-1/2 (r - bbar) on an explicit slot, |N^K|^-1/2 on an implicit one),
-// n_k(t) / m_k(t) count the group's earlier ratings with slot k explicit /
-// implicit, and g, a are the rate and decay of w (explicit) or c (implicit).
-// The Q_ts involve no error and no item state, so they are computed apart
-// from the dependent chain; the errors then follow from the forward
-// substitution e_t = r_t - P_t - sum_{s<t} Q_ts e_s, and the state moves to
-// the group's end in closed form.  This is Eq. (sgd_update) in stream order,
-// reassociated: the same values up to FP32 rounding.
-//
-// Roles.  The block's first runs, when long, each get a gang: helper waves
-// load and prepare groups (user rows from HBM or the mailbox, neighbour
-// coefficients, the Q_ts) into an LDS ring, and an item wave runs only the
-// chain (P_t, the substitution, the state and user-row updates).  The other
-// runs are taken one wave per run, doing both parts.
+// k_sgd_stratum (Alg. CULSH-MF, Eq. sgd_update with Eq. rr): one workgroup per
+// block of the stratum, kSgdWaves waves.  A wave takes the next item run of
+// its block (the ratings of one item j), holds the item state {v_j, bh_j, w_j,
+// c_j} in registers for the whole run -- the register-resident column state
+// of the paper's kernel -- and streams the users' {u_i, b_i} from HBM.  Lanes
+// own features f = lane + 64x and neighbour slots k = lane + 64y, so u.v, the
+// explicit w-sum and the implicit c-sum of Eq. (rr) fold into ONE 64-lane
+// reduction.  The block's first run, when long, is split between an item
+// wave that runs only the dependent update chain and helper waves that load
+// and prepare the user side (a gang, below).  Blocks of a stratum
+// share no user and no item; inside a block, a rating waits (LDS mailbox with
+// sequence numbers) for the previous rating of the same user, which makes the
+// result identical to running the block's ratings in order.
 #include <cmath>
-#include <type_traits>
 
 #include "common.hpp"
 #include "wave.hpp"
@@ -41,11 +22,17 @@
 namespace lshmf {
 
 constexpr int kSgdWaves = 16;
+constexpr int kGroup = 4;                        // ratings per pipeline stage
 constexpr int kHelpers = 4;                      // helper waves of a gang
 constexpr int kGangWaves = kHelpers + 1;
 constexpr int kMaxGangs = 2;                     // gangs per block
-constexpr int kGangMin = 48;                     // shortest run given a gang
-constexpr int kMaxRingGroups = 8;                // groups in a gang's ring
+constexpr int kGangMin = 48;                     // shortest segment given a gang
+constexpr int kHG = 6;                           // ratings per helper pipeline stage
+// ring slots of a gang: a multiple of kHelpers, so that every slot belongs to
+// one helper, and 2 * kHG + 3 per helper, so that a helper can prepare two
+// stages ahead of the item wave
+constexpr int kRing = (2 * kHG + 3) * kHelpers;
+constexpr int kIG = 8;                           // ratings per item-wave group
 constexpr int kSpinLimit = 1 << 24;              // bounded wait: a broken hand-over ends the kernel
 constexpr int kMaxMailboxBytes = 150 * 1024;     // mailbox part of a block's dynamic LDS
 constexpr int kMaxLdsBytes = 160 * 1024 - 256;   // all of it (static LDS aside)
@@ -71,90 +58,39 @@ struct SgdArgs {
     float* trash;
     int32_t* err;
     int F, K, P, nstride, s, slots;
-    int max_gangs;    // gangs the LDS holds (0: every run is taken by a single wave)
-    int ring_groups;  // groups in each gang's ring
+    int upd;          // bit 0: update the user side {b_i, u_i}; bit 1: the item side {bh_j, v_j, w_j, c_j}
+    int max_gangs;    // gangs the LDS holds (0: every segment is run by a single wave)
     int ring_off;     // float offset of the gang rings in dynamic LDS
+    int ring_rs;      // floats per ring slot: u (F), rw (K), cn (K)
     float inv_s;
-    // Eq. (sgd_update) as decay and rate: theta <- a theta + g (e x); a frozen
-    // side has a = 1, g = 0
-    float a_u, g_u, a_bu, g_bu;                  // user side: u_i, b_i
-    float a_w, a_c, g_w, g_c, inv_aw, inv_ac;    // item side: w_j, c_j
-    float pav[9], pab[9];                        // a_v^t, a_b^t
-    float pvi[8];                                // g_v a_v^-(t+1)
-    float gvp[8], gbp[8];                        // g_v a_v^t, g_b a_b^t
+    float g[6], l[6];
 };
 
-__host__ __device__ constexpr int ilog2c(int n) { return n <= 1 ? 0 : 1 + ilog2c(n >> 1); }
-__host__ __device__ constexpr int pow2_at_least(int n) { return n <= 1 ? 1 : 2 * pow2_at_least((n + 1) >> 1); }
-
-// Floats of one ring group of a gang: G rating slots (u: F, x-tilde: K,
-// x-acute: K, explicit-slot masks: 4 words), G headers (r - mu - b_i, b_i,
-// user, hand-over word), the G x G matrix Q and the group-end decay powers
-// of the w and c slots (2K).
-__host__ __device__ inline int ring_mask_off(int F, int K) { return (F + 2 * K + 1) & ~1; }
-__host__ __device__ inline int ring_slot_floats(int F, int K) { return ring_mask_off(F, K) + 4; }
-__host__ __device__ inline int ring_group_floats(int F, int K, int G)
-{
-    return ((G * ring_slot_floats(F, K) + 4 * G + G * G + 2 * K) + 3) & ~3;
-}
-
-// Sums NP values (a power of two <= 64) over the wave at once: each of
-// log2(NP) halving steps sends half of a lane's values to the partner lane
-// and adds the other half it receives; lane l ends with the total of value
-// l >> (6 - log2 NP).  Fixed association order.
-template <int NP>
-__device__ inline float batched_sum(float (&v)[NP], int lane)
-{
-    constexpr int LOG = ilog2c(NP);
-#pragma unroll
-    for (int st = 0; st < LOG; ++st) {
-        const int m = 32 >> st;
-        const int h = NP >> (st + 1);
-        const bool up = (lane & m) != 0;
-#pragma unroll
-        for (int i = 0; i < NP / 2; ++i) {
-            if (i < h) {
-                const float keep = up ? v[h + i] : v[i];
-                const float give = up ? v[i] : v[h + i];
-                v[i] = keep + __shfl_xor(give, m, kWave);
-            }
-        }
-    }
-    float x = v[0];
-#pragma unroll
-    for (int m = 32 >> LOG; m >= 1; m >>= 1) x += __shfl_xor(x, m, kWave);
-    return x;
-}
-
-// HBM inputs of one group, loaded a group ahead of use.  Lane t holds the
-// scalars of rating t; rows and neighbour-code bytes are per rating.
-template <int FP, int KP, int G>
-struct GStage {
-    float u[G][FP];
-    uint32_t nb[(G + 3) / 4][KP];  // neighbour-code byte of rating t at byte t % 4
-    uint32_t pw, lw;  // lane t: (user << 4) | code, hand-over word
-    float bi, b0;     // lane t
-};
-
-// One rating prepared for the group solve: its (possibly handed-over) user
-// row and the neighbour coefficients scaled for P (xt) and for Q and the
-// state update (xa).
+// User-side HBM inputs of one group of ratings, loaded a group ahead of use.
+// A user rated earlier in the same block is read from the block's LDS mailbox
+// instead, when its rating is computed.
 template <int FP, int KP>
-struct Prepared {
-    float u[FP];
-    float xt[KP], xa[KP];
-    uint32_t exm;  // bit y: this lane's slot k = lane + 64y is explicit for the rating
-    __device__ bool ex(int y) const { return ((exm >> y) & 1u) != 0; }
+struct Stage {
+    float gu[kGroup][FP];
+    float gbi[kGroup], b0[kGroup];
+    uint32_t nb[kGroup][KP];  // raw neighbour-code bytes of this lane's slots
+    uint32_t pk[kGroup];      // (user << 4) | code
+    uint32_t lk[kGroup];      // hand-over word
 };
 
-template <int FP, int KP, int G>
+// HBM inputs of kHG ratings of a helper wave, loaded a stage ahead of use.
+template <int FP, int KP>
+struct HStage {
+    float u[kHG][FP];
+    float bi[kHG], b0[kHG];
+    uint32_t nb[kHG][KP];
+    uint32_t pw[kHG], lw[kHG];
+};
+
+template <int FP, int KP>
 __global__ __launch_bounds__(kSgdWaves* kWave) void k_sgd_stratum(SgdArgs a, const uint32_t* __restrict__ pk,
                                                                    const uint32_t* __restrict__ link)
 {
-    constexpr int NPAIR = G * (G - 1) / 2;
-    constexpr int GP = FP + KP >= 3 ? 2 : 4;           // group of a wave that runs a whole run
-    constexpr int NPAIRP = GP * (GP - 1) / 2;
-    constexpr int NPP = pow2_at_least(NPAIRP + GP);    // its batched sum: pairs and P values
     // mailbox: slots + 1 rows (the last is a write sink) of F floats, b_i, sequence
     extern __shared__ float smem[];
     __shared__ int next_seg;
@@ -167,235 +103,592 @@ __global__ __launch_bounds__(kSgdWaves* kWave) void k_sgd_stratum(SgdArgs a, con
     const int64_t blk = (int64_t)a.s * a.P + blockIdx.x;
     const int64_t g0 = a.blk_seg[blk], g1 = a.blk_seg[blk + 1];
     const int nsegs = (int)(g1 - g0);
+    // The first segments of the block, while long, each get a gang: an item
+    // wave that keeps the item state and runs only the dependent update chain,
+    // fed through an LDS ring by helper waves that load and prepare the
+    // user-side inputs of every rating.
     int ngang = 0;
     for (int k = 0; k < a.max_gangs && k < nsegs; ++k) {
         if (a.seg_start[g0 + k + 1] - a.seg_start[g0 + k] < kGangMin) break;
         ngang = k + 1;
     }
-    const int RG = a.ring_groups;
-    const int GS = ring_group_floats(F, K, G);
-    const int RS = ring_slot_floats(F, K);
-    const int gang_floats = RG * GS + 2 * kMaxRingGroups;
+    const int RS = a.ring_rs;
+    const int GS = kRing * (RS + 6);  // floats per gang: data, headers, ready, done
     float* rings = smem + a.ring_off;
     for (int x = threadIdx.x; x <= dummy; x += blockDim.x) mb_seq[x] = 0;
     for (int gi = 0; gi < ngang; ++gi) {
-        int* fl = reinterpret_cast<int*>(rings + (size_t)gi * gang_floats + RG * GS);
-        for (int x = threadIdx.x; x < 2 * kMaxRingGroups; x += blockDim.x) fl[x] = 0;  // ready[], done[]
+        int* ready = reinterpret_cast<int*>(rings + (size_t)gi * GS + kRing * RS + kRing * 4);
+        for (int x = threadIdx.x; x < 2 * kRing; x += blockDim.x) ready[x] = 0;  // ready[] and done[]
     }
     if (threadIdx.x == 0) next_seg = ngang;
     __syncthreads();
     const float mu = (float)(*a.mu);
     const float inv_s = a.inv_s;
+    const bool usr = (a.upd & 1) != 0;
+    const bool itm = (a.upd & 2) != 0;
     const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));  // wave-uniform
-    bool dead = false;  // after one failed wait, later waits are skipped so the kernel ends
 
-    // ---- shared pieces -------------------------------------------------------
-    // HBM loads of the group of `cnt` ratings at stream positions p0..; no waits
-    auto stage = [&](auto& S, int64_t p0, int cnt) {
-        constexpr int GG = std::extent<decltype(S.u)>::value;
-        S.pw = lane < cnt ? pk[p0 + lane] : 0u;
-        S.lw = lane < cnt ? link[p0 + lane] : 0u;
-        const int64_t il = S.pw >> 4;
-        S.bi = a.bu[il];
-        S.b0 = a.b0[il];
-#pragma unroll
-        for (int x = 0; x < (GG + 3) / 4; ++x)
-#pragma unroll
-            for (int y = 0; y < KP; ++y) S.nb[x][y] = 0u;
-#pragma unroll
-        for (int t = 0; t < GG; ++t) {
-            const int64_t i = (uint32_t)__builtin_amdgcn_readlane((int)S.pw, t) >> 4;
+    if (wv < ngang * kGangWaves) {
+        // Ring protocol.  Helper h prepares ratings n = h, h + H, ... into
+        // slot n % kRing and sets ready; the item wave runs each group of kIG
+        // ratings, writes each u_i's new row to the mailbox (the user rates
+        // again later in the block) or to HBM, then publishes b_i, the
+        // hand-over sequence numbers and done for the group.  A slot is
+        // reused by the same helper kRing / H of its ratings later, once the
+        // slot's previous rating is done.  The item wave waits only after
+        // publishing all it has done, and a helper waits only for ratings
+        // below those it prepares, so every wait ends.
+        const int gang = wv / kGangWaves, role = wv % kGangWaves;
+        const int64_t seg = g0 + gang;
+        const int64_t j = a.seg_col[seg];
+        const int64_t ea = a.seg_start[seg];
+        const int len = (int)(a.seg_start[seg + 1] - ea);
+        float* rdata = rings + (size_t)gang * GS;
+        int* rhdr = reinterpret_cast<int*>(rdata + kRing * RS);
+        int* rready = rhdr + kRing * 4;
+        int* rdone = rready + kRing;
+        if (role == 0) {
+            // ---- item wave: Eq. (rr) and Eq. (sgd_update) in stream order
+            __builtin_amdgcn_s_setprio(3);
+            float v[FP], w[KP], c[KP];
 #pragma unroll
             for (int x = 0; x < FP; ++x) {
                 const int f = lane + x * kWave;
-                S.u[t][x] = *(f < F ? a.U + i * F + f : a.trash + lane);
+                v[x] = f < F ? a.V[j * F + f] : 0.0f;
             }
-            // positions past the run read the zero padding after the stream
-            const uint8_t* nbp = a.nib + (p0 + t) * a.nstride;
+            float bh = a.bv[j];
 #pragma unroll
             for (int y = 0; y < KP; ++y) {
-                const int byte = (lane >> 1) + y * (kWave / 2);
-                S.nb[t >> 2][y] |= (uint32_t)nbp[byte < a.nstride ? byte : 0] << (8 * (t & 3));
+                const int k = lane + y * kWave;
+                w[y] = k < K ? a.W[j * K + k] : 0.0f;
+                c[y] = k < K ? a.C[j * K + k] : 0.0f;
             }
-        }
-    };
-    // Waits for the hand-over of rating t's user (when an earlier rating of the
-    // user in this block precedes it), then its row and b_i, and the
-    // neighbour coefficients x of its slots.  Running decay powers of the
-    // group (pw, pc: a^n before this rating; iw, ic: g a^-(n+1)) advance.
-    float bhn[KP];
-    auto prep = [&](const auto& S, int t, Prepared<FP, KP>& R, float& bi_out, float (&pw)[KP], float (&pc)[KP],
-                    float (&iw)[KP], float (&ic)[KP]) {
-        const uint32_t lw = (uint32_t)__builtin_amdgcn_readlane((int)S.lw, t);
-        const bool has_pred = ((lw >> 30) & 1u) != 0;
-        const int pslot = has_pred ? (int)(lw & 0xFFFFu) : dummy;
-        if (has_pred) {
-            const int want = (int)((lw >> 16) & 0x3FFFu);
-            int spins = 0;
-            while (!dead && __builtin_amdgcn_readfirstlane(__hip_atomic_load(
-                                &mb_seq[pslot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) != want) {
-                if (++spins > kSpinLimit) {
-                    if (lane == 0) atomicOr(a.err, 2);
-                    dead = true;
+            bool dead = false;  // after one failed wait, later waits are skipped so the kernel ends
+            // lane t < cnt checks slot (g0 + t): are all kIG inputs of the group there?
+            auto group_ready = [&](int gs, int cnt) {
+                const int sl = (gs + lane) % kRing;
+                const int want = gs + lane + 1;
+                const bool ok = lane >= cnt ||
+                                __hip_atomic_load(&rready[sl], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) == want;
+                return __ballot(!ok) == 0ull;
+            };
+            auto wait_group = [&](int gs, int cnt) {
+                int spins = 0;
+                while (!dead && !group_ready(gs, cnt)) {
+                    if (++spins > kSpinLimit) {
+                        if (lane == 0) atomicOr(a.err, 4);
+                        dead = true;
+                    }
                 }
-                __builtin_amdgcn_s_sleep(1);
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+            };
+            float pu[kIG][FP], prw[kIG][KP], pcn[kIG][KP];
+            float preff = 0.0f, pbi = 0.0f;  // lane t: r - mu - b_i and b_i of rating gs + t
+            int pi = 0, plw = 0;               // lane t: user and hand-over word of rating gs + t
+            // The slot reads are unconditional and the lanes past F (or K)
+            // drop what they read: the next section of the slot, or past the
+            // last slot the ring headers, all inside the gang's LDS area.
+            auto load_group = [&](int gs, int cnt) {
+#pragma unroll
+                for (int t = 0; t < kIG; ++t) {
+                    const float* d = rdata + ((gs + t) % kRing) * RS;
+#pragma unroll
+                    for (int x = 0; x < FP; ++x) {
+                        const int f = lane + x * kWave;
+                        const float uv = d[f];
+                        pu[t][x] = f < F ? uv : 0.0f;
+                    }
+#pragma unroll
+                    for (int y = 0; y < KP; ++y) {
+                        const int k = lane + y * kWave;
+                        const float rv = d[F + k], cv = d[F + K + k];
+                        prw[t][y] = k < K ? rv : 0.0f;
+                        pcn[t][y] = k < K ? cv : 0.0f;
+                    }
+                }
+                const int* hd = rhdr + ((gs + (lane < cnt ? lane : 0)) % kRing) * 4;
+                preff = __int_as_float(hd[0]);
+                pbi = __int_as_float(hd[1]);
+                pi = hd[2];
+                plw = hd[3];
+            };
+            wait_group(0, len < kIG ? len : kIG);
+            load_group(0, len < kIG ? len : kIG);
+            for (int gs = 0; gs < len; gs += kIG) {
+                const int cnt = len - gs < kIG ? len - gs : kIG;
+                float u[kIG][FP], rw[kIG][KP], cn[kIG][KP];
+#pragma unroll
+                for (int t = 0; t < kIG; ++t) {
+#pragma unroll
+                    for (int x = 0; x < FP; ++x) u[t][x] = pu[t][x];
+#pragma unroll
+                    for (int y = 0; y < KP; ++y) {
+                        rw[t][y] = prw[t][y];
+                        cn[t][y] = pcn[t][y];
+                    }
+                }
+                const float reff_v = preff, bi_v = pbi;
+                const int i_v = pi, lw_v = plw;
+                // the next group's inputs, if they are already there
+                const int gn = gs + kIG;
+                const int cntn = len - gn < kIG ? len - gn : kIG;
+                bool have_next = false;
+                if (gn < len && group_ready(gn, cntn)) {
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+                    load_group(gn, cntn);
+                    have_next = true;
+                }
+                float errv = 0.0f;  // lane t: error of rating gs + t
+#pragma unroll
+                for (int t = 0; t < kIG; ++t) {
+                    if (t >= cnt) break;
+                    const float reff = __builtin_bit_cast(
+                        float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, reff_v), t));
+                    float part = 0.0f;
+#pragma unroll
+                    for (int x = 0; x < FP; ++x) part += u[t][x] * v[x];
+#pragma unroll
+                    for (int y = 0; y < KP; ++y) part += rw[t][y] * w[y] + cn[t][y] * c[y];
+                    const float err = reff - (bh + wave_sum(part));
+                    errv = lane == t ? err : errv;
+                    // u_i's new row: to the mailbox for the user's next rating in
+                    // the block, else to HBM (the other store goes to a sink)
+                    const int64_t i = (int64_t)__builtin_amdgcn_readlane(i_v, t);
+                    const uint32_t lw = (uint32_t)__builtin_amdgcn_readlane(lw_v, t);
+                    const bool has_succ = (lw >> 31) != 0;
+                    const int ws = has_succ ? (int)(lw & 0xFFFFu) : dummy;
+                    // wave-uniform destinations: the HBM row or a sink row
+                    float* urow = has_succ ? a.trash + kWave * FP : a.U + i * F;
+                    float* mrow = mb_u + ws * F;
+#pragma unroll
+                    for (int x = 0; x < FP; ++x) {
+                        const int f = lane + x * kWave;
+                        const float unew = usr ? u[t][x] + a.g[2] * (err * v[x] - a.l[2] * u[t][x]) : u[t][x];
+                        if (f < F) {
+                            mrow[f] = unew;
+                            urow[f] = unew;
+                        }
+                        const float vn = v[x] + a.g[3] * (err * u[t][x] - a.l[3] * v[x]);
+                        v[x] = itm ? vn : v[x];
+                    }
+                    const float bh_new = bh + a.g[1] * (err - a.l[1] * bh);
+                    bh = itm ? bh_new : bh;
+#pragma unroll
+                    for (int y = 0; y < KP; ++y) {
+                        // an explicit slot has cn == 0; padding slots stay zero either way
+                        const bool rs = cn[t][y] == 0.0f;
+                        const float wn = w[y] + a.g[4] * (err * rw[t][y] - a.l[4] * w[y]);
+                        const float cnn = c[y] + a.g[5] * (err * cn[t][y] - a.l[5] * c[y]);
+                        w[y] = (itm && rs) ? wn : w[y];
+                        c[y] = (itm && !rs) ? cnn : c[y];
+                    }
+                }
+                // publish the group (lane t: rating gs + t): b_i to the mailbox or
+                // HBM, then the hand-over sequence numbers and the done flags
+                {
+                    const bool live = lane < cnt;
+                    const bool succ = live && ((uint32_t)lw_v >> 31) != 0;
+                    const int ws = succ ? (lw_v & 0xFFFF) : dummy;
+                    const float bnew = usr ? bi_v + a.g[0] * (errv - a.l[0] * bi_v) : bi_v;
+                    if (live) {
+                        mb_b[ws] = bnew;
+                        *(succ ? a.trash + 2 * kWave * FP + lane : a.bu + i_v) = bnew;
+                    }
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+                    if (live) {
+                        __hip_atomic_store(&mb_seq[ws], ((lw_v >> 16) & 0x3FFF) + 1, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_WORKGROUP);
+                        __hip_atomic_store(&rdone[(gs + lane) % kRing], gs + lane + 1, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_WORKGROUP);
+                    }
+                }
+                if (gn < len && !have_next) {
+                    wait_group(gn, cntn);
+                    load_group(gn, cntn);
+                }
             }
-        }
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
-#pragma unroll
-        for (int x = 0; x < FP; ++x) {
-            const int f = lane + x * kWave;
-            const float mv = mb_u[f < F ? pslot * F + f : dummy * F];
-            R.u[x] = f < F ? (has_pred ? mv : S.u[t][x]) : 0.0f;
-        }
-        const float bi_s = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, S.bi), t));
-        const float b0_s = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, S.b0), t));
-        bi_out = has_pred ? mb_b[pslot] : bi_s;
-        const float base_i = mu + b0_s;
-        int code[KP];
-        int nR = 0;
-#pragma unroll
-        for (int y = 0; y < KP; ++y) {
-            const int k = lane + y * kWave;
-            code[y] = k < K ? (int)((S.nb[t >> 2][y] >> (8 * (t & 3) + (lane & 1) * 4)) & 15u) : 0;
-            nR += __popcll(__ballot(code[y] != 0));
-        }
-        const float sR = nR > 0 ? __builtin_amdgcn_rsqf((float)nR) : 0.0f;
-        const float sN = K - nR > 0 ? __builtin_amdgcn_rsqf((float)(K - nR)) : 0.0f;
-        R.exm = 0u;
-#pragma unroll
-        for (int y = 0; y < KP; ++y) {
-            const int k = lane + y * kWave;
-            const bool ex = code[y] != 0;
-            const bool im = !ex && k < K;
-            const float x = ex ? ((float)code[y] * inv_s - base_i - bhn[y]) * sR : (im ? sN : 0.0f);
-            R.exm |= (ex ? 1u : 0u) << y;
-            R.xt[y] = x * (ex ? pw[y] : pc[y]);
-            R.xa[y] = x * (ex ? iw[y] : ic[y]);
-            pw[y] = ex ? pw[y] * a.a_w : pw[y];
-            iw[y] = ex ? iw[y] * a.inv_aw : iw[y];
-            pc[y] = im ? pc[y] * a.a_c : pc[y];
-            ic[y] = im ? ic[y] * a.inv_ac : ic[y];
-        }
-    };
-    // pair (t, s), s < t, of a group -> index t(t-1)/2 + s
-    auto pair_part = [&](const Prepared<FP, KP>& T, const Prepared<FP, KP>& Sr, int t, int s) {
-        float uu = 0.0f;
-#pragma unroll
-        for (int x = 0; x < FP; ++x) uu += T.u[x] * Sr.u[x];
-        float q = a.gvp[t - 1 - s] * uu;
-#pragma unroll
-        for (int y = 0; y < KP; ++y) q += (T.ex(y) == Sr.ex(y)) ? T.xt[y] * Sr.xa[y] : 0.0f;
-        return q;
-    };
-    // The chain of one group: the errors from P (lane t: r - mu - b_i - P_t, the
-    // item-state part still to subtract) and the rows of Q, then the user rows
-    // and the item state moved to the group's end.  Lane t of reff/bi/lw holds
-    // rating t; cnt <= G ratings.
-    float v[FP], w[KP], c[KP], bh = 0.0f;
-    auto chain = [&](const auto& R, float pt_l, float reff_l, float bi_l, uint32_t user_l, uint32_t lw_l,
-                     const auto& qrow, const float (&pwg)[KP], const float (&pcg)[KP], int cnt) {
-        constexpr int GN = std::extent<std::remove_reference_t<decltype(R)>>::value;
-        // lane t: e_t after the substitution
-        float val = reff_l - a.pab[lane < GN ? lane : 0] * bh - pt_l;
-        float e[GN];
-#pragma unroll
-        for (int s = 0; s < GN; ++s) {
-            e[s] = 0.0f;
-            if (s < cnt) {
-                e[s] = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, val), s));
-                val -= lane > s ? qrow[s] * e[s] : 0.0f;
-            }
-        }
-        // user rows from v_t, the item vector before rating t, then the state
-        float vacc[FP], wacc[KP], cacc[KP];
-#pragma unroll
-        for (int x = 0; x < FP; ++x) vacc[x] = 0.0f;
-#pragma unroll
-        for (int y = 0; y < KP; ++y) wacc[y] = cacc[y] = 0.0f;
-#pragma unroll
-        for (int t = 0; t < GN; ++t) {
-            if (t >= cnt) break;
-            const int64_t i = (int64_t)__builtin_amdgcn_readlane((int)user_l, t);
-            const uint32_t lw = (uint32_t)__builtin_amdgcn_readlane((int)lw_l, t);
-            const bool has_succ = (lw >> 31) != 0;
-            const int ws = has_succ ? (int)(lw & 0xFFFFu) : dummy;
-            // wave-uniform destinations: the HBM row or a sink row
-            float* urow = has_succ ? a.trash + kWave * FP : a.U + i * F;
-            float* mrow = mb_u + ws * F;
-            const float gu = a.g_u * e[t] * a.pav[t];
-            const float gv = a.pvi[t] * e[t];
+            __builtin_amdgcn_s_setprio(0);
 #pragma unroll
             for (int x = 0; x < FP; ++x) {
                 const int f = lane + x * kWave;
-                const float vt = v[x] + vacc[x];
-                const float unew = a.a_u * R[t].u[x] + gu * vt;
                 if (f < F) {
-                    mrow[f] = unew;
-                    urow[f] = unew;
+                    a.V[j * F + f] = v[x];
                 }
-                vacc[x] += gv * R[t].u[x];
             }
+            if (lane == 0) a.bv[j] = bh;
 #pragma unroll
             for (int y = 0; y < KP; ++y) {
-                const float d = e[t] * R[t].xa[y];
-                wacc[y] += R[t].ex(y) ? d : 0.0f;
-                cacc[y] += R[t].ex(y) ? 0.0f : d;
+                const int k = lane + y * kWave;
+                if (k < K) {
+                    a.W[j * K + k] = w[y];
+                    a.C[j * K + k] = c[y];
+                }
+            }
+        } else {
+            // ---- helper wave h: ratings n = h, h + H, ... of the segment
+            const int h = role - 1;
+            const int mcount = h < len ? (len - h + kHelpers - 1) / kHelpers : 0;
+            bool dead = false;  // after one failed wait, later waits are skipped so the kernel ends
+            float bhn[KP];
+#pragma unroll
+            for (int y = 0; y < KP; ++y) {
+                const int k = lane + y * kWave;
+                bhn[y] = k < K ? a.nbr_b0[j * K + k] : 0.0f;
+            }
+            // HBM loads of kHG ratings (t0.. of the current word batch); no waits
+            auto hstage = [&](HStage<FP, KP>& S, uint32_t pkv, uint32_t lkv, int mb, int t0, int nbw) {
+#pragma unroll
+                for (int t = 0; t < kHG; ++t) {
+                    const int tt = t0 + t;
+                    const bool valid = tt < nbw;
+                    const uint32_t pw = (uint32_t)__builtin_amdgcn_readlane((int)pkv, tt & 63);
+                    const uint32_t lw = (uint32_t)__builtin_amdgcn_readlane((int)lkv, tt & 63);
+                    S.pw[t] = pw;
+                    S.lw[t] = lw;
+                    const int64_t i = valid ? (int64_t)(pw >> 4) : 0;
+                    const int64_t pos = valid ? ea + h + (int64_t)kHelpers * (mb + tt) : ea;
+#pragma unroll
+                    for (int x = 0; x < FP; ++x) {
+                        const int f = lane + x * kWave;
+                        S.u[t][x] = *(f < F ? a.U + i * F + f : a.trash + lane);
+                    }
+                    S.bi[t] = a.bu[i];
+                    S.b0[t] = a.b0[i];
+                    const uint8_t* nbp = a.nib + pos * a.nstride;
+#pragma unroll
+                    for (int y = 0; y < KP; ++y) {
+                        const int byte = (lane >> 1) + y * (kWave / 2);
+                        S.nb[t][y] = nbp[byte < a.nstride ? byte : 0];
+                    }
+                }
+            };
+            // user-side inputs of each staged rating into the ring, in order
+            auto hprep = [&](HStage<FP, KP>& S, int mb, int t0, int nbw) {
+#pragma unroll
+                for (int t = 0; t < kHG; ++t) {
+                    const int tt = t0 + t;
+                    if (tt >= nbw) break;
+                    const int n = h + kHelpers * (mb + tt);
+                    const int sl = n % kRing;
+                    const uint32_t pw = S.pw[t], lw = S.lw[t];
+                    // the slot's previous rating, n - kRing, must be done
+                    if (n >= kRing) {
+                        int spins = 0;
+                        while (!dead && __builtin_amdgcn_readfirstlane(__hip_atomic_load(
+                                            &rdone[sl], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) < n - kRing + 1) {
+                            if (++spins > kSpinLimit) {
+                                if (lane == 0) atomicOr(a.err, 4);
+                                dead = true;
+                            }
+                            __builtin_amdgcn_s_sleep(1);
+                        }
+                    }
+                    // an earlier rating of the user in this block hands its row over
+                    const bool has_pred = ((lw >> 30) & 1u) != 0;
+                    const int pslot = has_pred ? (int)(lw & 0xFFFFu) : dummy;
+                    if (has_pred) {
+                        const int want = (int)((lw >> 16) & 0x3FFFu);
+                        int spins = 0;
+                        while (!dead && __builtin_amdgcn_readfirstlane(__hip_atomic_load(
+                                            &mb_seq[pslot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) != want) {
+                            if (++spins > kSpinLimit) {
+                                if (lane == 0) atomicOr(a.err, 2);
+                                dead = true;
+                            }
+                            __builtin_amdgcn_s_sleep(1);
+                        }
+                    }
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+                    float u[FP];
+#pragma unroll
+                    for (int x = 0; x < FP; ++x) {
+                        const int f = lane + x * kWave;
+                        const float mv = mb_u[f < F ? pslot * F + f : dummy * F];
+                        u[x] = f < F ? (has_pred ? mv : S.u[t][x]) : 0.0f;
+                    }
+                    const float bi = has_pred ? mb_b[pslot] : S.bi[t];
+                    const float base_i = mu + S.b0[t];
+                    int code[KP];
+                    int nR = 0;
+#pragma unroll
+                    for (int y = 0; y < KP; ++y) {
+                        const int k = lane + y * kWave;
+                        code[y] = k < K ? (int)((S.nb[t][y] >> ((lane & 1) * 4)) & 15u) : 0;
+                        nR += __popcll(__ballot(code[y] != 0));
+                    }
+                    const float sR = nR > 0 ? __builtin_amdgcn_rsqf((float)nR) : 0.0f;
+                    const float sN = K - nR > 0 ? __builtin_amdgcn_rsqf((float)(K - nR)) : 0.0f;
+                    float* d = rdata + sl * RS;
+#pragma unroll
+                    for (int x = 0; x < FP; ++x) {
+                        const int f = lane + x * kWave;
+                        if (f < F) d[f] = u[x];
+                    }
+#pragma unroll
+                    for (int y = 0; y < KP; ++y) {
+                        const int k = lane + y * kWave;
+                        const float resid = (float)code[y] * inv_s - base_i - bhn[y];
+                        if (k < K) {
+                            d[F + k] = code[y] ? resid * sR : 0.0f;
+                            d[F + K + k] = code[y] ? 0.0f : sN;
+                        }
+                    }
+                    const float r = (float)(pw & 15u) * inv_s;
+                    if (lane == 0) {
+                        int* hd = rhdr + sl * 4;
+                        hd[0] = __float_as_int(r - (mu + bi));
+                        hd[1] = __float_as_int(bi);
+                        hd[2] = (int)(pw >> 4);
+                        hd[3] = (int)lw;
+                    }
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+                    if (lane == 0) __hip_atomic_store(&rready[sl], n + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                }
+            };
+            HStage<FP, KP> SA, SB;
+            for (int mb = 0; mb < mcount; mb += kWave) {
+                const int nbw = mcount - mb < kWave ? mcount - mb : kWave;
+                uint32_t pkv = 0u, lkv = 0u;
+                if (lane < nbw) {
+                    const int64_t pos = ea + h + (int64_t)kHelpers * (mb + lane);
+                    pkv = pk[pos];
+                    lkv = link[pos];
+                }
+                hstage(SA, pkv, lkv, mb, 0, nbw);
+                for (int t0 = 0;; t0 += 2 * kHG) {
+                    hstage(SB, pkv, lkv, mb, t0 + kHG, nbw);
+                    hprep(SA, mb, t0, nbw);
+                    if (t0 + kHG >= nbw) break;
+                    hstage(SA, pkv, lkv, mb, t0 + 2 * kHG, nbw);
+                    hprep(SB, mb, t0 + kHG, nbw);
+                    if (t0 + 2 * kHG >= nbw) break;
+                }
             }
         }
-        const float pv = a.pav[cnt < GN ? cnt : GN];
-#pragma unroll
-        for (int x = 0; x < FP; ++x) v[x] = pv * (v[x] + vacc[x]);
-#pragma unroll
-        for (int y = 0; y < KP; ++y) {
-            w[y] = pwg[y] * (w[y] + wacc[y]);
-            c[y] = pcg[y] * (c[y] + cacc[y]);
-        }
-        float bn = a.pab[cnt < GN ? cnt : GN] * bh;
-#pragma unroll
-        for (int t = 0; t < GN; ++t)
-            if (t < cnt) bn += a.gbp[cnt - 1 - t] * e[t];
-        bh = bn;
-        // b_i of lane t's user to the mailbox or HBM, then the hand-over numbers
-        const bool live = lane < cnt;
-        const bool succ = live && (lw_l >> 31) != 0;
-        const int ws = succ ? (int)(lw_l & 0xFFFFu) : dummy;
-        const float bnew = a.a_bu * bi_l + a.g_bu * val;
-        if (live) {
-            mb_b[ws] = bnew;
-            *(succ ? a.trash + 2 * kWave * FP + lane : a.bu + user_l) = bnew;
-        }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
-        if (succ)
-            __hip_atomic_store(&mb_seq[ws], (int)((lw_l >> 16) & 0x3FFFu) + 1, __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_WORKGROUP);
-    };
-    auto load_item = [&](int64_t j) {
+    }
+
+    while (true) {
+        int g = 0;
+        if (lane == 0) g = atomicAdd(&next_seg, 1);
+        g = __builtin_amdgcn_readfirstlane(g);
+        if (g >= nsegs) break;
+        const int64_t seg = g0 + g;
+        const int64_t j = a.seg_col[seg];
+        const int64_t ea = a.seg_start[seg], ez = a.seg_start[seg + 1];
+        if (ez - ea > 4 * kGroup) __builtin_amdgcn_s_setprio(2);
+
+        // item state, register resident for the whole segment
+        float v[FP], w[KP], c[KP], bhn[KP];
 #pragma unroll
         for (int x = 0; x < FP; ++x) {
             const int f = lane + x * kWave;
             v[x] = f < F ? a.V[j * F + f] : 0.0f;
         }
-        bh = a.bv[j];
+        float bh = a.bv[j];
 #pragma unroll
         for (int y = 0; y < KP; ++y) {
             const int k = lane + y * kWave;
-            w[y] = k < K ? a.W[j * K + k] : 0.0f;
-            c[y] = k < K ? a.C[j * K + k] : 0.0f;
+            w[y] = c[y] = bhn[y] = 0.0f;
+            if (k < K) {
+                w[y] = a.W[j * K + k];
+                c[y] = a.C[j * K + k];
+                bhn[y] = a.nbr_b0[j * K + k];
+            }
         }
-    };
-    auto load_bhn = [&](int64_t j) {
+
+        // (user, code) and hand-over words of a group: one vector load each
+        auto words = [&](uint32_t& px, uint32_t& lx, int64_t gb) {
+            px = lane < kGroup ? pk[gb + lane] : 0u;
+            lx = lane < kGroup ? link[gb + lane] : 0u;
+        };
+        // wait for an earlier rating of the same user, then load the inputs
+        // HBM inputs of a group, loaded a group ahead; no waits here, so a
+        // rating never waits on a hand-over meant for a later one
+        auto stage = [&](Stage<FP, KP>& S, uint32_t px, uint32_t lx, int64_t gb) {
 #pragma unroll
-        for (int y = 0; y < KP; ++y) {
-            const int k = lane + y * kWave;
-            bhn[y] = k < K ? a.nbr_b0[j * K + k] : 0.0f;
+            for (int sl = 0; sl < kGroup; ++sl) {
+                const uint32_t pw = (uint32_t)__builtin_amdgcn_readlane((int)px, sl);
+                const uint32_t lw = (uint32_t)__builtin_amdgcn_readlane((int)lx, sl);
+                S.pk[sl] = pw;
+                S.lk[sl] = lw;
+                const int64_t i = pw >> 4;
+                // lanes past F read the sink row: every load is issued by all lanes
+#pragma unroll
+                for (int x = 0; x < FP; ++x) {
+                    const int f = lane + x * kWave;
+                    const float gv = *(f < F ? a.U + i * F + f : a.trash + lane);
+                    S.gu[sl][x] = f < F ? gv : 0.0f;   // lanes past F keep u = 0 (and so v = 0)
+                }
+                S.gbi[sl] = a.bu[i];
+                S.b0[sl] = a.b0[i];
+                const uint8_t* nbp = a.nib + (gb + sl) * a.nstride;
+#pragma unroll
+                for (int y = 0; y < KP; ++y) {
+                    const int byte = (lane >> 1) + y * (kWave / 2);
+                    S.nb[sl][y] = nbp[byte < a.nstride ? byte : 0];
+                }
+            }
+        };
+        // Eq. (rr) and Eq. (sgd_update) for the ratings of one group, in order;
+        // then hand the updated user rows to later ratings of the same users
+        auto compute = [&](Stage<FP, KP>& S, int64_t gb) {
+            // are the hand-overs of the whole group there?  lane t checks rating gb + t
+            uint32_t lwl = 0u;
+#pragma unroll
+            for (int sl = 0; sl < kGroup; ++sl) lwl = lane == sl ? S.lk[sl] : lwl;
+            const bool hpl = lane < kGroup && gb + lane < ez && ((lwl >> 30) & 1u);
+            const bool okl = !hpl || __hip_atomic_load(&mb_seq[lwl & 0xFFFFu], __ATOMIC_RELAXED,
+                                                       __HIP_MEMORY_SCOPE_WORKGROUP) == (int)((lwl >> 16) & 0x3FFFu);
+            const bool ready = __ballot(!okl) == 0ull;
+            float mrow[kGroup][FP], mbv[kGroup];
+            if (ready) {
+                // read every handed-over row of the group at once
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+#pragma unroll
+                for (int sl = 0; sl < kGroup; ++sl) {
+                    const uint32_t lw = S.lk[sl];
+                    const int rs = (gb + sl < ez && ((lw >> 30) & 1u)) ? (int)(lw & 0xFFFFu) : dummy;
+#pragma unroll
+                    for (int x = 0; x < FP; ++x) {
+                        const int f = lane + x * kWave;
+                        mrow[sl][x] = mb_u[f < F ? rs * F + f : dummy * F];
+                    }
+                    mbv[sl] = mb_b[rs];
+                }
+            }
+#pragma unroll
+            for (int sl = 0; sl < kGroup; ++sl) {
+                const bool valid = gb + sl < ez;
+                const uint32_t lw = S.lk[sl];
+                const bool has_pred = valid && ((lw >> 30) & 1u);
+                const bool has_succ = valid && (lw >> 31);
+                const int slot = (int)(lw & 0xFFFFu);
+                const int64_t i = S.pk[sl] >> 4;
+                const float r = (float)(S.pk[sl] & 15u) * inv_s;
+                const float base_i = mu + S.b0[sl];
+                int code[KP];
+                float resid[KP];
+                int nR = 0;
+#pragma unroll
+                for (int y = 0; y < KP; ++y) {
+                    const int k = lane + y * kWave;
+                    code[y] = k < K ? (int)((S.nb[sl][y] >> ((lane & 1) * 4)) & 15u) : 0;
+                    resid[y] = (float)code[y] * inv_s - base_i - bhn[y];
+                    nR += __popcll(__ballot(code[y] != 0));
+                }
+                const float sR = nR > 0 ? __builtin_amdgcn_rsqf((float)nR) : 0.0f;
+                const float sN = K - nR > 0 ? __builtin_amdgcn_rsqf((float)(K - nR)) : 0.0f;
+                // an earlier rating of the user in this block hands its row over
+                if (has_pred && !ready) {
+                    const int want = (int)((lw >> 16) & 0x3FFFu);
+                    int spins = 0;
+                    while (__builtin_amdgcn_readfirstlane(__hip_atomic_load(&mb_seq[slot], __ATOMIC_RELAXED,
+                                                                            __HIP_MEMORY_SCOPE_WORKGROUP)) != want) {
+                        if (++spins > kSpinLimit) {
+                            if (lane == 0) atomicOr(a.err, 2);
+                            break;
+                        }
+                        __builtin_amdgcn_s_sleep(1);
+                    }
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+#pragma unroll
+                    for (int x = 0; x < FP; ++x) {
+                        const int f = lane + x * kWave;
+                        mrow[sl][x] = mb_u[f < F ? slot * F + f : dummy * F];
+                    }
+                    mbv[sl] = mb_b[slot];
+                }
+                float u[FP];
+#pragma unroll
+                for (int x = 0; x < FP; ++x) {
+                    const int f = lane + x * kWave;
+                    u[x] = has_pred ? (f < F ? mrow[sl][x] : 0.0f) : S.gu[sl][x];
+                }
+                const float bi = has_pred ? mbv[sl] : S.gbi[sl];
+                // u.v + |R^K|^-1/2 sum resid*w + |N^K|^-1/2 sum c: one reduction
+                float part = 0.0f;
+#pragma unroll
+                for (int x = 0; x < FP; ++x) part += u[x] * v[x];
+#pragma unroll
+                for (int y = 0; y < KP; ++y) {
+                    const float t = code[y] ? resid[y] * w[y] * sR : c[y] * sN;
+                    part += lane + y * kWave < K ? t : 0.0f;
+                }
+                const float err = r - (mu + bi + bh + wave_sum(part));
+                // all right-hand sides from the pre-step state.  The last rating
+                // of a user in the block writes HBM; earlier ones only the
+                // mailbox.  Stores that must not happen go to sinks instead, so
+                // every lane issues the same stores without branches.
+                const bool to_hbm = valid && !has_succ;
+                const int ws = has_succ ? slot : dummy;
+                const float bnew = usr ? bi + a.g[0] * (err - a.l[0] * bi) : bi;
+                float* bsink = a.trash + 2 * kWave * FP;
+                *((lane == 0 && to_hbm) ? a.bu + i : bsink + lane) = bnew;
+                mb_b[lane == 0 ? ws : dummy] = bnew;
+                const float bh_new = bh + a.g[1] * (err - a.l[1] * bh);
+                bh = (valid && itm) ? bh_new : bh;
+#pragma unroll
+                for (int x = 0; x < FP; ++x) {
+                    const int f = lane + x * kWave;
+                    const float unew = usr ? u[x] + a.g[2] * (err * v[x] - a.l[2] * u[x]) : u[x];
+                    *((to_hbm && f < F) ? a.U + i * F + f : a.trash + kWave * FP + f) = unew;
+                    mb_u[f < F ? ws * F + f : dummy * F] = unew;
+                    const float vn = v[x] + a.g[3] * (err * u[x] - a.l[3] * v[x]);
+                    v[x] = (valid && itm) ? vn : v[x];
+                }
+#pragma unroll
+                for (int y = 0; y < KP; ++y) {
+                    const bool in_k = lane + y * kWave < K;
+                    const float wn = w[y] + a.g[4] * (sR * err * resid[y] - a.l[4] * w[y]);
+                    const float cn = c[y] + a.g[5] * (sN * err - a.l[5] * c[y]);
+                    w[y] = (valid && itm && in_k && code[y]) ? wn : w[y];
+                    c[y] = (valid && itm && in_k && !code[y]) ? cn : c[y];
+                }
+            }
+            // the mailbox rows are written: publish their sequence numbers
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+            if (lane == 0) {
+#pragma unroll
+                for (int sl = 0; sl < kGroup; ++sl) {
+                    const uint32_t lw = S.lk[sl];
+                    const bool has_succ = gb + sl < ez && (lw >> 31);
+                    const int ws = has_succ ? (int)(lw & 0xFFFFu) : dummy;
+                    __hip_atomic_store(&mb_seq[ws], (int)((lw >> 16) & 0x3FFFu) + 1, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_WORKGROUP);
+                }
+            }
+        };
+
+        Stage<FP, KP> SA, SB;
+        uint32_t pkA, lkA, pkB, lkB;
+        if (ez - ea <= kGroup) {
+            words(pkA, lkA, ea);
+            stage(SA, pkA, lkA, ea);
+            compute(SA, ea);
+        } else {
+            // inputs of group g+1 in flight while group g computes
+            words(pkA, lkA, ea);
+            words(pkB, lkB, ea + kGroup);
+            stage(SA, pkA, lkA, ea);
+            words(pkA, lkA, ea + 2 * kGroup);
+            for (int64_t gb = ea;; gb += 2 * kGroup) {
+                stage(SB, pkB, lkB, gb + kGroup);
+                words(pkB, lkB, gb + 3 * kGroup);
+                compute(SA, gb);
+                if (gb + kGroup >= ez) break;
+                stage(SA, pkA, lkA, gb + 2 * kGroup);
+                words(pkA, lkA, gb + 4 * kGroup);
+                compute(SB, gb + kGroup);
+                if (gb + 2 * kGroup >= ez) break;
+            }
         }
-    };
-    auto store_item = [&](int64_t j) {
+        __builtin_amdgcn_s_setprio(0);
 #pragma unroll
         for (int x = 0; x < FP; ++x) {
             const int f = lane + x * kWave;
-            if (f < F) a.V[j * F + f] = v[x];
+            if (f < F) {
+                a.V[j * F + f] = v[x];
+            }
         }
         if (lane == 0) a.bv[j] = bh;
 #pragma unroll
@@ -406,367 +699,36 @@ __global__ __launch_bounds__(kSgdWaves* kWave) void k_sgd_stratum(SgdArgs a, con
                 a.C[j * K + k] = c[y];
             }
         }
-    };
-    // the P-value of every rating of the group: dots with the group-start state
-    auto p_parts = [&](const auto& R, auto& p) {
-        constexpr int GN = std::extent<std::remove_reference_t<decltype(R)>>::value;
-#pragma unroll
-        for (int t = 0; t < GN; ++t) {
-            float uv = 0.0f;
-#pragma unroll
-            for (int x = 0; x < FP; ++x) uv += R[t].u[x] * v[x];
-            float q = a.pav[t] * uv;
-#pragma unroll
-            for (int y = 0; y < KP; ++y) q += R[t].xt[y] * (R[t].ex(y) ? w[y] : c[y]);
-            p[t] = q;
-        }
-    };
-
-    if (wv < ngang * kGangWaves) {
-        // ---- a gang: helpers fill ring groups, the item wave consumes them
-        const int gang = wv / kGangWaves, role = wv % kGangWaves;
-        const int64_t seg = g0 + gang;
-        const int64_t j = a.seg_col[seg];
-        const int64_t ea = a.seg_start[seg];
-        const int len = (int)(a.seg_start[seg + 1] - ea);
-        const int ngroups = (len + G - 1) / G;
-        float* ring = rings + (size_t)gang * gang_floats;
-        int* ready = reinterpret_cast<int*>(ring + RG * GS);
-        int* done = ready + kMaxRingGroups;
-        if (role == 0) {
-            // ---- item wave
-            __builtin_amdgcn_s_setprio(3);
-            load_item(j);
-            for (int g = 0; g < ngroups; ++g) {
-                const int cnt = len - g * G < G ? len - g * G : G;
-                const int gs = g % RG;
-                int spins = 0;
-                while (!dead && __builtin_amdgcn_readfirstlane(__hip_atomic_load(
-                                    &ready[gs], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) != g + 1) {
-                    if (++spins > kSpinLimit) {
-                        if (lane == 0) atomicOr(a.err, 4);
-                        dead = true;
-                    }
-                }
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
-                const float* base = ring + (size_t)gs * GS;
-                Prepared<FP, KP> R[G];
-#pragma unroll
-                for (int t = 0; t < G; ++t) {
-                    const float* d = base + t * RS;
-                    const bool ok = t < cnt;
-#pragma unroll
-                    for (int x = 0; x < FP; ++x) {
-                        const int f = lane + x * kWave;
-                        const float uv = d[f < F ? f : 0];
-                        R[t].u[x] = (ok && f < F) ? uv : 0.0f;
-                    }
-                    const uint64_t* eb = reinterpret_cast<const uint64_t*>(d + ring_mask_off(F, K));
-                    R[t].exm = 0u;
-#pragma unroll
-                    for (int y = 0; y < KP; ++y) {
-                        const int k = lane + y * kWave;
-                        const float xt = d[F + (k < K ? k : 0)], xa = d[F + K + (k < K ? k : 0)];
-                        const bool inb = ok && k < K;
-                        R[t].xt[y] = inb ? xt : 0.0f;
-                        R[t].xa[y] = inb ? xa : 0.0f;
-                        R[t].exm |= (inb && ((eb[y] >> lane) & 1ull)) ? (1u << y) : 0u;
-                    }
-                }
-                const int* hd = reinterpret_cast<const int*>(base + G * RS) + 4 * (lane < cnt ? lane : 0);
-                const float reff_l = __int_as_float(hd[0]);
-                const float bi_l = __int_as_float(hd[1]);
-                const uint32_t user_l = (uint32_t)hd[2];
-                const uint32_t lw_l = lane < cnt ? (uint32_t)hd[3] : 0u;
-                const float* qb = base + G * RS + 4 * G + (lane < G ? lane : 0) * G;
-                float qrow[G];
-#pragma unroll
-                for (int s = 0; s < G; ++s) qrow[s] = qb[s];
-                float pwg[KP], pcg[KP];
-                const float* pg = base + G * RS + 4 * G + G * G;
-#pragma unroll
-                for (int y = 0; y < KP; ++y) {
-                    const int k = lane + y * kWave;
-                    pwg[y] = k < K ? pg[k] : 1.0f;
-                    pcg[y] = k < K ? pg[K + k] : 1.0f;
-                }
-                // the ring group is read: hand it back to its helper
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
-                if (lane == 0) __hip_atomic_store(&done[gs], g + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                float p[G];
-                p_parts(R, p);
-                const float tot = batched_sum<G>(p, lane);
-                const float pt_l = __shfl(tot, (lane < G ? lane : 0) << (6 - ilog2c(G)), kWave);
-                chain(R, pt_l, reff_l, bi_l, user_l, lw_l, qrow, pwg, pcg, cnt);
-            }
-            __builtin_amdgcn_s_setprio(0);
-            store_item(j);
-        } else {
-            // ---- helper h: groups h, h + H, ... of the run
-            const int h = role - 1;
-            load_bhn(j);
-            GStage<FP, KP, G> SA;
-            if (h < ngroups) stage(SA, ea + (int64_t)h * G, len - h * G < G ? len - h * G : G);
-            for (int g = h; g < ngroups; g += kHelpers) {
-                const int cnt = len - g * G < G ? len - g * G : G;
-                const int gs = g % RG;
-                GStage<FP, KP, G> SB;
-                const int gn = g + kHelpers;
-                if (gn < ngroups) stage(SB, ea + (int64_t)gn * G, len - gn * G < G ? len - gn * G : G);
-                // the ring group's previous occupant must have been read
-                if (g >= RG) {
-                    int spins = 0;
-                    while (!dead && __builtin_amdgcn_readfirstlane(__hip_atomic_load(
-                                        &done[gs], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) < g - RG + 1) {
-                        if (++spins > kSpinLimit) {
-                            if (lane == 0) atomicOr(a.err, 4);
-                            dead = true;
-                        }
-                        __builtin_amdgcn_s_sleep(1);
-                    }
-                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
-                }
-                float* base = ring + (size_t)gs * GS;
-                float pw[KP], pc[KP], iw[KP], ic[KP];
-#pragma unroll
-                for (int y = 0; y < KP; ++y) {
-                    pw[y] = pc[y] = 1.0f;
-                    iw[y] = a.g_w * a.inv_aw;
-                    ic[y] = a.g_c * a.inv_ac;
-                }
-                int* hdw = reinterpret_cast<int*>(base + G * RS);
-                // Q: the pairs of the group, each added as soon as its later rating
-                // is prepared (the earlier one is read back from the ring)
-                // rows [1, TS) are summed first, rows [TS, G) second (fewer live registers)
-                constexpr int TS = G > 6 ? 6 : G;
-                constexpr int NQ1 = pow2_at_least(TS * (TS - 1) / 2);
-                constexpr int NQ2 = pow2_at_least(NPAIR - TS * (TS - 1) / 2);
-                float q[NQ1 > NQ2 ? NQ1 : NQ2];
-                auto flush_pairs = [&](auto& qq, int first, int count) {
-                    constexpr int NQ = std::extent<std::remove_reference_t<decltype(qq)>>::value;
-                    const float tot = batched_sum<NQ>(qq, lane);
-                    const int idx = first + (lane >> (6 - ilog2c(NQ)));
-                    if ((lane & ((1 << (6 - ilog2c(NQ))) - 1)) == 0 && idx - first < count) {
-                        int tq = 1;
-                        while (tq * (tq + 1) / 2 <= idx) ++tq;
-                        const int sq = idx - tq * (tq - 1) / 2;
-                        base[G * RS + 4 * G + tq * G + sq] = tot + a.gbp[tq - 1 - sq];
-                    }
-                };
-#pragma unroll
-                for (int x = 0; x < NQ1; ++x) q[x] = 0.0f;
-#pragma unroll
-                for (int t = 0; t < G; ++t) {
-                    if (t == TS) {
-                        float q1[NQ1];
-#pragma unroll
-                        for (int x = 0; x < NQ1; ++x) q1[x] = q[x];
-                        flush_pairs(q1, 0, TS * (TS - 1) / 2);
-#pragma unroll
-                        for (int x = 0; x < NQ2; ++x) q[x] = 0.0f;
-                    }
-                    if (t < cnt) {
-                        Prepared<FP, KP> Rt;
-                        float bi = 0.0f;
-                        prep(SA, t, Rt, bi, pw, pc, iw, ic);
-                        float* d = base + t * RS;
-#pragma unroll
-                        for (int x = 0; x < FP; ++x) {
-                            const int f = lane + x * kWave;
-                            if (f < F) d[f] = Rt.u[x];
-                        }
-#pragma unroll
-                        for (int y = 0; y < KP; ++y) {
-                            const int k = lane + y * kWave;
-                            if (k < K) {
-                                d[F + k] = Rt.xt[y];
-                                d[F + K + k] = Rt.xa[y];
-                            }
-                            const uint64_t m = __ballot(Rt.ex(y));
-                            if (lane == 0) reinterpret_cast<uint64_t*>(d + ring_mask_off(F, K))[y] = m;
-                        }
-                        if (lane == 0) {
-                            const uint32_t pwv = (uint32_t)__builtin_amdgcn_readlane((int)SA.pw, t);
-                            const float r = (float)(pwv & 15u) * inv_s;
-                            hdw[4 * t + 0] = __float_as_int(r - (mu + bi));
-                            hdw[4 * t + 1] = __float_as_int(bi);
-                            hdw[4 * t + 2] = (int)(pwv >> 4);
-                            hdw[4 * t + 3] = __builtin_amdgcn_readlane((int)SA.lw, t);
-                        }
-#pragma unroll
-                        for (int s2 = 0; s2 < t; ++s2) {
-                            const float* ds = base + s2 * RS;
-                            const uint64_t* ebs = reinterpret_cast<const uint64_t*>(ds + ring_mask_off(F, K));
-                            Prepared<FP, KP> Rs;
-#pragma unroll
-                            for (int x = 0; x < FP; ++x) {
-                                const int f = lane + x * kWave;
-                                const float uv = ds[f < F ? f : 0];
-                                Rs.u[x] = f < F ? uv : 0.0f;
-                            }
-                            Rs.exm = 0u;
-#pragma unroll
-                            for (int y = 0; y < KP; ++y) {
-                                const int k = lane + y * kWave;
-                                const float xa = ds[F + K + (k < K ? k : 0)];
-                                Rs.xa[y] = k < K ? xa : 0.0f;
-                                Rs.xt[y] = 0.0f;
-                                Rs.exm |= (k < K && ((ebs[y] >> lane) & 1ull)) ? (1u << y) : 0u;
-                            }
-                            const int pidx = t * (t - 1) / 2 + s2 - (t >= TS ? TS * (TS - 1) / 2 : 0);
-                            q[pidx] = pair_part(Rt, Rs, t, s2);
-                        }
-                    }
-                }
-                float* pg = base + G * RS + 4 * G + G * G;
-#pragma unroll
-                for (int y = 0; y < KP; ++y) {
-                    const int k = lane + y * kWave;
-                    if (k < K) {
-                        pg[k] = pw[y];
-                        pg[K + k] = pc[y];
-                    }
-                }
-                if (TS < G) {
-                    float q2[NQ2];
-#pragma unroll
-                    for (int x = 0; x < NQ2; ++x) q2[x] = q[x];
-                    flush_pairs(q2, TS * (TS - 1) / 2, NPAIR - TS * (TS - 1) / 2);
-                } else {
-                    float q1[NQ1];
-#pragma unroll
-                    for (int x = 0; x < NQ1; ++x) q1[x] = q[x];
-                    flush_pairs(q1, 0, NPAIR);
-                }
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
-                if (lane == 0) __hip_atomic_store(&ready[gs], g + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                SA = SB;
-            }
-        }
-    }
-
-    // ---- the other runs: one wave per run, both parts
-    while (true) {
-        int gsel = 0;
-        if (lane == 0) gsel = atomicAdd(&next_seg, 1);
-        gsel = __builtin_amdgcn_readfirstlane(gsel);
-        if (gsel >= nsegs) break;
-        const int64_t seg = g0 + gsel;
-        const int64_t j = a.seg_col[seg];
-        const int64_t ea = a.seg_start[seg];
-        const int len = (int)(a.seg_start[seg + 1] - ea);
-        if (len > 4 * GP) __builtin_amdgcn_s_setprio(2);
-        load_item(j);
-        load_bhn(j);
-        const int ngroups = (len + GP - 1) / GP;
-        GStage<FP, KP, GP> SA;
-        stage(SA, ea, len < GP ? len : GP);
-        for (int g = 0; g < ngroups; ++g) {
-            const int cnt = len - g * GP < GP ? len - g * GP : GP;
-            GStage<FP, KP, GP> SB;
-            const int gn = g + 1;
-            if (gn < ngroups) stage(SB, ea + (int64_t)gn * GP, len - gn * GP < GP ? len - gn * GP : GP);
-            Prepared<FP, KP> R[GP];
-            float pw[KP], pc[KP], iw[KP], ic[KP];
-#pragma unroll
-            for (int y = 0; y < KP; ++y) {
-                pw[y] = pc[y] = 1.0f;
-                iw[y] = a.g_w * a.inv_aw;
-                ic[y] = a.g_c * a.inv_ac;
-            }
-            float bi_l = 0.0f;
-            // pairs (Q) and P values, each added as soon as its rating is prepared
-            float q[NPP];
-#pragma unroll
-            for (int x = 0; x < NPP; ++x) q[x] = 0.0f;
-#pragma unroll
-            for (int t = 0; t < GP; ++t) {
-                if (t < cnt) {
-                    float bi = 0.0f;
-                    prep(SA, t, R[t], bi, pw, pc, iw, ic);
-                    bi_l = lane == t ? bi : bi_l;
-                    float uv = 0.0f;
-#pragma unroll
-                    for (int x = 0; x < FP; ++x) uv += R[t].u[x] * v[x];
-                    float pp = a.pav[t] * uv;
-#pragma unroll
-                    for (int y = 0; y < KP; ++y) pp += R[t].xt[y] * (R[t].ex(y) ? w[y] : c[y]);
-                    q[NPAIRP + t] = pp;
-#pragma unroll
-                    for (int s2 = 0; s2 < t; ++s2) q[t * (t - 1) / 2 + s2] = pair_part(R[t], R[s2], t, s2);
-                } else {
-#pragma unroll
-                    for (int x = 0; x < FP; ++x) R[t].u[x] = 0.0f;
-#pragma unroll
-                    for (int y = 0; y < KP; ++y) R[t].xt[y] = R[t].xa[y] = 0.0f;
-                    R[t].exm = 0u;
-                }
-            }
-            const float tot = batched_sum<NPP>(q, lane);
-            constexpr int SH = 6 - ilog2c(NPP);
-            const int tl = lane < GP ? lane : 0;
-            float qrow[GP];
-#pragma unroll
-            for (int s = 0; s < GP; ++s) {
-                const int idx = s < tl ? tl * (tl - 1) / 2 + s : 0;
-                const float qv = __shfl(tot, idx << SH, kWave);
-                qrow[s] = s < tl ? qv + a.gbp[s < tl ? tl - 1 - s : 0] : 0.0f;
-            }
-            const float pt_l = __shfl(tot, (NPAIRP + tl) << SH, kWave);
-            const uint32_t pwl = lane < cnt ? SA.pw : 0u;
-            const float r = (float)(pwl & 15u) * inv_s;
-            const float reff_l = r - (mu + bi_l);
-            chain(R, pt_l, reff_l, bi_l, pwl >> 4, lane < cnt ? SA.lw : 0u, qrow, pw, pc, cnt);
-            SA = SB;
-        }
-        __builtin_amdgcn_s_setprio(0);
-        store_item(j);
     }
 }
 
 // Dynamic LDS of one block: the mailbox (slots + 1 rows of F floats, b_i and
-// a sequence word) and the gang rings with their flags.
-template <int G>
+// a sequence word) and the gang rings.
 static size_t sgd_lds_bytes(const SgdArgs& args)
 {
-    const size_t gang = (size_t)args.ring_groups * ring_group_floats(args.F, args.K, G) + 2 * kMaxRingGroups;
-    return ((size_t)args.ring_off + (size_t)args.max_gangs * gang) * sizeof(float);
+    const size_t gs = (size_t)kRing * (args.ring_rs + 6);
+    return ((size_t)args.ring_off + (size_t)args.max_gangs * gs) * sizeof(float);
 }
 
-template <int FP, int KP, int G>
-static int launch_sgd(SgdArgs args, const uint32_t* pk, const uint32_t* link, hipStream_t s)
+template <int FP, int KP>
+static int launch_sgd(const SgdArgs& args, const uint32_t* pk, const uint32_t* link, hipStream_t s)
 {
-    // as many ring groups and gangs as fit beside the mailbox
-    args.max_gangs = kMaxGangs;
-    args.ring_groups = kMaxRingGroups;
-    while (sgd_lds_bytes<G>(args) > (size_t)kMaxLdsBytes) {
-        if (args.ring_groups > 4) args.ring_groups = 4;
-        else if (args.max_gangs > 0) {
-            --args.max_gangs;
-            args.ring_groups = kMaxRingGroups;
-        } else break;
-    }
-    if (args.max_gangs == 0) args.ring_groups = 1;
-    const size_t lds = sgd_lds_bytes<G>(args);
+    const size_t lds = sgd_lds_bytes(args);
     if (lds > 64 * 1024) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sgd_stratum<FP, KP, G>),
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sgd_stratum<FP, KP>),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return hip_fail(e, "hipFuncSetAttribute(k_sgd_stratum)");
     }
-    hipLaunchKernelGGL((k_sgd_stratum<FP, KP, G>), dim3((unsigned)args.P), dim3(kSgdWaves * kWave), lds, s, args,
+    hipLaunchKernelGGL((k_sgd_stratum<FP, KP>), dim3((unsigned)args.P), dim3(kSgdWaves * kWave), lds, s, args,
                        pk, link);
     LSHMF_LAUNCHED("k_sgd_stratum");
     return LSHMF_OK;
 }
 
-// Group size: 8 ratings where the rows are short, 4 where the registers of
-// eight prepared ratings would not fit.
 template <int FP>
 static int launch_sgd_k(const SgdArgs& args, const uint32_t* pk, const uint32_t* link, hipStream_t s)
 {
-    if (args.K > kWave) return launch_sgd<FP, 2, 4>(args, pk, link, s);
-    if constexpr (FP <= 1) return launch_sgd<FP, 1, 8>(args, pk, link, s);
-    else return launch_sgd<FP, 1, 4>(args, pk, link, s);
+    return args.K <= kWave ? launch_sgd<FP, 1>(args, pk, link, s) : launch_sgd<FP, 2>(args, pk, link, s);
 }
 
 // Can k_sgd_stratum run this stream: the mailbox of every block in LDS and
@@ -812,42 +774,22 @@ int run_sgd(lshmf_ctx* c, Stream& st, const lshmf_hparams* hp, int epoch, int up
     a.P = c->P;
     a.nstride = c->nstride;
     a.slots = (int)st.max_block_slots;
+    a.upd = upd;
     a.inv_s = 1.0f / (float)d.rscale;
+    // gangs only where their rings fit beside the mailbox
     a.ring_off = (int)(((st.max_block_slots + 1) * (d.F + 2) + 3) & ~3LL);
+    a.ring_rs = d.F + 2 * d.K;
     a.max_gangs = kMaxGangs;
-    a.ring_groups = kMaxRingGroups;
-    // Eq. (learn_rate): gamma_t = alpha / (1 + beta * t^1.5); Eq. (sgd_update)
-    // as theta <- (1 - gamma lambda) theta + gamma (e x).  Order of the six
-    // groups: b_i, bh_j, u_i, v_j, w_j, c_j.
+    while (a.max_gangs > 0 && sgd_lds_bytes(a) > (size_t)kMaxLdsBytes) --a.max_gangs;
+    // Eq. (learn_rate): gamma_t = alpha / (1 + beta * t^1.5)
     const double den = 1.0 + (double)hp->beta * std::pow((double)epoch, 1.5);
-    double g[6], dec[6];
     for (int x = 0; x < 6; ++x) {
-        g[x] = (double)(float)((double)hp->alpha[x] / den);
-        dec[x] = 1.0 - g[x] * (double)hp->lambda[x];
+        a.g[x] = (float)((double)hp->alpha[x] / den);
+        a.l[x] = hp->lambda[x];
     }
-    const bool usr = (upd & 1) != 0, itm = (upd & 2) != 0;
-    if (d.model == LSHMF_PLAIN_MF) g[0] = g[1] = 0.0, dec[0] = dec[1] = 1.0;  // no biases to learn
-    if (!usr) g[0] = g[2] = 0.0, dec[0] = dec[2] = 1.0;
-    if (!itm) g[1] = g[3] = g[4] = g[5] = 0.0, dec[1] = dec[3] = dec[4] = dec[5] = 1.0;
-    a.a_bu = (float)dec[0];
-    a.g_bu = (float)g[0];
-    a.a_u = (float)dec[2];
-    a.g_u = (float)g[2];
-    a.a_w = (float)dec[4];
-    a.a_c = (float)dec[5];
-    a.g_w = (float)g[4];
-    a.g_c = (float)g[5];
-    a.inv_aw = (float)(1.0 / dec[4]);
-    a.inv_ac = (float)(1.0 / dec[5]);
-    for (int t = 0; t <= 8; ++t) {
-        a.pav[t] = (float)std::pow(dec[3], t);
-        a.pab[t] = (float)std::pow(dec[1], t);
-    }
-    for (int t = 0; t < 8; ++t) {
-        a.pvi[t] = (float)(g[3] * std::pow(dec[3], -(t + 1)));
-        a.gvp[t] = (float)(g[3] * std::pow(dec[3], t));
-        a.gbp[t] = (float)(g[1] * std::pow(dec[1], t));
-    }
+    // plain MF (Alg. CUSGD++'s model, rhat = u . v): no biases to learn; with
+    // zero rates the bias updates leave b and bh exactly at their zero start
+    if (d.model == LSHMF_PLAIN_MF) a.g[0] = a.g[1] = 0.0f;
     const int fp = (d.F + kWave - 1) / kWave;
     for (int stratum = 0; stratum < c->P; ++stratum) {
         a.s = stratum;

@@ -456,3 +456,24 @@ def poisson_arrivals(n: int, rate: float, seed: int = MASTER_SEED) -> np.ndarray
     """Arrival times (s) of a Poisson process of the given rate (requests / s)."""
     rng = _rng(seed, 41)
     return np.cumsum(rng.exponential(1.0 / rate, n))
+
+
+def twin_items(u: np.ndarray, it: np.ndarray, rc: np.ndarray, N: int, n_pairs: int,
+               seed: int = MASTER_SEED) -> Tuple[np.ndarray, np.ndarray, np.ndarray, np.ndarray]:
+    """Training ratings in which n_pairs items are twins of others: item b's
+    ratings are replaced by a copy of item a's (same users, same codes), so
+    a and b have equal rating columns.  Returns (u, it, rc, pairs [n, 2]),
+    rows of the ratings sorted by (item, user).  An input transform for
+    tests that need colliding items at any hash width."""
+    rng = _rng(seed, 31)
+    ids = rng.permutation(N)[: 2 * n_pairs].reshape(n_pairs, 2).astype(np.int32)
+    a, b = ids[:, 0], ids[:, 1]
+    keep = ~np.isin(it, b)
+    src = np.isin(it, a)
+    to = np.zeros(N, np.int32)
+    to[a] = b
+    u2 = np.concatenate([u[keep], u[src]])
+    i2 = np.concatenate([it[keep], to[it[src]]])
+    r2 = np.concatenate([rc[keep], rc[src]])
+    order = np.lexsort((u2, i2))
+    return (u2[order].astype(np.int32), i2[order].astype(np.int32), r2[order].astype(np.uint8), ids)

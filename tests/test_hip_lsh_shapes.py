@@ -63,6 +63,8 @@ SHAPES = ["small_p2", "small_p7", "small_p3q100", "ml100k_p3q100", "nfsmall_p3q1
 def test_hash_state_signatures_and_lists_bit_exact(name):
     w = synth.WORKLOADS[name]
     d = synth.generate(w)
+    u, it, rc, twins = synth.twin_items(d["train_u"], d["train_i"], d["train_rc"], w.N, max(4, w.N // 40))
+    d = dict(d, train_u=u, train_i=it, train_rc=rc)
     R = synth.family_rand(w)
     _say("[gpu] hash shape %s: family %d, G=%d p=%d q=%d (B=%d)" % (name, w.family, w.G, w.p, w.q, w.B))
     m = build_gpu(w, d, R)
@@ -79,5 +81,8 @@ def test_hash_state_signatures_and_lists_bit_exact(name):
     # the lists are not just the random supplement: most slots come from collisions
     keys = orc.band_keys(sig, w.B, w.G, w.p, w.q)
     hits = sum(int((orc.pair_counts(keys, j)[JK[j]] > 0).sum()) for j in range(0, w.N, max(1, w.N // 50)))
-    _say("[gpu] %s: %d colliding slots in the sampled lists" % (name, hits))
+    paired = sum(int(b in JK[a]) + int(a in JK[b]) for a, b in twins)
+    _say("[gpu] %s: %d colliding slots in the sampled lists, %d of %d twin slots"
+         % (name, hits, paired, 2 * len(twins)))
     assert hits > 0
+    assert paired >= len(twins)
