@@ -308,6 +308,22 @@ int lshmf_sync_storage(lshmf_ctx* ctx, lshmf_stream_t stream);
 int lshmf_rmse(lshmf_ctx* ctx, const float* d_pred, const uint8_t* d_rc, int64_t n,
                double* d_out, lshmf_stream_t stream);
 
+/* lshmf_rmse for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): no
+ * context and no arena.  Same arguments and result as lshmf_rmse, with the
+ * rating scale passed directly (rscale 1 or 2); the value is bit-identical
+ * to lshmf_rmse's.  Its FP64 partial sums live in a fixed 4 KiB device array
+ * of the library (512 partials, whatever n), one per GPU, held until the
+ * process ends; the first call on a device looks up that device's copy.
+ * It calls no allocating routine.  Calls on one GPU share the array:
+ * calls that overlap in time on the same GPU (different streams, or
+ * different host threads) race and may return wrong values; calls ordered on
+ * one stream do not.  The stream must belong to the current device.
+ * LSHMF_EINVAL for a NULL d_out, n < 0, NULL data with n > 0 or another
+ * rscale. */
+int lshmf_rmse_noalloc(const float* d_pred, const uint8_t* d_rc, int64_t n, int32_t rscale,
+                       double* d_out, lshmf_stream_t stream);
+
 /* Phase timing of build_lsh_neighbours (diagnostics).  While enabled, the
  * call records HIP events at its phase boundaries on its stream (the events
  * are created here; nothing else changes).  lshmf_lsh_phase_ms waits for the

@@ -109,6 +109,7 @@ def lib():
                                         i32, i32, C.c_uint32, vp]
             L.predict.argtypes = [vp, vp, vp, i64, vp, vp]
             L.lshmf_rmse.argtypes = [vp, vp, vp, i64, vp, vp]
+            L.lshmf_rmse_noalloc.argtypes = [vp, vp, i64, i32, vp, vp]
             L.lshmf_export_layout.argtypes = [vp, C.POINTER(Layout)]
             L.lshmf_sync_storage.argtypes = [vp, vp]
             L.lshmf_serve_stage_bytes.argtypes = [vp, i64, C.POINTER(C.c_size_t)]
@@ -137,6 +138,16 @@ def header_functions() -> Sequence[str]:
     import re
     src = open(HEADER).read()
     return re.findall(r"^\s*(?:int|void|const char\*)\s+([a-z_][a-z0-9_]*)\s*\(", src, re.M)
+
+
+def rmse_noalloc(pred: torch.Tensor, rc: torch.Tensor, rscale: int, out: torch.Tensor):
+    """lshmf_rmse_noalloc: the RMSE of predictions against rating codes into
+    out[0] (FP64), with no context and no allocation by the library."""
+    assert pred.dtype == torch.float32 and rc.dtype == torch.uint8 and out.dtype == torch.float64
+    assert pred.numel() == rc.numel() and out.numel() >= 1
+    _check(lib().lshmf_rmse_noalloc(_ptr(pred), _ptr(rc), pred.numel(), rscale, _ptr(out),
+                                    _stream(out.device)))
+    return out
 
 
 class LshMF:
