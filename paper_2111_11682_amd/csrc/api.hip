@@ -49,6 +49,7 @@ void carve_stream(Carver& k, Stream& st, int64_t cap, int64_t P, int nstride)
     st.seg_col = k.take<int32_t>(cap);
     st.seg_start = k.take<int64_t>(cap + 1);
     st.blk_slots = k.take<int32_t>(P * P);
+    st.blk_order = k.take<int32_t>(P * P);
     st.stats = k.take<int64_t>(4);
 }
 
@@ -100,7 +101,7 @@ size_t carve(lshmf_ctx* c, char* base)
     c->trash = k.take<float>(1024);
     const int64_t cn = max3(max3(2 * Mc, 2 * Nc, P * P), max3(nz, nq, bc), 4);
     c->cnt = k.take<int64_t>(cn + 2);
-    c->sort_n = max3(max3(nz, nq, bc), Nc, Mc) + 2;
+    c->sort_n = max3(max3(nz, nq, bc), max3(Nc, Mc, P * P), 0) + 2;
     c->sk[0] = k.take<uint64_t>(c->sort_n);
     c->sk[1] = k.take<uint64_t>(c->sort_n);
     c->sv[0] = k.take<uint32_t>(c->sort_n);

@@ -98,6 +98,7 @@ struct Stream {
     int32_t* seg_col;          // cap               item of each run
     int64_t* seg_start;        // cap + 1
     int32_t* blk_slots;        // P*P               mailbox slots per block
+    int32_t* blk_order;        // P*P               dispatch order of each stratum's blocks: most ratings first
     int64_t n = 0;             // host copies after a build
     int64_t max_block_nnz = 0;
     int64_t max_block_slots = 0;

@@ -216,6 +216,20 @@ __global__ void k_dep_fill(const uint64_t* keys, const uint32_t* pos, int64_t n,
 }
 
 // mailbox slots used by each block
+// Dispatch order of the blocks of each stratum: key (stratum, ratings desc,
+// block id asc), so that a stratum's heaviest blocks start first.
+__global__ void k_keys_blkorder(const int64_t* blk_ptr, int64_t P, int pb, uint64_t* keys, uint32_t* vals)
+{
+    for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < P * P;
+         x += (int64_t)gridDim.x * blockDim.x) {
+        const uint64_t st = (uint64_t)(x / P), b = (uint64_t)(x % P);
+        const int64_t nnz = blk_ptr[x + 1] - blk_ptr[x];
+        const uint64_t wgt = nnz > 0xFFFFFFFFLL ? 0xFFFFFFFFull : (uint64_t)nnz;
+        keys[x] = (st << (32 + pb)) | ((0xFFFFFFFFull - wgt) << pb) | b;
+        vals[x] = (uint32_t)b;
+    }
+}
+
 __global__ void k_block_slots(const int64_t* blk_ptr, const int64_t* ex, int64_t nblk, int32_t* out)
 {
     for (int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; b < nblk;
@@ -585,6 +599,16 @@ int build_stream_async(lshmf_ctx* c, Stream& st, const int32_t* u, const int32_t
     hipLaunchKernelGGL(k_block_slots, dim3(grid_for(P * P)), dim3(256), 0, s, st.blk_ptr, chain, P * P,
                        st.blk_slots);
     LSHMF_LAUNCHED("k_block_slots");
+    // blocks of each stratum, heaviest first (the order blocks are dispatched in)
+    {
+        const int pb = bits_for((uint64_t)P);
+        hipLaunchKernelGGL(k_keys_blkorder, dim3(grid_for(P * P)), dim3(256), 0, s, st.blk_ptr, P, pb, c->sk[0],
+                           c->sv[0]);
+        LSHMF_LAUNCHED("k_keys_blkorder");
+        int ro = 0;
+        LSHMF_TRY(radix_sort(c->sk, c->sv, P * P, pb + 32 + pb, c->hist, c->scan_tmp, s, &ro));
+        LSHMF_HIP(hipMemcpyAsync(st.blk_order, c->sv[ro], sizeof(int32_t) * P * P, hipMemcpyDeviceToDevice, s));
+    }
     // zero tails: the SGD kernel reads a few records past a run's end
     LSHMF_TRY(fill_i32(reinterpret_cast<int32_t*>(st.pk) + n, kStreamPad, 0, s));
     LSHMF_TRY(fill_i32(reinterpret_cast<int32_t*>(st.link) + n, kStreamPad, 0, s));

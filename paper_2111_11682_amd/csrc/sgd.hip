@@ -44,6 +44,7 @@ struct SgdArgs {
     const uint8_t* nib;
     const int64_t* blk_ptr;
     const int64_t* blk_seg;
+    const int32_t* blk_order;  // P*P: block run by each workgroup of a stratum
     const int32_t* seg_col;
     const int64_t* seg_start;
     const float* nbr_b0;
@@ -100,7 +101,7 @@ __global__ __launch_bounds__(kSgdWaves* kWave) void k_sgd_stratum(SgdArgs a, con
     float* mb_b = smem + (size_t)(dummy + 1) * F;
     int* mb_seq = reinterpret_cast<int*>(mb_b + dummy + 1);
     const int lane = threadIdx.x & (kWave - 1);
-    const int64_t blk = (int64_t)a.s * a.P + blockIdx.x;
+    const int64_t blk = (int64_t)a.s * a.P + a.blk_order[(int64_t)a.s * a.P + blockIdx.x];
     const int64_t g0 = a.blk_seg[blk], g1 = a.blk_seg[blk + 1];
     const int nsegs = (int)(g1 - g0);
     // The first segments of the block, while long, each get a gang: an item
@@ -756,6 +757,7 @@ int run_sgd(lshmf_ctx* c, Stream& st, const lshmf_hparams* hp, int epoch, int up
     a.nib = c->nstride > 0 ? st.nib : reinterpret_cast<const uint8_t*>(c->trash);
     a.blk_ptr = st.blk_ptr;
     a.blk_seg = st.blk_seg;
+    a.blk_order = st.blk_order;
     a.seg_col = st.seg_col;
     a.seg_start = st.seg_start;
     a.nbr_b0 = c->nbr_b0;
