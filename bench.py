@@ -139,32 +139,36 @@ def cpu_baseline(w, d, P, stride=16, target_s=8.0):
                       % (P, stride, SHAPE_NAMES.get(w.name, w.name), Ms, u.size, nN, tN, all_threads, n1, t1)}
 
 
-def serve_runs(w, d, storage, loads=(0.3, 0.6, 0.9), log_fn=log):
+def serve_runs(w, d, storage, loads=(0.3, 0.6, 0.9), logs=6, log_fn=log):
     """Serving loop on the online split of the workload: pre-train on 80%,
     stream the rest as update batches (log-uniform 1k-1M ratings) mixed 1:4
     with query requests (log-uniform 1-10k pairs); back to back, then Poisson
-    arrivals at fractions of the capacity measured back to back."""
+    arrivals at fractions of the capacity measured back to back.  `logs`
+    request logs (seeded cuts of the same stream into batches) are replayed
+    at every setting and their latencies pooled, so that the percentiles
+    rest on a few hundred requests."""
     import numpy as np
     import torch
     from paper_2111_11682_amd import lshmf, synth
 
     sp = synth.online_split(w, d, frac_new=0.01, stream_frac=0.2)
-    L = synth.serve_log(sp, w.M, w.N, 1000, 1000000, 1, 10000)
-    req = L["req"]
+    Ls = [synth.serve_log(sp, w.M, w.N, 1000, 1000000, 1, 10000, seed=synth.MASTER_SEED + k) for k in range(logs)]
     M0, N0 = int(sp["M_old"]), int(sp["N_old"])
     dev = torch.device("cuda:0")
     pin = lambda a: torch.from_numpy(a).pin_memory()
-    upd = (pin(L["upd_u"]), pin(L["upd_i"]), pin(L["upd_rc"]))
-    qry = (pin(L["q_u"]), pin(L["q_i"]))
     U0 = torch.from_numpy(d["U0"]).to(dev)
     V0 = torch.from_numpy(d["V0"]).to(dev)
     H = torch.from_numpy(d["H"].view(np.int32)).to(dev)
     pre = [torch.from_numpy(sp[k]).to(dev) for k in ("pretrain_u", "pretrain_i", "pretrain_rc")]
-    batch_cap = int(req["n"][req["kind"] == 0].max())
-    log_fn("serve: %d requests (%d updates, %d update ratings, %d query pairs), batch_cap %d" %
-           (req.size, int((req["kind"] == 0).sum()), L["upd_u"].size, L["q_u"].size, batch_cap))
+    batch_cap = max(int(L["req"]["n"][L["req"]["kind"] == 0].max()) for L in Ls)
+    n_req = sum(L["req"].size for L in Ls)
+    log_fn("serve: %d logs, %d requests (%d updates), batch_cap %d" %
+           (logs, n_req, sum(int((L["req"]["kind"] == 0).sum()) for L in Ls), batch_cap))
 
-    def run(arrival):
+    def run(L, arrival):
+        req = L["req"]
+        upd = (pin(L["upd_u"]), pin(L["upd_i"]), pin(L["upd_rc"]))
+        qry = (pin(L["q_u"]), pin(L["q_i"]))
         m = lshmf.LshMF(M0, N0, w.F, w.K, w.G, w.p, w.q, w.rscale, pre[0].numel(), n_strata=w.n_strata,
                         device=dev, M_cap=w.M, N_cap=w.N, nnz_cap=d["train_u"].size,
                         batch_cap=batch_cap, storage=storage)
@@ -182,34 +186,47 @@ def serve_runs(w, d, storage, loads=(0.3, 0.6, 0.9), log_fn=log):
         m.close()
         return start, done, status
 
-    def summary(arrival, start, done, status):
+    def pooled(results):
+        """results: [(L, arrival, start, done, status)] -> latency summary."""
         out = {}
         for kind, name in ((1, "query"), (0, "update")):
-            sel = (req["kind"] == kind) & (status == 0)
-            lat = (done - arrival)[sel] * 1e3
+            lat = []
+            for L, arr, start, done, status in results:
+                sel = (L["req"]["kind"] == kind) & (status == 0)
+                lat.append((done - arr)[sel] * 1e3)
+            lat = np.concatenate(lat)
             out[name + "_p50_ms"] = round(float(np.percentile(lat, 50)), 3)
             out[name + "_p99_ms"] = round(float(np.percentile(lat, 99)), 3)
-        out["refused"] = int((status != 0).sum())
+            out[name + "_count"] = int(lat.size)
+        out["refused"] = int(sum(int((st != 0).sum()) for _, _, _, _, st in results))
         return out
 
-    zero = np.zeros(req.size)
-    start, done, status = run(zero)
-    makespan = float(done.max())
-    capacity = req.size / makespan
-    upd_sel = (req["kind"] == 0) & (status == 0)
-    upd_time = float(np.sum(done[upd_sel] - start[upd_sel]))
-    online_rate = float(np.sum(req["n"][upd_sel])) / upd_time if upd_time > 0 else 0.0
+    b2b, makespan, upd_time, upd_n = [], 0.0, 0.0, 0
+    for L in Ls:
+        zero = np.zeros(L["req"].size)
+        start, done, status = run(L, zero)
+        b2b.append((L, zero, start, done, status))
+        makespan += float(done.max())
+        sel = (L["req"]["kind"] == 0) & (status == 0)
+        upd_time += float(np.sum(done[sel] - start[sel]))
+        upd_n += int(np.sum(L["req"]["n"][sel]))
+    capacity = n_req / makespan
+    online_rate = upd_n / upd_time if upd_time > 0 else 0.0
     log_fn("back to back: %.3f s for %d requests (%.1f requests/s), online %.0f rating updates/s"
-           % (makespan, req.size, capacity, online_rate))
-    res = {"back_to_back": dict(summary(zero, start, done, status), makespan_s=round(makespan, 4))}
+           % (makespan, n_req, capacity, online_rate))
+    res = {"back_to_back": dict(pooled(b2b), makespan_s=round(makespan, 4))}
     for rho in loads:
-        arr = synth.poisson_arrivals(req.size, rho * capacity)
-        start, done, status = run(arr)
-        res["load_%.1f" % rho] = summary(arr, start, done, status)
+        rs = []
+        for k, L in enumerate(Ls):
+            arr = synth.poisson_arrivals(L["req"].size, rho * capacity, seed=synth.MASTER_SEED + 100 * k + 1)
+            start, done, status = run(L, arr)
+            rs.append((L, arr, start, done, status))
+        res["load_%.1f" % rho] = pooled(rs)
         log_fn("load %.1f: %s" % (rho, res["load_%.1f" % rho]))
-    return {"workload": "%s-shaped online stream (1%% new users and items, 20%% of ratings streamed)"
-                        % SHAPE_NAMES.get(w.name, w.name),
-            "requests": int(req.size), "update_ratings": int(L["upd_u"].size), "query_pairs": int(L["q_u"].size),
+    return {"workload": "%s-shaped online stream (1%% new users and items, 20%% of ratings streamed, %d seeded "
+                        "request logs)" % (SHAPE_NAMES.get(w.name, w.name), logs),
+            "requests": int(n_req), "update_ratings": int(sum(L["upd_u"].size for L in Ls)),
+            "query_pairs": int(sum(L["q_u"].size for L in Ls)),
             "storage": storage, "capacity_requests_per_s": round(capacity, 2),
             "online_updates_per_s": round(online_rate, 1), "loads": res}
 
