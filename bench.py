@@ -328,11 +328,15 @@ def main():
         lsh_main(args, w, d)
         return
     g = {k: torch.from_numpy(v).to(dev) for k, v in d.items() if k != "H"}
-    H = torch.from_numpy(d["H"].view(np.int32)).to(dev)
+    if w.family == 0:
+        H = torch.from_numpy(d["H"].view(np.int32)).to(dev)
+    else:  # the draws of the RP_cos / minHash families
+        R = synth.family_rand(w)
+        H = torch.from_numpy(R.view(np.int32) if R.dtype == np.uint32 else R).to(dev)
     nnz = d["train_u"].size
     P = w.n_strata
     m = lshmf.LshMF(w.M, w.N, w.F, w.K, w.G, w.p, w.q, w.rscale, nnz, n_strata=P, device=dev,
-                    storage=args.storage)
+                    storage=args.storage, hash_family=w.family, model=w.model)
     m.set_timing(True)
     pred = torch.empty(d["test_u"].size, dtype=torch.float32, device=dev)
     rmse = torch.empty(1, dtype=torch.float64, device=dev)
@@ -410,6 +414,7 @@ def main():
     value = epochs * nnz / (ms / 1e3)
     out = {
         "metric": ("rating SGD updates/sec (K-neighbour term incl.)" if w.K > 0
+                   else "rating SGD updates/sec (plain MF, CUSGD++ model)" if w.model == 1
                    else "rating SGD updates/sec (biased MF, K = 0)"),
         "value": round(value, 1),
         "unit": "updates/s",

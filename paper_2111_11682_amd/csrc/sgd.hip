@@ -62,7 +62,7 @@ struct SgdArgs {
     int upd;          // bit 0: update the user side {b_i, u_i}; bit 1: the item side {bh_j, v_j, w_j, c_j}
     int max_gangs;    // gangs the LDS holds (0: every segment is run by a single wave)
     int ring_off;     // float offset of the gang rings in dynamic LDS
-    int ring_rs;      // floats per ring slot: u (F), rw (K), cn (K)
+    int ring_rs;      // floats per ring slot: u (64 FP), rw (64 KP), cn (64 KP), zero-padded
     float inv_s;
     float g[6], l[6];
 };
@@ -186,25 +186,19 @@ __global__ __launch_bounds__(kSgdWaves* kWave) void k_sgd_stratum(SgdArgs a, con
             float pu[kIG][FP], prw[kIG][KP], pcn[kIG][KP];
             float preff = 0.0f, pbi = 0.0f;  // lane t: r - mu - b_i and b_i of rating gs + t
             int pi = 0, plw = 0;               // lane t: user and hand-over word of rating gs + t
-            // The slot reads are unconditional and the lanes past F (or K)
-            // drop what they read: the next section of the slot, or past the
-            // last slot the ring headers, all inside the gang's LDS area.
+            // Slot sections are whole multiples of 64 floats, zero past F and
+            // K, so every lane loads straight into its register (no selects:
+            // the loads of a group issue back to back).
             auto load_group = [&](int gs, int cnt) {
 #pragma unroll
                 for (int t = 0; t < kIG; ++t) {
-                    const float* d = rdata + ((gs + t) % kRing) * RS;
+                    const float* d = rdata + ((gs + t) % kRing) * RS + lane;
 #pragma unroll
-                    for (int x = 0; x < FP; ++x) {
-                        const int f = lane + x * kWave;
-                        const float uv = d[f];
-                        pu[t][x] = f < F ? uv : 0.0f;
-                    }
+                    for (int x = 0; x < FP; ++x) pu[t][x] = d[x * kWave];
 #pragma unroll
                     for (int y = 0; y < KP; ++y) {
-                        const int k = lane + y * kWave;
-                        const float rv = d[F + k], cv = d[F + K + k];
-                        prw[t][y] = k < K ? rv : 0.0f;
-                        pcn[t][y] = k < K ? cv : 0.0f;
+                        prw[t][y] = d[(FP + y) * kWave];
+                        pcn[t][y] = d[(FP + KP + y) * kWave];
                     }
                 }
                 const int* hd = rhdr + ((gs + (lane < cnt ? lane : 0)) % kRing) * 4;
@@ -419,20 +413,16 @@ __global__ __launch_bounds__(kSgdWaves* kWave) void k_sgd_stratum(SgdArgs a, con
                     }
                     const float sR = nR > 0 ? __builtin_amdgcn_rsqf((float)nR) : 0.0f;
                     const float sN = K - nR > 0 ? __builtin_amdgcn_rsqf((float)(K - nR)) : 0.0f;
-                    float* d = rdata + sl * RS;
+                    // u (zero past F), then rw and cn (zero past K), 64 floats a section
+                    float* d = rdata + sl * RS + lane;
 #pragma unroll
-                    for (int x = 0; x < FP; ++x) {
-                        const int f = lane + x * kWave;
-                        if (f < F) d[f] = u[x];
-                    }
+                    for (int x = 0; x < FP; ++x) d[x * kWave] = u[x];
 #pragma unroll
                     for (int y = 0; y < KP; ++y) {
                         const int k = lane + y * kWave;
                         const float resid = (float)code[y] * inv_s - base_i - bhn[y];
-                        if (k < K) {
-                            d[F + k] = code[y] ? resid * sR : 0.0f;
-                            d[F + K + k] = code[y] ? 0.0f : sN;
-                        }
+                        d[(FP + y) * kWave] = code[y] ? resid * sR : 0.0f;
+                        d[(FP + KP + y) * kWave] = (k < K && !code[y]) ? sN : 0.0f;
                     }
                     const float r = (float)(pw & 15u) * inv_s;
                     if (lane == 0) {
@@ -703,6 +693,11 @@ __global__ __launch_bounds__(kSgdWaves* kWave) void k_sgd_stratum(SgdArgs a, con
     }
 }
 
+// Lane passes over F features and K neighbour slots, as the kernel
+// instantiations take them (K = 0 runs with one pass of zero slots).
+static int fp_of(int F) { return (F + kWave - 1) / kWave; }
+static int kp_of(int K) { return K > kWave ? 2 : 1; }
+
 // Dynamic LDS of one block: the mailbox (slots + 1 rows of F floats, b_i and
 // a sequence word) and the gang rings.
 static size_t sgd_lds_bytes(const SgdArgs& args)
@@ -780,7 +775,7 @@ int run_sgd(lshmf_ctx* c, Stream& st, const lshmf_hparams* hp, int epoch, int up
     a.inv_s = 1.0f / (float)d.rscale;
     // gangs only where their rings fit beside the mailbox
     a.ring_off = (int)(((st.max_block_slots + 1) * (d.F + 2) + 3) & ~3LL);
-    a.ring_rs = d.F + 2 * d.K;
+    a.ring_rs = kWave * (fp_of(d.F) + 2 * kp_of(d.K));
     a.max_gangs = kMaxGangs;
     while (a.max_gangs > 0 && sgd_lds_bytes(a) > (size_t)kMaxLdsBytes) --a.max_gangs;
     // Eq. (learn_rate): gamma_t = alpha / (1 + beta * t^1.5)

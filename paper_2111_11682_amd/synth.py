@@ -60,6 +60,7 @@ class Workload:
     beta: float                # learning-rate decay, Eq. learn_rate
     n_strata: int = 256
     family: int = 0            # hash family: 0 simLSH, 1 RP_cos, 2 minHash
+    model: int = 0             # 0 neighbourhood model (Eq. rr), 1 plain MF (Alg. CUSGD++, K = 0)
 
     @property
     def B(self) -> int:
@@ -135,6 +136,11 @@ _SHAPES = {
     "ml100k_minhash_p3": ("ml100k", dict(family=2, p=3, q=16)),
     "ml10m_rpcos": ("ml10m", dict(family=1)),
     "ml10m_minhash": ("ml10m", dict(family=2)),
+    "ml100k_rpcos": ("ml100k", dict(family=1)),
+    "ml100k_minhash": ("ml100k", dict(family=2)),
+    "netflix_p3q200": ("netflix", dict(p=3, q=200)),
+    "netflix_rpcos": ("netflix", dict(family=1)),
+    "netflix_minhash": ("netflix", dict(family=2)),
 }
 for _name, (_base, _kw) in _SHAPES.items():
     WORKLOADS[_name] = dataclasses.replace(WORKLOADS[_base], name=_name, **_kw)
@@ -477,3 +483,15 @@ def twin_items(u: np.ndarray, it: np.ndarray, rc: np.ndarray, N: int, n_pairs: i
     r2 = np.concatenate([rc[keep], rc[src]])
     order = np.lexsort((u2, i2))
     return (u2[order].astype(np.int32), i2[order].astype(np.int32), r2[order].astype(np.uint8), ids)
+
+
+# CULSH-MF against CUSGD++ (Sec. 5.3 comparison at F = 32, 64, 128): the
+# neighbourhood model with K = 32 and plain MF (u . v only, K = 0) on the same
+# data and learning rates.
+for _base in ("ml10m", "netflix"):
+    for _F in (32, 64, 128):
+        WORKLOADS["%s_f%d_k32" % (_base, _F)] = dataclasses.replace(WORKLOADS[_base], name="%s_f%d_k32" % (_base, _F),
+                                                                    F=_F, K=32)
+        WORKLOADS["%s_f%d_cusgd" % (_base, _F)] = dataclasses.replace(WORKLOADS[_base],
+                                                                      name="%s_f%d_cusgd" % (_base, _F), F=_F, K=0,
+                                                                      model=1)
