@@ -38,7 +38,7 @@ def log(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
 
 
-def sgd_bytes_per_epoch(nnz, nseg, F, K, nstride):
+def sgd_bytes_per_epoch(nnz, nseg, F, K, nstride, u_bytes=4):
     """Algorithmic HBM bytes of one epoch of k_sgd_stratum.
 
     Per rating: packed (user, code) 4 + hand-over word 4 + neighbour codes
@@ -46,9 +46,10 @@ def sgd_bytes_per_epoch(nnz, nseg, F, K, nstride):
     b0_i 4.  Per item segment (a run of one item inside a block): v_j read and
     write 8F, bh_j read and write 8, w_j and c_j read and write 16K, the fixed
     baselines of the K neighbours 4K, segment descriptor 12.  The kernel is
-    the same in both storage modes (BF16 copies are converted after it).
+    the same in storage modes FP32 and BF16 (BF16 copies are converted after
+    it); in mode BF16_U the user row is 2 bytes a feature (u_bytes = 2).
     """
-    per_rating = 4 + 4 + nstride + 8 * F + 8 + 4
+    per_rating = 4 + 4 + nstride + 2 * u_bytes * F + 8 + 4
     per_seg = 8 * F + 8 + 16 * K + 4 * K + 12
     return nnz * per_rating + nseg * per_seg
 
@@ -293,9 +294,9 @@ def main():
     ap.add_argument("--no-serve", action="store_true", help="leave the serving runs out of the training line")
     ap.add_argument("--mode", choices=("train", "serve", "lsh"), default="train",
                     help="serve: the serving loop alone; lsh: the neighbour search alone")
-    ap.add_argument("--storage", choices=("fp32", "bf16"), default=None,
-                    help="bf16: BF16 copies of U, V, W, C beside the FP32 masters "
-                         "(default fp32 for training, bf16 for serving)")
+    ap.add_argument("--storage", choices=("fp32", "bf16", "bf16u"), default=None,
+                    help="bf16: BF16 copies of U, V, W, C beside the FP32 masters; bf16u: user rows "
+                         "stored in BF16 only (default fp32 for training, bf16 for serving)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one plain 1 GiB device copy, the reference for HBM byte counters")
     args = ap.parse_args()
@@ -386,7 +387,7 @@ def main():
 
     lay = m.layout()
     nseg = int(m.arena_view(lay.blk_seg, P * P + 1, torch.int64)[-1].item())
-    epoch_bytes = sgd_bytes_per_epoch(nnz, nseg, w.F, w.K, lay.nstride)
+    epoch_bytes = sgd_bytes_per_epoch(nnz, nseg, w.F, w.K, lay.nstride, 2 if args.storage == "bf16u" else 4)
     launch_bytes = epoch_bytes / P
     launch_s = sgd_ms_epoch / 1e3 / P
     achieved = launch_bytes / launch_s / 1e9
@@ -425,7 +426,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f32" if args.storage != "bf16u" else "f32 (BF16 user rows)",
         "data": "synthetic (seeded Zipf/lognormal ratings with planted structure, %s shape)"
                 % SHAPE_NAMES.get(w.name.split("_")[0], w.name),
         "config": {"workload": "%s-shaped LSH-MF training job (ingest, simLSH top-K, %d SGD epochs, held-out "

@@ -41,7 +41,14 @@ enum {
     LSHMF_EDEVICE = -4    /* a HIP runtime error; message has its string      */
 };
 
-enum { LSHMF_FP32 = 0, LSHMF_BF16 = 1 };
+/* Storage modes.  LSHMF_BF16: FP32 masters of U, V, W, C plus BF16 copies
+ * that predict reads.  LSHMF_BF16_U: the user rows are stored only in BF16
+ * (table U16; U is not used and may be NULL) -- the SGD reads them as BF16,
+ * computes in FP32 and writes them back rounded to nearest even, so each
+ * rating moves 4F bytes of u instead of 8F; V, W, C keep FP32 masters and
+ * BF16 copies as in LSHMF_BF16.  Inside an SGD block a user's row passes
+ * from one rating to the next in FP32. */
+enum { LSHMF_FP32 = 0, LSHMF_BF16 = 1, LSHMF_BF16_U = 2 };
 
 /* Hash families of the neighbour search (Sec. 4.1 simLSH; RP_cos and minHash
  * are the two other LSH families of the top-K comparison in Sec. 5.3). */
@@ -67,8 +74,9 @@ typedef struct lshmf_dims {
     int32_t rscale;    /* rating code scale, 1 or 2                          */
     int32_t psi_exp;   /* Psi(r) = rc^psi_exp in the hash sums (2: Psi = r^2) */
     int32_t n_strata;  /* P: users and items split into P blocks by id mod P */
-    int32_t storage;   /* LSHMF_FP32, or LSHMF_BF16: BF16 copies of U, V, W, C
-                          for serving next to the FP32 masters              */
+    int32_t storage;   /* LSHMF_FP32; LSHMF_BF16: BF16 copies of U, V, W, C
+                          for serving next to the FP32 masters; LSHMF_BF16_U:
+                          U stored in BF16 only (see the storage modes)     */
     int32_t hash_family; /* LSHMF_SIMLSH, LSHMF_RPCOS or LSHMF_MINHASH       */
     int32_t model;     /* LSHMF_NEIGHBOURHOOD or LSHMF_PLAIN_MF              */
     int32_t reserved;  /* 0                                                  */
@@ -113,7 +121,8 @@ typedef struct lshmf_hparams {
  * master row also rewrites its BF16 copy before it returns (one conversion
  * pass over the tables after the SGD); predict reads the copies.  The
  * pointers are ignored in mode LSHMF_FP32.  With K = 0, W, C, JK, W16 and C16
- * hold nothing and may be NULL. */
+ * hold nothing and may be NULL.  In mode LSHMF_BF16_U, U16 is the only copy of
+ * the user rows (the caller initialises U16; U is ignored and may be NULL). */
 typedef struct lshmf_tables {
     float* U;
     float* V;
@@ -221,7 +230,8 @@ int sgd_epoch(lshmf_ctx* ctx, const lshmf_hparams* hp, int32_t epoch, double* d_
  *     users on existing items update only b_i, u_i; (B) ratings on new items
  *     update only bh_j, v_j, w_j, c_j; (C) the rest update both sides; R(i)
  *     includes the batch.
- * The caller writes U rows [M, M_new) and V rows [N, N_new) before the call;
+ * The caller writes U rows [M, M_new) (U16 rows in mode LSHMF_BF16_U) and V
+ * rows [N, N_new) before the call;
  * the library zeroes bu, bv, W, C of the new ids.  d_H holds M_new rows.
  * The batch joins the training set of later sgd_epoch calls.  Exceeding a
  * capacity, or a batch phase too large for one SGD block (raise n_strata),

@@ -181,8 +181,8 @@ int validate(const lshmf_dims* d)
         set_error("n_strata=%d outside 1..4096", d->n_strata);
         return LSHMF_EINVAL;
     }
-    if (d->storage != LSHMF_FP32 && d->storage != LSHMF_BF16) {
-        set_error("storage=%d is neither LSHMF_FP32 nor LSHMF_BF16", d->storage);
+    if (d->storage != LSHMF_FP32 && d->storage != LSHMF_BF16 && d->storage != LSHMF_BF16_U) {
+        set_error("storage=%d is none of LSHMF_FP32, LSHMF_BF16, LSHMF_BF16_U", d->storage);
         return LSHMF_EINVAL;
     }
     if (d->nnz < 0 || d->nnz >= ((int64_t)1 << 31)) {
@@ -301,13 +301,13 @@ int lshmf_bind(lshmf_ctx* ctx, const lshmf_tables* t, void* d_arena, size_t aren
     }
     // with K = 0 the neighbour tables hold nothing and may be NULL
     const bool nbr = ctx->d.K > 0;
-    if (!t->U || !t->V || !t->bu || !t->bv || (nbr && (!t->W || !t->C || !t->JK)) || !t->acc || !t->sig ||
+    if ((!t->U && ctx->d.storage != LSHMF_BF16_U) || !t->V || !t->bu || !t->bv || (nbr && (!t->W || !t->C || !t->JK)) || !t->acc || !t->sig ||
         !t->b0 || !t->bh0 || !t->mu) {
         set_error("a table pointer is NULL");
         return LSHMF_EINVAL;
     }
-    if (ctx->d.storage == LSHMF_BF16 && (!t->U16 || !t->V16 || (nbr && (!t->W16 || !t->C16)))) {
-        set_error("storage mode BF16 needs the U16, V16, W16 and C16 tables");
+    if (ctx->d.storage != LSHMF_FP32 && (!t->U16 || !t->V16 || (nbr && (!t->W16 || !t->C16)))) {
+        set_error("storage modes BF16 and BF16_U need the U16, V16, W16 and C16 tables");
         return LSHMF_EINVAL;
     }
     if (reinterpret_cast<uintptr_t>(d_arena) & 255) {

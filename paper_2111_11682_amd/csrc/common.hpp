@@ -71,6 +71,9 @@ constexpr int kRmsePartials = 512;
 int rmse_with(const float* pred, const uint8_t* rc, int64_t n, int rscale, double* partial, double* out,
               hipStream_t s);
 
+// BF16 (round to nearest even) of n FP32 values.
+int to_bf16_rows(const float* src, uint16_t* dst, int64_t n, hipStream_t s);
+
 // Fills.
 int fill_i64(int64_t* p, int64_t n, int64_t v, hipStream_t s);
 int fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);

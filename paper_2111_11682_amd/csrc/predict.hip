@@ -46,8 +46,9 @@ __global__ __launch_bounds__(256) void k_bf16_touched(const int64_t* ptr, int64_
 // c->M users) and of the item rows with ratings in it (its CSC col_ptr).
 int refresh_bf16_touched(lshmf_ctx* c, const int64_t* b_rptr, const int64_t* b_cptr, hipStream_t s)
 {
-    if (c->d.storage != LSHMF_BF16) return LSHMF_OK;
-    const int64_t F = c->d.F, K = c->d.K, M = c->M, N = c->N;
+    if (c->d.storage == LSHMF_FP32) return LSHMF_OK;
+    const int64_t F = c->d.F, K = c->d.K, N = c->N;
+    const int64_t M = c->d.storage == LSHMF_BF16_U ? 0 : c->M;  // BF16_U: U16 is the master
     auto grid = [](int64_t rows) {
         int64_t b = ceil_div(rows > 0 ? rows * kWave : 1, 256);
         return (unsigned)(b > 16384 ? 16384 : b);
@@ -71,9 +72,9 @@ int refresh_bf16_touched(lshmf_ctx* c, const int64_t* b_rptr, const int64_t* b_c
 // BF16 copies of the rows [m0, m1) of U and [n0, n1) of V, W, C.
 int refresh_bf16(lshmf_ctx* c, int64_t m0, int64_t m1, int64_t n0, int64_t n1, hipStream_t s)
 {
-    if (c->d.storage != LSHMF_BF16) return LSHMF_OK;
+    if (c->d.storage == LSHMF_FP32) return LSHMF_OK;
     const int64_t F = c->d.F, K = c->d.K;
-    LSHMF_TRY(to_bf16_rows(c->t.U + m0 * F, c->t.U16 + m0 * F, (m1 - m0) * F, s));
+    if (c->d.storage == LSHMF_BF16) LSHMF_TRY(to_bf16_rows(c->t.U + m0 * F, c->t.U16 + m0 * F, (m1 - m0) * F, s));
     LSHMF_TRY(to_bf16_rows(c->t.V + n0 * F, c->t.V16 + n0 * F, (n1 - n0) * F, s));
     LSHMF_TRY(to_bf16_rows(c->t.W + n0 * K, c->t.W16 + n0 * K, (n1 - n0) * K, s));
     return to_bf16_rows(c->t.C + n0 * K, c->t.C16 + n0 * K, (n1 - n0) * K, s);
@@ -188,7 +189,7 @@ int run_predict(lshmf_ctx* c, const int32_t* qu, const int32_t* qi, int64_t n, f
 {
     if (n <= 0) return LSHMF_OK;
     const lshmf_dims& d = c->d;
-    const bool bf = d.storage == LSHMF_BF16;
+    const bool bf = d.storage != LSHMF_FP32;  // BF16 copies (BF16), or BF16 user rows and copies (BF16_U)
     PredArgs a{c->t.JK, c->t.b0, c->t.bh0, c->t.mu,
                bf ? (const void*)c->t.U16 : (const void*)c->t.U, bf ? (const void*)c->t.V16 : (const void*)c->t.V,
                c->t.bu, c->t.bv,
@@ -265,6 +266,7 @@ struct LossArgs {
     const float* b0;
     const double* mu;
     const float* U;
+    const uint16_t* U16;  // storage mode BF16_U: the user rows (U unused), else NULL
     const float* V;
     const float* bu;
     const float* bv;
@@ -314,7 +316,7 @@ __global__ __launch_bounds__(kLossWaves* kWave) void k_loss_sse(LossArgs a, doub
 #pragma unroll
             for (int x = 0; x < FP; ++x) {
                 const int f = lane + x * kWave;
-                if (f < F) part += a.U[i * F + f] * v[x];
+                if (f < F) part += (a.U16 ? from_bf16(a.U16[i * F + f]) : a.U[i * F + f]) * v[x];
             }
             int code[KP];
             int nR = 0;
@@ -349,8 +351,9 @@ __global__ __launch_bounds__(kLossWaves* kWave) void k_loss_sse(LossArgs a, doub
 // Squared norms of the six tables (b, bh, U, V, W, C): block b owns a fixed
 // grid-stride share of each and writes partial[t * blocks + b].
 __global__ __launch_bounds__(256) void k_loss_norms(const float* bu, int64_t nb, const float* bv, int64_t nbh,
-                                                    const float* U, int64_t nu, const float* V, int64_t nv,
-                                                    const float* W, const float* C, int64_t nk, double* partial)
+                                                    const float* U, const uint16_t* U16, int64_t nu, const float* V,
+                                                    int64_t nv, const float* W, const float* C, int64_t nk,
+                                                    double* partial)
 {
     __shared__ double scratch[256 / kWave];
     const float* tab[6] = {bu, bv, U, V, W, C};
@@ -359,7 +362,7 @@ __global__ __launch_bounds__(256) void k_loss_norms(const float* bu, int64_t nb,
         double s = 0.0;
         for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < len[t];
              x += (int64_t)gridDim.x * blockDim.x) {
-            const double v = (double)tab[t][x];
+            const double v = (t == 2 && U16) ? (double)from_bf16(U16[x]) : (double)tab[t][x];
             s += v * v;
         }
         const double tot = block_sum_f64(s, scratch);
@@ -390,8 +393,9 @@ int run_loss(lshmf_ctx* c, const lshmf_hparams* hp, double* out, hipStream_t s)
 {
     const lshmf_dims& d = c->d;
     const Stream& st = c->train;
+    const uint16_t* u16 = d.storage == LSHMF_BF16_U ? c->t.U16 : nullptr;
     LossArgs a{st.pk, c->nstride > 0 ? st.nib : reinterpret_cast<const uint8_t*>(c->trash), st.seg_col,
-               st.seg_start, c->nbr_b0, c->t.b0, c->t.mu, c->t.U, c->t.V, c->t.bu, c->t.bv,
+               st.seg_start, c->nbr_b0, c->t.b0, c->t.mu, c->t.U, u16, c->t.V, c->t.bu, c->t.bv,
                d.K > 0 ? c->t.W : c->trash, d.K > 0 ? c->t.C : c->trash, st.n > 0 ? st.nseg : 0,
                d.F, d.K, c->nstride, 1.0f / (float)d.rscale};
     double* part = c->red;  // [0, B): squared errors; [(t+1)B, (t+2)B): norm t
@@ -410,8 +414,8 @@ int run_loss(lshmf_ctx* c, const lshmf_hparams* hp, double* out, hipStream_t s)
 #undef LSHMF_LOSS
     LSHMF_LAUNCHED("k_loss_sse");
     const int64_t M = c->M, N = c->N, F = d.F, K = d.K;
-    hipLaunchKernelGGL(k_loss_norms, grid, dim3(256), 0, s, c->t.bu, M, c->t.bv, N, c->t.U, M * F, c->t.V, N * F,
-                       a.W, a.C, K > 0 ? N * K : 0, part + kLossBlocks);
+    hipLaunchKernelGGL(k_loss_norms, grid, dim3(256), 0, s, c->t.bu, M, c->t.bv, N, c->t.U, u16, M * F, c->t.V,
+                       N * F, a.W, a.C, K > 0 ? N * K : 0, part + kLossBlocks);
     LSHMF_LAUNCHED("k_loss_norms");
     LossLam lam;
     for (int t = 0; t < 6; ++t) lam.l[t] = hp->lambda[t];

@@ -182,9 +182,16 @@ int lshmf_serve(lshmf_ctx* ctx, const lshmf_serve_io* io, lshmf_stream_t compute
                 if (e == hipSuccess) e = hipEventRecord(up, ps);
                 if (e == hipSuccess) e = hipStreamWaitEvent(cs, up, 0);
                 // initial factor rows of the new ids (Alg. "Online Learning" takes them as input)
-                if (e == hipSuccess && q.M_new > ctx->M)
-                    e = hipMemcpyAsync(ctx->t.U + ctx->M * F, io->d_U0 + ctx->M * F,
-                                       sizeof(float) * F * (q.M_new - ctx->M), hipMemcpyDeviceToDevice, cs);
+                if (e == hipSuccess && q.M_new > ctx->M) {
+                    if (ctx->d.storage == LSHMF_BF16_U) {  // the user rows live in BF16 only
+                        if (to_bf16_rows(io->d_U0 + ctx->M * F, ctx->t.U16 + ctx->M * F, F * (q.M_new - ctx->M), cs) !=
+                            LSHMF_OK)
+                            e = hipErrorLaunchFailure;
+                    } else {
+                        e = hipMemcpyAsync(ctx->t.U + ctx->M * F, io->d_U0 + ctx->M * F,
+                                           sizeof(float) * F * (q.M_new - ctx->M), hipMemcpyDeviceToDevice, cs);
+                    }
+                }
                 if (e == hipSuccess && q.N_new > ctx->N)
                     e = hipMemcpyAsync(ctx->t.V + ctx->N * F, io->d_V0 + ctx->N * F,
                                        sizeof(float) * F * (q.N_new - ctx->N), hipMemcpyDeviceToDevice, cs);

@@ -51,6 +51,7 @@ struct SgdArgs {
     const float* b0;
     const double* mu;
     float* U;
+    uint16_t* U16;    // storage mode BF16_U: the user rows in HBM are BF16 (U unused), else NULL
     float* V;
     float* bu;
     float* bv;
@@ -88,7 +89,7 @@ struct HStage {
     uint32_t pw[kHG], lw[kHG];
 };
 
-template <int FP, int KP>
+template <int FP, int KP, bool UB>
 __global__ __launch_bounds__(kSgdWaves* kWave) void k_sgd_stratum(SgdArgs a, const uint32_t* __restrict__ pk,
                                                                    const uint32_t* __restrict__ link)
 {
@@ -252,8 +253,11 @@ __global__ __launch_bounds__(kSgdWaves* kWave) void k_sgd_stratum(SgdArgs a, con
                     const uint32_t lw = (uint32_t)__builtin_amdgcn_readlane(lw_v, t);
                     const bool has_succ = (lw >> 31) != 0;
                     const int ws = has_succ ? (int)(lw & 0xFFFFu) : dummy;
-                    // wave-uniform destinations: the HBM row or a sink row
-                    float* urow = has_succ ? a.trash + kWave * FP : a.U + i * F;
+                    // wave-uniform destinations: the HBM row or a sink row (FP32,
+                    // or BF16 with round to nearest even in storage mode BF16_U)
+                    float* urow = (has_succ || UB) ? a.trash + kWave * FP : a.U + i * F;
+                    uint16_t* hrow = (!has_succ && UB) ? a.U16 + i * F
+                                                          : reinterpret_cast<uint16_t*>(a.trash + 3 * kWave * FP);
                     float* mrow = mb_u + ws * F;
 #pragma unroll
                     for (int x = 0; x < FP; ++x) {
@@ -261,7 +265,8 @@ __global__ __launch_bounds__(kSgdWaves* kWave) void k_sgd_stratum(SgdArgs a, con
                         const float unew = usr ? u[t][x] + a.g[2] * (err * v[x] - a.l[2] * u[t][x]) : u[t][x];
                         if (f < F) {
                             mrow[f] = unew;
-                            urow[f] = unew;
+                            if constexpr (UB) hrow[f] = to_bf16(unew);
+                            else urow[f] = unew;
                         }
                         const float vn = v[x] + a.g[3] * (err * u[t][x] - a.l[3] * v[x]);
                         v[x] = itm ? vn : v[x];
@@ -342,10 +347,18 @@ __global__ __launch_bounds__(kSgdWaves* kWave) void k_sgd_stratum(SgdArgs a, con
                     S.lw[t] = lw;
                     const int64_t i = valid ? (int64_t)(pw >> 4) : 0;
                     const int64_t pos = valid ? ea + h + (int64_t)kHelpers * (mb + tt) : ea;
+                    if constexpr (UB) {
 #pragma unroll
-                    for (int x = 0; x < FP; ++x) {
-                        const int f = lane + x * kWave;
-                        S.u[t][x] = *(f < F ? a.U + i * F + f : a.trash + lane);
+                        for (int x = 0; x < FP; ++x) {
+                            const int f = lane + x * kWave;
+                            S.u[t][x] = from_bf16(a.U16[f < F ? i * F + f : 0]);
+                        }
+                    } else {
+#pragma unroll
+                        for (int x = 0; x < FP; ++x) {
+                            const int f = lane + x * kWave;
+                            S.u[t][x] = *(f < F ? a.U + i * F + f : a.trash + lane);
+                        }
                     }
                     S.bi[t] = a.bu[i];
                     S.b0[t] = a.b0[i];
@@ -504,11 +517,20 @@ __global__ __launch_bounds__(kSgdWaves* kWave) void k_sgd_stratum(SgdArgs a, con
                 S.lk[sl] = lw;
                 const int64_t i = pw >> 4;
                 // lanes past F read the sink row: every load is issued by all lanes
+                if constexpr (UB) {
 #pragma unroll
-                for (int x = 0; x < FP; ++x) {
-                    const int f = lane + x * kWave;
-                    const float gv = *(f < F ? a.U + i * F + f : a.trash + lane);
-                    S.gu[sl][x] = f < F ? gv : 0.0f;   // lanes past F keep u = 0 (and so v = 0)
+                    for (int x = 0; x < FP; ++x) {
+                        const int f = lane + x * kWave;
+                        const float gv = from_bf16(a.U16[f < F ? i * F + f : 0]);
+                        S.gu[sl][x] = f < F ? gv : 0.0f;
+                    }
+                } else {
+#pragma unroll
+                    for (int x = 0; x < FP; ++x) {
+                        const int f = lane + x * kWave;
+                        const float gv = *(f < F ? a.U + i * F + f : a.trash + lane);
+                        S.gu[sl][x] = f < F ? gv : 0.0f;   // lanes past F keep u = 0 (and so v = 0)
+                    }
                 }
                 S.gbi[sl] = a.bu[i];
                 S.b0[sl] = a.b0[i];
@@ -622,7 +644,12 @@ __global__ __launch_bounds__(kSgdWaves* kWave) void k_sgd_stratum(SgdArgs a, con
                 for (int x = 0; x < FP; ++x) {
                     const int f = lane + x * kWave;
                     const float unew = usr ? u[x] + a.g[2] * (err * v[x] - a.l[2] * u[x]) : u[x];
-                    *((to_hbm && f < F) ? a.U + i * F + f : a.trash + kWave * FP + f) = unew;
+                    if constexpr (UB) {
+                        uint16_t* hs = reinterpret_cast<uint16_t*>(a.trash + 3 * kWave * FP);
+                        *((to_hbm && f < F) ? a.U16 + i * F + f : hs + f) = to_bf16(unew);
+                    } else {
+                        *((to_hbm && f < F) ? a.U + i * F + f : a.trash + kWave * FP + f) = unew;
+                    }
                     mb_u[f < F ? ws * F + f : dummy * F] = unew;
                     const float vn = v[x] + a.g[3] * (err * u[x] - a.l[3] * v[x]);
                     v[x] = (valid && itm) ? vn : v[x];
@@ -706,16 +733,16 @@ static size_t sgd_lds_bytes(const SgdArgs& args)
     return ((size_t)args.ring_off + (size_t)args.max_gangs * gs) * sizeof(float);
 }
 
-template <int FP, int KP>
+template <int FP, int KP, bool UB>
 static int launch_sgd(const SgdArgs& args, const uint32_t* pk, const uint32_t* link, hipStream_t s)
 {
     const size_t lds = sgd_lds_bytes(args);
     if (lds > 64 * 1024) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sgd_stratum<FP, KP>),
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sgd_stratum<FP, KP, UB>),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return hip_fail(e, "hipFuncSetAttribute(k_sgd_stratum)");
     }
-    hipLaunchKernelGGL((k_sgd_stratum<FP, KP>), dim3((unsigned)args.P), dim3(kSgdWaves * kWave), lds, s, args,
+    hipLaunchKernelGGL((k_sgd_stratum<FP, KP, UB>), dim3((unsigned)args.P), dim3(kSgdWaves * kWave), lds, s, args,
                        pk, link);
     LSHMF_LAUNCHED("k_sgd_stratum");
     return LSHMF_OK;
@@ -724,7 +751,9 @@ static int launch_sgd(const SgdArgs& args, const uint32_t* pk, const uint32_t* l
 template <int FP>
 static int launch_sgd_k(const SgdArgs& args, const uint32_t* pk, const uint32_t* link, hipStream_t s)
 {
-    return args.K <= kWave ? launch_sgd<FP, 1>(args, pk, link, s) : launch_sgd<FP, 2>(args, pk, link, s);
+    // storage mode BF16_U has its own instantiation: the FP32 kernels stay as they are
+    if (args.U16) return args.K <= kWave ? launch_sgd<FP, 1, true>(args, pk, link, s) : launch_sgd<FP, 2, true>(args, pk, link, s);
+    return args.K <= kWave ? launch_sgd<FP, 1, false>(args, pk, link, s) : launch_sgd<FP, 2, false>(args, pk, link, s);
 }
 
 // Can k_sgd_stratum run this stream: the mailbox of every block in LDS and
@@ -759,6 +788,7 @@ int run_sgd(lshmf_ctx* c, Stream& st, const lshmf_hparams* hp, int epoch, int up
     a.b0 = c->t.b0;
     a.mu = c->t.mu;
     a.U = c->t.U;
+    a.U16 = d.storage == LSHMF_BF16_U ? c->t.U16 : nullptr;
     a.V = c->t.V;
     a.bu = c->t.bu;
     a.bv = c->t.bv;

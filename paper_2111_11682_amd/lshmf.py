@@ -20,7 +20,8 @@ LIB_PATH = os.environ.get("LSHMF_LIB") or os.path.join(HERE, "liblshmf.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "lshmf.h")
 
 LSHMF_OK = 0
-LSHMF_FP32, LSHMF_BF16 = 0, 1
+LSHMF_FP32, LSHMF_BF16, LSHMF_BF16_U = 0, 1, 2
+STORAGE = {"fp32": LSHMF_FP32, "bf16": LSHMF_BF16, "bf16u": LSHMF_BF16_U}
 SIMLSH, RPCOS, MINHASH = 0, 1, 2
 NEIGHBOURHOOD, PLAIN_MF = 0, 1
 REBUILD_NBRS = 1
@@ -159,15 +160,16 @@ class LshMF:
                  storage: str = "fp32", hash_family: int = SIMLSH, model: int = NEIGHBOURHOOD):
         """Tables are allocated for the capacities (0: the initial M, N, nnz);
         batch_cap > 0 enables online_update batches of up to that many ratings.
-        storage "bf16" adds BF16 copies U16, V16, W16, C16 that predict reads.
+        storage "bf16" adds BF16 copies U16, V16, W16, C16 that predict reads;
+        "bf16u" keeps the user rows only in BF16 (U16; U is not used).
         hash_family: SIMLSH, RPCOS or MINHASH (the neighbour search's hash);
         model: NEIGHBOURHOOD (Eq. rr) or PLAIN_MF (u . v only, K = 0)."""
         self.device = torch.device(device)
-        assert storage in ("fp32", "bf16")
+        assert storage in STORAGE
         self.storage = storage
         self.hash_family = hash_family
         self.dims = Dims(M, N, F, K, G, p, q, rscale, psi_exp, n_strata,
-                         LSHMF_BF16 if storage == "bf16" else LSHMF_FP32, hash_family, model, 0, nnz,
+                         STORAGE[storage], hash_family, model, 0, nnz,
                          M_cap, N_cap, nnz_cap, batch_cap)
         M, N = max(M, M_cap), max(N, N_cap)
         self.B = G * p * q
@@ -195,7 +197,7 @@ class LshMF:
         off = (-self.arena.data_ptr()) % 256
         self._arena_ptr = self.arena.data_ptr() + off
         bf16 = dict(dtype=torch.bfloat16, device=dev)
-        if storage == "bf16":
+        if storage != "fp32":
             self.U16 = torch.zeros(M, F, **bf16)
             self.V16 = torch.zeros(N, F, **bf16)
             self.W16 = torch.zeros(N, K, **bf16)
@@ -225,6 +227,8 @@ class LshMF:
     def set_factors(self, U0: torch.Tensor, V0: torch.Tensor):
         """Initial U, V of the first rows (copied); b, bh, W, C start at zero."""
         self.U[: U0.shape[0]].copy_(U0)
+        if self.storage == "bf16u":  # the user rows live in BF16 only (round to nearest even)
+            self.U16[: U0.shape[0]].copy_(U0.to(torch.bfloat16))
         self.V[: V0.shape[0]].copy_(V0)
         for t in (self.bu, self.bv, self.W, self.C):
             t.zero_()
@@ -299,6 +303,8 @@ class LshMF:
         if lay.M < M_new <= self.U.shape[0]:
             assert U_new is not None and tuple(U_new.shape) == (M_new - lay.M, self.dims.F)
             self.U[lay.M: M_new].copy_(U_new)
+            if self.storage == "bf16u":
+                self.U16[lay.M: M_new].copy_(U_new.to(torch.bfloat16))
         if lay.N < N_new <= self.V.shape[0]:
             assert V_new is not None and tuple(V_new.shape) == (N_new - lay.N, self.dims.F)
             self.V[lay.N: N_new].copy_(V_new)

@@ -35,7 +35,7 @@ def _create(**kw):
                                  dict(G=40, p=1, q=4, hash_family=2), dict(hash_family=3),
                                  dict(model=1), dict(model=2, K=0),
                                  dict(rscale=3),
-                                 dict(psi_exp=0), dict(n_strata=0), dict(storage=2),
+                                 dict(psi_exp=0), dict(n_strata=0), dict(storage=3),
                                  dict(nnz=-1), dict(M=0), dict(N=1), dict(M_cap=900),
                                  dict(N_cap=1000), dict(nnz_cap=100), dict(batch_cap=-1)])
 def test_create_rejects_bad_dims(bad):

@@ -2,10 +2,12 @@
 
 480,189 users x 17,770 items, 98,591,605 training ratings, F = 128, K = 100,
 128 hash bits, in the launch configuration bench.py times (1,536 strata),
-storage mode BF16 (FP32 masters, BF16 copies that predict reads).  Hash sums,
+storage mode BF16 (FP32 masters, BF16 copies that predict reads), then again
+with the user rows stored in BF16 only (storage BF16_U).  Hash sums,
 signatures and neighbour lists bit for bit; one SGD epoch over all ratings
 within 1e-4 element by element (tablecmp.py); held-out RMSE after that epoch,
-predicted from the BF16 copies, within 0.5% of the FP64 oracle's.
+predicted from the BF16 copies, within 0.5% of the FP64 oracle's, in both
+storage modes.
 """
 import sys
 import time
@@ -63,3 +65,15 @@ def test_netflix_shape_neighbours_epoch_and_bf16_rmse():
     r_orc = o.rmse(d["test_u"], d["test_i"], d["test_rc"])
     _say("[gpu] netflix RMSE after one epoch: gpu (BF16 copies) %.6f oracle (FP64) %.6f" % (r_gpu, r_orc))
     assert abs(r_gpu - r_orc) <= 0.005 * r_orc
+    m.close()
+    # the same epoch with the user rows stored in BF16 only (storage BF16_U)
+    m2 = lshmf.LshMF(w.M, w.N, w.F, w.K, w.G, w.p, w.q, w.rscale, d["train_u"].size,
+                     n_strata=w.n_strata, storage="bf16u")
+    m2.ingest(*[torch.from_numpy(d[k]).to(dev) for k in ("train_u", "train_i", "train_rc")])
+    m2.set_factors(torch.from_numpy(d["U0"]).to(dev), torch.from_numpy(d["V0"]).to(dev))
+    m2.build_lsh_neighbours(torch.from_numpy(d["H"].view(np.int32)).to(dev), SEED_FILL)
+    m2.sgd_epoch(w.alpha, w.lam, w.beta, 0)
+    m2.check()
+    r16 = m2.rmse(m2.predict(tu, ti), trc).item()
+    _say("[gpu] netflix RMSE after one epoch, user rows in BF16 only: gpu %.6f oracle (FP64) %.6f" % (r16, r_orc))
+    assert abs(r16 - r_orc) <= 0.005 * r_orc
