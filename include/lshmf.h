@@ -119,7 +119,8 @@ typedef struct lshmf_hparams {
  * BF16 bit patterns (round to nearest even) of the FP32 tables above, which
  * stay the masters that SGD reads and writes.  Every call that changes a
  * master row also rewrites its BF16 copy before it returns (one conversion
- * pass over the tables after the SGD); predict reads the copies.  The
+ * pass over the tables after the SGD); predict reads the copies, and
+ * snapshots of b and bh taken at the same moments (kept in the arena).  The
  * pointers are ignored in mode LSHMF_FP32.  With K = 0, W, C, JK, W16 and C16
  * hold nothing and may be NULL.  In mode LSHMF_BF16_U, U16 is the only copy of
  * the user rows (the caller initialises U16; U is ignored and may be NULL). */
@@ -257,7 +258,17 @@ int online_update(lshmf_ctx* ctx, const int32_t* d_u, const int32_t* d_i, const 
  *     sees exactly the updates that arrived before it, so the answers do not
  *     depend on how requests were merged;
  *   - payload uploads and result downloads run on a copy stream beside the
- *     compute stream, double-buffered in the caller's device staging area.
+ *     compute stream, double-buffered in the caller's device staging area;
+ *   - in storage mode LSHMF_BF16, predict reads only the BF16 copies and the
+ *     bias snapshots, which an update rewrites in its last step: queries then
+ *     run on a stream of their own (created and destroyed by the call, default
+ *     priority) beside the hashing, neighbour and SGD phases of the next
+ *     update, and only that last step waits for the queries that arrived
+ *     before it.  In the other modes queries and updates share the compute
+ *     stream.  Either way a query sees exactly the updates that arrived before
+ *     it, so answers do not depend on the overlap;
+ *   - an update's upload waits until the previous update no longer reads the
+ *     staging.
  * Request times are seconds from the start of the call; the loop waits for
  * arrivals in real time (all zero: back to back).  Host payload arrays
  * should be pinned for the copies to overlap. */

@@ -15,7 +15,7 @@ int stream_codes(lshmf_ctx* c, Stream& st, hipStream_t s);
 int run_sgd(lshmf_ctx* c, Stream& st, const lshmf_hparams* hp, int epoch, int upd, hipStream_t s);
 int run_online(lshmf_ctx* c, const int32_t* u, const int32_t* it, const uint8_t* rc, int64_t n, int32_t M_new,
                int32_t N_new, const void* R, uint64_t seed_fill, const lshmf_hparams* hp, int epoch,
-               int passes, uint32_t flags, hipStream_t s);
+               int passes, uint32_t flags, hipStream_t s, bool refresh = true);
 int run_loss(lshmf_ctx* c, const lshmf_hparams* hp, double* out, hipStream_t s);
 int run_predict(lshmf_ctx* c, const int32_t* qu, const int32_t* qi, int64_t n, float* out, hipStream_t s);
 int run_rmse(lshmf_ctx* c, const float* pred, const uint8_t* rc, int64_t n, double* out, hipStream_t s);
@@ -113,6 +113,8 @@ size_t carve(lshmf_ctx* c, char* base)
     if (scan_n2 > scan_n) scan_n = scan_n2;
     c->scan_tmp = k.take<int64_t>(scan_n);
     c->red = k.take<double>(8192);
+    c->bu_s = k.take<float>(Mc);
+    c->bv_s = k.take<float>(Nc);
     c->nbr_b0 = k.take<float>((size_t)Nc * d.K);
     c->bitem = k.take<int32_t>(nq);
     c->bbegin = k.take<int32_t>(nq + 1);

@@ -74,6 +74,10 @@ int rmse_with(const float* pred, const uint8_t* rc, int64_t n, int rscale, doubl
 // BF16 (round to nearest even) of n FP32 values.
 int to_bf16_rows(const float* src, uint16_t* dst, int64_t n, hipStream_t s);
 
+// BF16 copies (and bias snapshots) of every row after `core` phases of an
+// online batch; see run_online.
+int refresh_after_online(lshmf_ctx* c, int32_t M_old, int32_t N_old, uint32_t flags, hipStream_t s);
+
 // Fills.
 int fill_i64(int64_t* p, int64_t n, int64_t v, hipStream_t s);
 int fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
@@ -179,6 +183,8 @@ struct lshmf_ctx {
     float* old_w;
     float* old_c;
     int32_t* err;              // device status words: [0] SGD waits, [1] input checks
+    float* bu_s;               // M_cap  BF16 modes: snapshot of b that predict reads (refreshed with the copies)
+    float* bv_s;               // N_cap  snapshot of bh
 
     // phase timing of the neighbour search (diagnostics)
     bool timing = false, timed = false;

@@ -142,9 +142,22 @@ static int check_and_layout(lshmf_ctx* c, const int32_t* u, const int32_t* it, c
     return status;
 }
 
+// BF16 copies and bias snapshots after an online batch: every row after a
+// rebuild (w, c moved with their ids), else the rows the SGD changed (the
+// batch's users and items, from the batch's CSR and CSC) and the new ids.
+int refresh_after_online(lshmf_ctx* c, int32_t M_old, int32_t N_old, uint32_t flags, hipStream_t s)
+{
+    if (flags & LSHMF_REBUILD_NBRS) return refresh_bf16(c, 0, c->M, 0, c->N, s);
+    LSHMF_TRY(refresh_bf16_touched(c, c->brow_ptr, c->bcol_ptr, s));
+    return refresh_bf16(c, M_old, c->M, N_old, c->N, s);
+}
+
+// refresh = false leaves the BF16 copies and bias snapshots of the batch's
+// rows to a later refresh_after_online (the serving loop orders it after the
+// queries that must not see the batch).
 int run_online(lshmf_ctx* c, const int32_t* u, const int32_t* it, const uint8_t* rc, int64_t n, int32_t M_new,
                int32_t N_new, const void* R, uint64_t seed_fill, const lshmf_hparams* hp, int epoch,
-               int passes, uint32_t flags, hipStream_t s)
+               int passes, uint32_t flags, hipStream_t s, bool refresh)
 {
     const int32_t M_old = c->M, N_old = c->N;
     const int K = c->d.K;
@@ -194,14 +207,7 @@ int run_online(lshmf_ctx* c, const int32_t* u, const int32_t* it, const uint8_t*
     static const int kUpd[3] = {1, 2, 3};  // user side, item side, both
     for (int p = 0; p < passes; ++p)
         for (int k = 0; k < 3; ++k) LSHMF_TRY(run_sgd(c, c->phase[k], hp, epoch, kUpd[k], s));
-    // BF16 copies: every row after a rebuild (w, c moved with their ids), else
-    // the rows the SGD changed (the batch's users and items) and the new ids
-    if (flags & LSHMF_REBUILD_NBRS) {
-        LSHMF_TRY(refresh_bf16(c, 0, M_new, 0, N_new, s));
-    } else {
-        LSHMF_TRY(refresh_bf16_touched(c, c->brow_ptr, c->bcol_ptr, s));
-        LSHMF_TRY(refresh_bf16(c, M_old, M_new, N_old, N_new, s));
-    }
+    if (refresh) LSHMF_TRY(refresh_after_online(c, M_old, N_old, flags, s));
     c->neighbours = true;
     return LSHMF_OK;
 }

@@ -25,17 +25,37 @@ int to_bf16_rows(const float* src, uint16_t* dst, int64_t n, hipStream_t s)
     return LSHMF_OK;
 }
 
+// Plain copies of n FP32 values (the bias snapshots that predict reads in the
+// BF16 storage modes).
+__global__ void k_copy_f32(const float* src, float* dst, int64_t n)
+{
+    for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < n;
+         x += (int64_t)gridDim.x * blockDim.x)
+        dst[x] = src[x];
+}
+
+static int copy_rows(const float* src, float* dst, int64_t n, hipStream_t s)
+{
+    if (n <= 0) return LSHMF_OK;
+    int64_t b = ceil_div(n, 256);
+    if (b > 16384) b = 16384;
+    hipLaunchKernelGGL(k_copy_f32, dim3((unsigned)b), dim3(256), 0, s, src, dst, n);
+    LSHMF_LAUNCHED("k_copy_f32");
+    return LSHMF_OK;
+}
+
 // BF16 copies of the rows r < n_rows with ptr[r+1] > ptr[r] (the rows a batch
 // touched) of up to two FP32 tables of `width` floats a row; a wave per row.
 __global__ __launch_bounds__(256) void k_bf16_touched(const int64_t* ptr, int64_t n_rows, const float* a,
                                                       uint16_t* a16, int64_t wa, const float* b, uint16_t* b16,
-                                                      int64_t wb)
+                                                      int64_t wb, const float* bias, float* bias_s)
 {
     const int lane = threadIdx.x & (kWave - 1);
     const int64_t w0 = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kWave;
     const int64_t nw = (int64_t)gridDim.x * blockDim.x / kWave;
     for (int64_t r = w0; r < n_rows; r += nw) {
         if (ptr[r + 1] == ptr[r]) continue;
+        if (bias && lane == 0) bias_s[r] = bias[r];
         for (int64_t k = lane; k < wa; k += kWave) a16[r * wa + k] = to_bf16(a[r * wa + k]);
         if (b)
             for (int64_t k = lane; k < wb; k += kWave) b16[r * wb + k] = to_bf16(b[r * wb + k]);
@@ -47,23 +67,24 @@ __global__ __launch_bounds__(256) void k_bf16_touched(const int64_t* ptr, int64_
 int refresh_bf16_touched(lshmf_ctx* c, const int64_t* b_rptr, const int64_t* b_cptr, hipStream_t s)
 {
     if (c->d.storage == LSHMF_FP32) return LSHMF_OK;
-    const int64_t F = c->d.F, K = c->d.K, N = c->N;
-    const int64_t M = c->d.storage == LSHMF_BF16_U ? 0 : c->M;  // BF16_U: U16 is the master
+    const int64_t F = c->d.F, K = c->d.K, N = c->N, M = c->M;
+    const int64_t wu = c->d.storage == LSHMF_BF16_U ? 0 : F;  // BF16_U: U16 is the master, only b is copied
     auto grid = [](int64_t rows) {
         int64_t b = ceil_div(rows > 0 ? rows * kWave : 1, 256);
         return (unsigned)(b > 16384 ? 16384 : b);
     };
     if (M > 0) {
-        hipLaunchKernelGGL(k_bf16_touched, dim3(grid(M)), dim3(256), 0, s, b_rptr, M, c->t.U, c->t.U16, F,
-                           (const float*)nullptr, (uint16_t*)nullptr, (int64_t)0);
+        hipLaunchKernelGGL(k_bf16_touched, dim3(grid(M)), dim3(256), 0, s, b_rptr, M, c->t.U, c->t.U16, wu,
+                           (const float*)nullptr, (uint16_t*)nullptr, (int64_t)0, (const float*)c->t.bu, c->bu_s);
         LSHMF_LAUNCHED("k_bf16_touched(users)");
     }
     if (N > 0) {
         hipLaunchKernelGGL(k_bf16_touched, dim3(grid(N)), dim3(256), 0, s, b_cptr, N, c->t.V, c->t.V16, F, c->t.W,
-                           c->t.W16, K);
+                           c->t.W16, K, (const float*)c->t.bv, c->bv_s);
         LSHMF_LAUNCHED("k_bf16_touched(items V,W)");
         hipLaunchKernelGGL(k_bf16_touched, dim3(grid(N)), dim3(256), 0, s, b_cptr, N, c->t.C, c->t.C16, K,
-                           (const float*)nullptr, (uint16_t*)nullptr, (int64_t)0);
+                           (const float*)nullptr, (uint16_t*)nullptr, (int64_t)0, (const float*)nullptr,
+                           (float*)nullptr);
         LSHMF_LAUNCHED("k_bf16_touched(items C)");
     }
     return LSHMF_OK;
@@ -75,6 +96,8 @@ int refresh_bf16(lshmf_ctx* c, int64_t m0, int64_t m1, int64_t n0, int64_t n1, h
     if (c->d.storage == LSHMF_FP32) return LSHMF_OK;
     const int64_t F = c->d.F, K = c->d.K;
     if (c->d.storage == LSHMF_BF16) LSHMF_TRY(to_bf16_rows(c->t.U + m0 * F, c->t.U16 + m0 * F, (m1 - m0) * F, s));
+    LSHMF_TRY(copy_rows(c->t.bu + m0, c->bu_s + m0, m1 - m0, s));
+    LSHMF_TRY(copy_rows(c->t.bv + n0, c->bv_s + n0, n1 - n0, s));
     LSHMF_TRY(to_bf16_rows(c->t.V + n0 * F, c->t.V16 + n0 * F, (n1 - n0) * F, s));
     LSHMF_TRY(to_bf16_rows(c->t.W + n0 * K, c->t.W16 + n0 * K, (n1 - n0) * K, s));
     return to_bf16_rows(c->t.C + n0 * K, c->t.C16 + n0 * K, (n1 - n0) * K, s);
@@ -192,7 +215,7 @@ int run_predict(lshmf_ctx* c, const int32_t* qu, const int32_t* qi, int64_t n, f
     const bool bf = d.storage != LSHMF_FP32;  // BF16 copies (BF16), or BF16 user rows and copies (BF16_U)
     PredArgs a{c->t.JK, c->t.b0, c->t.bh0, c->t.mu,
                bf ? (const void*)c->t.U16 : (const void*)c->t.U, bf ? (const void*)c->t.V16 : (const void*)c->t.V,
-               c->t.bu, c->t.bv,
+               bf ? c->bu_s : c->t.bu, bf ? c->bv_s : c->t.bv,
                bf ? (const void*)c->t.W16 : (const void*)c->t.W, bf ? (const void*)c->t.C16 : (const void*)c->t.C,
                c->row_ptr, c->csr_col, c->csr_rc, c->M, c->N, d.F, d.K, 1.0f / (float)d.rscale};
     int64_t blocks = ceil_div(n * kWave, 256);

@@ -11,6 +11,10 @@
 
 namespace lshmf {
 
+int run_online(lshmf_ctx* c, const int32_t* u, const int32_t* it, const uint8_t* rc, int64_t n, int32_t M_new,
+               int32_t N_new, const void* R, uint64_t seed_fill, const lshmf_hparams* hp, int epoch,
+               int passes, uint32_t flags, hipStream_t s, bool refresh);
+
 namespace {
 
 size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
@@ -107,17 +111,45 @@ int lshmf_serve(lshmf_ctx* ctx, const lshmf_serve_io* io, lshmf_stream_t compute
     uint8_t* src = reinterpret_cast<uint8_t*>(stage + L.upd_rc);
     const int64_t F = ctx->d.F;
 
-    // events: a small pool, recycled as work retires
-    constexpr int kEvents = 8;
-    hipEvent_t pool[kEvents];
-    int nev = 0;
-    for (; nev < kEvents; ++nev) {
-        hipError_t e = hipEventCreateWithFlags(&pool[nev], hipEventDisableTiming);
-        if (e != hipSuccess) {
-            for (int k = 0; k < nev; ++k) (void)hipEventDestroy(pool[k]);
-            return hip_fail(e, "hipEventCreateWithFlags");
-        }
+    // In storage mode BF16, queries read only the BF16 copies and bias
+    // snapshots, which an update rewrites in its last step: queries then run
+    // on a stream of their own beside the next update's hashing, neighbour
+    // and SGD phases, and only that last step waits for them.  Other modes
+    // read live tables, so queries and updates share the compute stream.
+    const bool overlap = ctx->d.storage == LSHMF_BF16;
+    hipStream_t qs = cs;
+    constexpr int kEvents = 16;
+    // events: a pool recycled as work retires, plus three markers that are
+    // recorded again each time (a wait refers to the latest record)
+    hipEvent_t pool[kEvents] = {};
+    hipEvent_t mark[3] = {};
+    hipError_t e0 = hipSuccess;
+    for (int k = 0; k < kEvents && e0 == hipSuccess; ++k) {
+        e0 = hipEventCreateWithFlags(&pool[k], hipEventDisableTiming);
+        if (e0 != hipSuccess) pool[k] = nullptr;
     }
+    for (int k = 0; k < 3 && e0 == hipSuccess; ++k) {
+        e0 = hipEventCreateWithFlags(&mark[k], hipEventDisableTiming);
+        if (e0 != hipSuccess) mark[k] = nullptr;
+    }
+    if (e0 == hipSuccess && overlap) {
+        e0 = hipStreamCreateWithFlags(&qs, hipStreamNonBlocking);
+        if (e0 != hipSuccess) qs = cs;
+    }
+    hipEvent_t visible = mark[0], qdone = mark[1], upd_fin = mark[2];
+    auto release_all = [&]() {
+        for (hipEvent_t x : pool)
+            if (x) (void)hipEventDestroy(x);
+        for (hipEvent_t x : mark)
+            if (x) (void)hipEventDestroy(x);
+        if (qs != cs) (void)hipStreamDestroy(qs);
+    };
+    if (e0 != hipSuccess) {
+        release_all();
+        return hip_fail(e0, "lshmf_serve set-up");
+    }
+    bool have_visible = false, have_qdone = false, have_upd = false;
+
     std::deque<hipEvent_t> free_ev(pool, pool + kEvents);
     std::deque<Work> inflight;
     bool qbusy[2] = {false, false};
@@ -126,9 +158,9 @@ int lshmf_serve(lshmf_ctx* ctx, const lshmf_serve_io* io, lshmf_stream_t compute
     const auto t0 = std::chrono::steady_clock::now();
 
     auto take_event = [&]() {
-        hipEvent_t e = free_ev.front();
+        hipEvent_t x = free_ev.front();
         free_ev.pop_front();
-        return e;
+        return x;
     };
     auto refuse = [&](int64_t r, int st) {
         const double t = seconds_since(t0);
@@ -139,26 +171,28 @@ int lshmf_serve(lshmf_ctx* ctx, const lshmf_serve_io* io, lshmf_stream_t compute
 
     while (retired < io->n_req && status == LSHMF_OK) {
         bool progress = false;
-        // retire finished work, in launch order
-        while (!inflight.empty()) {
-            const hipError_t e = hipEventQuery(inflight.front().ev[0]);
-            if (e == hipErrorNotReady) break;
+        // retire finished work, whichever finished (queries may overtake an update)
+        for (auto it = inflight.begin(); it != inflight.end();) {
+            const hipError_t e = hipEventQuery(it->ev[0]);
+            if (e == hipErrorNotReady) {
+                ++it;
+                continue;
+            }
             if (e != hipSuccess) {
                 status = hip_fail(e, "hipEventQuery");
                 break;
             }
-            const Work w = inflight.front();
-            inflight.pop_front();
             const double t = seconds_since(t0);
-            for (int64_t r = w.first; r <= w.last; ++r) io->h_done[r] = t;
-            retired += w.last - w.first + 1;
-            if (w.qslot >= 0) qbusy[w.qslot] = false;
-            for (int k = 0; k < w.nev; ++k) free_ev.push_back(w.ev[k]);
+            for (int64_t r = it->first; r <= it->last; ++r) io->h_done[r] = t;
+            retired += it->last - it->first + 1;
+            if (it->qslot >= 0) qbusy[it->qslot] = false;
+            for (int k = 0; k < it->nev; ++k) free_ev.push_back(it->ev[k]);
+            it = inflight.erase(it);
             progress = true;
         }
         if (status != LSHMF_OK) break;
 
-        if (next < io->n_req && inflight.size() < 2 && free_ev.size() >= 3 && R[next].arrival <= seconds_since(t0)) {
+        if (next < io->n_req && inflight.size() < 4 && free_ev.size() >= 3 && R[next].arrival <= seconds_since(t0)) {
             const lshmf_request& q = R[next];
             if (q.kind == LSHMF_REQ_UPDATE) {
                 if (q.n > ctx->d.batch_cap || ctx->nnz + q.n > ctx->d.nnz_cap || q.M_new > ctx->d.M_cap ||
@@ -170,10 +204,11 @@ int lshmf_serve(lshmf_ctx* ctx, const lshmf_serve_io* io, lshmf_stream_t compute
                     refuse(next++, LSHMF_EINVAL);
                     continue;
                 }
-                // The update staging is free again: online_update synchronises its
-                // stream after the last kernel that reads the batch.
+                // The update staging is rewritten only once the previous update's
+                // kernels, the last readers of it, are done.
                 hipEvent_t up = take_event(), fin = take_event();
                 hipError_t e = hipSuccess;
+                if (have_upd) e = hipStreamWaitEvent(ps, upd_fin, 0);
                 if (e == hipSuccess && q.n > 0)
                     e = hipMemcpyAsync(su, io->h_u + q.offset, 4 * q.n, hipMemcpyHostToDevice, ps);
                 if (e == hipSuccess && q.n > 0)
@@ -202,8 +237,9 @@ int lshmf_serve(lshmf_ctx* ctx, const lshmf_serve_io* io, lshmf_stream_t compute
                     break;
                 }
                 io->h_start[next] = seconds_since(t0);
-                const int st = online_update(ctx, su, si, src, q.n, q.M_new, q.N_new, io->d_rand, io->seed_fill,
-                                             &io->hp, io->epoch, io->passes, 0u, compute_);
+                const int32_t M_old = ctx->M, N_old = ctx->N;
+                const int st = run_online(ctx, su, si, src, q.n, q.M_new, q.N_new, io->d_rand, io->seed_fill, &io->hp,
+                                          io->epoch, io->passes, 0u, cs, !overlap);
                 if (st == LSHMF_EINVAL || st == LSHMF_ECAPACITY) {  // refused before anything changed
                     io->h_done[next] = seconds_since(t0);
                     io->h_status[next] = st;
@@ -219,11 +255,24 @@ int lshmf_serve(lshmf_ctx* ctx, const lshmf_serve_io* io, lshmf_stream_t compute
                     status = st;
                     break;
                 }
-                e = hipEventRecord(fin, cs);
+                if (overlap) {
+                    // the copies change only after the queries that came before this update
+                    if (have_qdone) e = hipStreamWaitEvent(cs, qdone, 0);
+                    int st2 = e == hipSuccess ? refresh_after_online(ctx, M_old, N_old, 0u, cs) : LSHMF_OK;
+                    if (e == hipSuccess && st2 == LSHMF_OK) e = hipEventRecord(visible, cs);
+                    if (st2 != LSHMF_OK) {
+                        status = st2;
+                        break;
+                    }
+                    have_visible = true;
+                }
+                if (e == hipSuccess) e = hipEventRecord(fin, cs);
+                if (e == hipSuccess) e = hipEventRecord(upd_fin, cs);
                 if (e != hipSuccess) {
                     status = hip_fail(e, "hipEventRecord");
                     break;
                 }
+                have_upd = true;
                 io->h_status[next] = LSHMF_OK;
                 inflight.push_back(Work{next, next, {fin, up}, 2, -1});
                 ++next;
@@ -259,7 +308,9 @@ int lshmf_serve(lshmf_ctx* ctx, const lshmf_serve_io* io, lshmf_stream_t compute
                         at += R[r].n;
                     }
                     if (e == hipSuccess) e = hipEventRecord(up, ps);
-                    if (e == hipSuccess) e = hipStreamWaitEvent(cs, up, 0);
+                    if (e == hipSuccess) e = hipStreamWaitEvent(qs, up, 0);
+                    // these queries see every update that arrived before them
+                    if (e == hipSuccess && overlap && have_visible) e = hipStreamWaitEvent(qs, visible, 0);
                     if (e != hipSuccess) {
                         for (hipEvent_t x : {up, ready, fin}) free_ev.push_back(x);
                         status = hip_fail(e, "lshmf_serve query upload");
@@ -270,13 +321,17 @@ int lshmf_serve(lshmf_ctx* ctx, const lshmf_serve_io* io, lshmf_stream_t compute
                         io->h_start[r] = ts;
                         io->h_status[r] = LSHMF_OK;
                     }
-                    const int st = predict(ctx, qu, qi, total, out, compute_);
+                    const int st = predict(ctx, qu, qi, total, out, reinterpret_cast<lshmf_stream_t>(qs));
                     if (st != LSHMF_OK) {
                         for (hipEvent_t x : {up, ready, fin}) free_ev.push_back(x);
                         status = st;
                         break;
                     }
-                    e = hipEventRecord(ready, cs);
+                    e = hipEventRecord(ready, qs);
+                    if (e == hipSuccess && overlap) {
+                        e = hipEventRecord(qdone, qs);
+                        have_qdone = true;
+                    }
                     if (e == hipSuccess) e = hipStreamWaitEvent(ps, ready, 0);
                     at = 0;
                     for (int64_t r = next; r <= last && e == hipSuccess; ++r) {
@@ -301,12 +356,14 @@ int lshmf_serve(lshmf_ctx* ctx, const lshmf_serve_io* io, lshmf_stream_t compute
     idle:
         if (!progress) std::this_thread::yield();
     }
-    // drain whatever is still queued, then release the events
+    // drain whatever is still queued, then release the events and the query stream
     hipError_t e1 = hipStreamSynchronize(cs);
     hipError_t e2 = hipStreamSynchronize(ps);
-    for (int k = 0; k < kEvents; ++k) (void)hipEventDestroy(pool[k]);
+    hipError_t e3 = qs != cs ? hipStreamSynchronize(qs) : hipSuccess;
+    release_all();
     if (status == LSHMF_OK && e1 != hipSuccess) status = hip_fail(e1, "hipStreamSynchronize(compute)");
     if (status == LSHMF_OK && e2 != hipSuccess) status = hip_fail(e2, "hipStreamSynchronize(copy)");
+    if (status == LSHMF_OK && e3 != hipSuccess) status = hip_fail(e3, "hipStreamSynchronize(queries)");
     if (status == LSHMF_OK) status = sync_status(ctx, cs);  // an SGD wait that gave up
     return status;
 }

@@ -26,12 +26,12 @@ def _say(msg):
     sys.stdout.flush()
 
 
-def _pretrained(w, d, sp, batch_cap):
+def _pretrained(w, d, sp, batch_cap, storage):
     from paper_2111_11682_amd import lshmf
     M0, N0 = int(sp["M_old"]), int(sp["N_old"])
     m = lshmf.LshMF(M0, N0, w.F, w.K, w.G, w.p, w.q, w.rscale, sp["pretrain_u"].size,
                     n_strata=w.n_strata, M_cap=w.M, N_cap=w.N, nnz_cap=d["train_u"].size + 64,
-                    batch_cap=batch_cap)
+                    batch_cap=batch_cap, storage=storage)
     dev = m.device
     m.ingest(*[torch.from_numpy(sp[k]).to(dev) for k in ("pretrain_u", "pretrain_i", "pretrain_rc")])
     m.set_factors(torch.from_numpy(d["U0"][:M0]).to(dev), torch.from_numpy(d["V0"][:N0]).to(dev))
@@ -42,7 +42,10 @@ def _pretrained(w, d, sp, batch_cap):
     return m
 
 
-def test_serve_equals_requests_one_at_a_time():
+@pytest.mark.parametrize("storage", ["fp32", "bf16", "bf16u"])
+def test_serve_equals_requests_one_at_a_time(storage):
+    # fp32 and bf16u: queries and updates on one stream; bf16: queries on a
+    # stream of their own, overlapping the next update up to its last step
     w = synth.WORKLOADS["small"]
     d = synth.generate(w)
     sp = synth.online_split(w, d, frac_new=0.03, stream_frac=0.2)
@@ -64,7 +67,7 @@ def test_serve_equals_requests_one_at_a_time():
     V0 = torch.from_numpy(d["V0"]).to(dev)
     H = torch.from_numpy(d["H"].view(np.int32)).to(dev)
 
-    m1 = _pretrained(w, d, sp, batch_cap)
+    m1 = _pretrained(w, d, sp, batch_cap, storage)
     pred, start, done, status = m1.serve(req, upd, qry, U0, V0, H, SEED_FILL, w.alpha, w.lam, w.beta,
                                          3, 1, max_query_batch=mqb)
     assert m1.device_status() == 0
@@ -75,11 +78,11 @@ def test_serve_equals_requests_one_at_a_time():
     starts = start[q]
     assert np.any(starts[1:] == starts[:-1]), "no queries were merged"
     lat = (done - req["arrival"])[q & (status == 0)]
-    _say("[gpu] serve query latency p50 %.3f ms p99 %.3f ms" %
-         (1e3 * np.percentile(lat, 50), 1e3 * np.percentile(lat, 99)))
+    _say("[gpu] serve (%s) query latency p50 %.3f ms p99 %.3f ms" %
+         (storage, 1e3 * np.percentile(lat, 50), 1e3 * np.percentile(lat, 99)))
 
     # the same requests, one call each
-    m2 = _pretrained(w, d, sp, batch_cap)
+    m2 = _pretrained(w, d, sp, batch_cap, storage)
     ref = torch.full_like(pred, float("nan"))
     Mc, Nc = int(sp["M_old"]), int(sp["N_old"])
     for r in range(req.size):
@@ -95,7 +98,12 @@ def test_serve_equals_requests_one_at_a_time():
             ref[o:o + n] = m2.predict(qry[0][o:o + n].to(dev), qry[1][o:o + n].to(dev)).cpu()
     torch.cuda.synchronize()
     assert torch.equal(pred, ref)
-    for k in ("U", "V", "bu", "bv", "W", "C", "JK", "acc", "sig", "b0", "bh0"):
+    tabs = ["U", "V", "bu", "bv", "W", "C", "JK", "acc", "sig", "b0", "bh0"]
+    if storage != "fp32":
+        tabs += ["U16", "V16", "W16", "C16"]
+    if storage == "bf16u":
+        tabs.remove("U")  # not used in this mode
+    for k in tabs:
         assert torch.equal(getattr(m1, k), getattr(m2, k)), k
     lay1, lay2 = m1.layout(), m2.layout()
     assert (lay1.M, lay1.N, lay1.nnz) == (lay2.M, lay2.N, lay2.nnz)
