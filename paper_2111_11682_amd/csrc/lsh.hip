@@ -16,20 +16,25 @@
 //   k_nbr_codes     per training rating (i, j): the rating code of user i for
 //                   each neighbour JK[j][k] (0 if not rated), 4 bits per slot;
 //                   this resolves R^K(i;j) and N^K(i;j) once for all epochs.
+//   k_nbr_codes_rows  the same codes by user row through an LDS item map, for
+//                   streams that hold most of the store.
 #include "common.hpp"
 
 namespace lshmf {
 
 // ------------------------------------------------------------ projection
-// A wave walks a chunk of CSC positions.  Lane (g, w) owns signature word w
-// of the current 64-word slice (32 bits) and takes the positions p of the
-// chunk with p = first + g (mod R), R = 64 / Wd rating groups, Wd the slice's
-// word count rounded up to a power of two.  Per rating it loads one word of
-// H_i and adds Psi(r) to the counters of its set bits, S_t += Psi * bit_t;
-// T sums Psi.  At a column change the lane adds its part of
-// acc[j][32w + t] = sum Psi (2 bit - 1) = 2 S_t - T with integer atomics, so
+// A wave walks a chunk of CSC positions, one column segment at a time (the
+// columns meeting the chunk, in order).  Lane (g, w) owns signature word w of
+// the current 64-word slice (32 bits) and takes the positions p of the
+// segment with p = start + g (mod R), R = 64 / Wd rating groups, Wd the
+// slice's word count rounded up to a power of two.  Per rating it loads one
+// word of H_i and adds Psi(r) to the counters of its set bits,
+// S_t += Psi * bit_t; T sums Psi.  At the segment's end the R groups' counters
+// are summed across the wave and one lane per word adds
+// acc[j][32w + t] += 2 S_t - T = sum Psi (2 bit - 1) with integer atomics, so
 // the sums are exact and independent of the order of the flushes (the
-// counters wrap modulo 2^32; the exact total fits int32).
+// counters wrap modulo 2^32; the exact total fits int32).  Summing before the
+// atomics keeps a popular column's chunks to one atomic per bit each.
 constexpr int kAccChunk = 1024;    // CSC positions per wave
 
 __global__ __launch_bounds__(256) void k_simlsh_acc(const int64_t* col_ptr, const int32_t* row,
@@ -42,9 +47,10 @@ __global__ __launch_bounds__(256) void k_simlsh_acc(const int64_t* col_ptr, cons
     const int64_t p0 = wave * kAccChunk;
     if (p0 >= nnz) return;
     const int64_t p1 = p0 + kAccChunk < nnz ? p0 + kAccChunk : nnz;
+    const int Wd = 1 << wd_log2;
     const int R = kWave >> wd_log2;
     const int grp = lane >> wd_log2;
-    const int w = (int)blockIdx.y * kWave + (lane & ((1 << wd_log2) - 1));
+    const int w = (int)blockIdx.y * kWave + (lane & (Wd - 1));
     const bool wok = w < words;
     // column containing p0: largest j with col_ptr[j] <= p0
     int32_t lo = 0, hi = N;  // invariant col_ptr[lo] <= p0 < col_ptr[hi]
@@ -54,41 +60,54 @@ __global__ __launch_bounds__(256) void k_simlsh_acc(const int64_t* col_ptr, cons
         else hi = mid;
     }
     int32_t j = lo;
-    int64_t jend = col_ptr[j + 1];
-    uint32_t S[32];
+    int64_t cs = p0;
+    for (;;) {
+        const int64_t cend = col_ptr[j + 1];
+        const int64_t ce = cend < p1 ? cend : p1;
+        uint32_t S[32];
 #pragma unroll
-    for (int t = 0; t < 32; ++t) S[t] = 0u;
-    uint32_t T = 0u;
-    auto flush = [&]() {
-        if (wok && T != 0u) {
+        for (int t = 0; t < 32; ++t) S[t] = 0u;
+        uint32_t T = 0u;
+        int64_t p = cs + grp;
+        int64_t i_next = p < ce ? row[p] : 0;
+        uint32_t c_next = p < ce ? rc[p] : 0u;
+        while (p < ce) {
+            const int64_t i = i_next;
+            const uint32_t code = c_next;
+            const int64_t pn = p + R;
+            if (pn < ce) {
+                i_next = row[pn];
+                c_next = rc[pn];
+            }
+            const uint32_t x = wok ? H[i * words + w] : 0u;
+            uint32_t psi = 1u;
+            for (int e = 0; e < psi_exp; ++e) psi *= code;
+            T += psi;
+#pragma unroll
+            for (int t = 0; t < 32; ++t) S[t] += ((x >> t) & 1u) * psi;
+            p = pn;
+        }
+        // sum the R groups: lanes with the same word differ in the bits above wd_log2
+        for (int o = Wd; o < kWave; o <<= 1) {
+#pragma unroll
+            for (int t = 0; t < 32; ++t) S[t] += (uint32_t)__shfl_xor((int)S[t], o, kWave);
+            T += (uint32_t)__shfl_xor((int)T, o, kWave);
+        }
+        if (grp == 0 && wok && T != 0u) {
             int32_t* a = acc + (int64_t)j * B + 32 * w;
 #pragma unroll
             for (int t = 0; t < 32; ++t) {
                 const int32_t v = (int32_t)(2u * S[t] - T);
                 if (32 * w + t < B && v != 0) atomicAdd(a + t, v);
-                S[t] = 0u;
             }
         }
-        T = 0u;
-    };
-    for (int64_t p = p0 + grp; p < p1; p += R) {
-        if (p >= jend) {
-            flush();
-            do {
-                ++j;
-                jend = col_ptr[j + 1];
-            } while (p >= jend);
-        }
-        const int64_t i = row[p];
-        const uint32_t x = wok ? H[i * words + w] : 0u;
-        uint32_t psi = 1u;
-        const uint32_t code = rc[p];
-        for (int e = 0; e < psi_exp; ++e) psi *= code;
-        T += psi;
-#pragma unroll
-        for (int t = 0; t < 32; ++t) S[t] += ((x >> t) & 1u) * psi;
+        if (ce >= p1) break;
+        // next column with ratings (empty columns end where this one ends)
+        do {
+            ++j;
+        } while (col_ptr[j + 1] <= ce);
+        cs = ce;
     }
-    flush();
 }
 
 __global__ void k_simlsh_sign(const int32_t* acc, int32_t N, int B, int words, uint32_t* sig)
@@ -438,6 +457,75 @@ __global__ __launch_bounds__(256) void k_nbr_codes(const uint32_t* pk, const int
     }
 }
 
+// The same codes by user row, for streams that hold most of the store.
+// k_stream_csr_pos finds each stream rating's CSR position (one binary search
+// per rating, one lane each) and records the stream position there; entries
+// of the store outside the stream keep -1.  k_nbr_codes_rows then takes one
+// user row at a time per workgroup: the row's rating codes are scattered into
+// an LDS byte map indexed by item (N bytes), and every 4-byte word of every
+// record of the row (8 slots) is resolved with 8 LDS reads, so a rating costs
+// its K neighbour ids from L2 instead of K binary searches in HBM.
+constexpr int kCodeMapMax = 65536;   // items an LDS byte map can hold
+
+__global__ void k_stream_csr_pos(const uint32_t* pk, const int32_t* sj, int64_t n, const int64_t* row_ptr,
+                                 const int32_t* csr_col, int32_t* pos)
+{
+    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < n;
+         p += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = pk[p] >> 4;
+        const int32_t j = sj[p];
+        const int64_t z = row_ptr[i + 1];
+        int64_t l = row_ptr[i], r = z;
+        while (l < r) {
+            const int64_t m = (l + r) >> 1;
+            if (csr_col[m] < j) l = m + 1;
+            else r = m;
+        }
+        if (l < z && csr_col[l] == j) pos[l] = (int32_t)p;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_nbr_codes_rows(const int64_t* row_ptr, const int32_t* csr_col,
+                                                        const uint8_t* csr_rc, int32_t M, int32_t N,
+                                                        const int32_t* pos, const int32_t* JK, int K,
+                                                        uint8_t* nib, int nstride)
+{
+    extern __shared__ uint32_t map_words[];
+    uint8_t* map = reinterpret_cast<uint8_t*>(map_words);
+    const int tid = threadIdx.x, nt = blockDim.x;
+    for (int x = tid; x < (N + 3) / 4; x += nt) map_words[x] = 0;
+    const int wpr = nstride / 4;               // 4-byte words per record
+    const bool quads = (K & 3) == 0;           // JK rows 16-byte aligned
+    for (int32_t i = blockIdx.x; i < M; i += gridDim.x) {
+        const int64_t a = row_ptr[i];
+        const int32_t deg = (int32_t)(row_ptr[i + 1] - a);
+        __syncthreads();                       // the previous row's map is clear
+        for (int32_t x = tid; x < deg; x += nt) map[csr_col[a + x]] = csr_rc[a + x];
+        __syncthreads();
+        const int32_t work = deg * wpr;
+        for (int32_t t = tid; t < work; t += nt) {
+            const int32_t e = t / wpr, w = t - e * wpr;
+            const int32_t p = pos[a + e];
+            if (p < 0) continue;
+            const int32_t* jk = JK + (int64_t)csr_col[a + e] * K;
+            const int k0 = 8 * w;
+            uint32_t word = 0;
+            if (quads && k0 + 8 <= K) {
+                const int4 q0 = *reinterpret_cast<const int4*>(jk + k0);
+                const int4 q1 = *reinterpret_cast<const int4*>(jk + k0 + 4);
+                word = (uint32_t)map[q0.x] | (uint32_t)map[q0.y] << 4 | (uint32_t)map[q0.z] << 8 |
+                       (uint32_t)map[q0.w] << 12 | (uint32_t)map[q1.x] << 16 | (uint32_t)map[q1.y] << 20 |
+                       (uint32_t)map[q1.z] << 24 | (uint32_t)map[q1.w] << 28;
+            } else {
+                for (int h = 0; h < 8 && k0 + h < K; ++h) word |= (uint32_t)map[jk[k0 + h]] << (4 * h);
+            }
+            *reinterpret_cast<uint32_t*>(nib + (int64_t)p * nstride + 4 * w) = word;
+        }
+        __syncthreads();
+        for (int32_t x = tid; x < deg; x += nt) map[csr_col[a + x]] = 0;
+    }
+}
+
 __global__ void k_nbr_b0(const int32_t* JK, const float* bh0, int64_t n, float* out)
 {
     for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < n;
@@ -558,9 +646,24 @@ int neighbours_for(lshmf_ctx* c, int32_t j_first, int32_t count, uint64_t seed_f
 int stream_codes(lshmf_ctx* c, Stream& st, hipStream_t s)
 {
     if (st.n > 0 && c->d.K > 0) {
-        hipLaunchKernelGGL(k_nbr_codes, dim3(grid_for(st.n * kWave, 256, 65536)), dim3(256), 0, s, st.pk, st.sj,
-                           st.n, c->t.JK, c->d.K, c->row_ptr, c->csr_col, c->csr_rc, st.nib, c->nstride);
-        LSHMF_LAUNCHED("k_nbr_codes");
+        if (c->N <= kCodeMapMax && st.n * 4 >= c->nnz) {
+            // by user row: c->e2s (free outside a stream build) holds the
+            // stream position of every CSR entry
+            LSHMF_TRY(fill_i32(c->e2s, c->nnz, -1, s));
+            hipLaunchKernelGGL(k_stream_csr_pos, dim3(grid_for(st.n)), dim3(256), 0, s, st.pk, st.sj, st.n,
+                               c->row_ptr, c->csr_col, c->e2s);
+            LSHMF_LAUNCHED("k_stream_csr_pos");
+            const size_t lds = sizeof(uint32_t) * (size_t)((c->N + 3) / 4);
+            const unsigned grid = (unsigned)(c->M < 4096 ? (c->M > 0 ? c->M : 1) : 4096);
+            hipLaunchKernelGGL(k_nbr_codes_rows, dim3(grid), dim3(256), lds, s, c->row_ptr, c->csr_col, c->csr_rc,
+                               c->M, c->N, c->e2s, c->t.JK, c->d.K, st.nib, c->nstride);
+            LSHMF_LAUNCHED("k_nbr_codes_rows");
+        } else {
+            hipLaunchKernelGGL(k_nbr_codes, dim3(grid_for(st.n * kWave, 256, 65536)), dim3(256), 0, s, st.pk,
+                               st.sj, st.n, c->t.JK, c->d.K, c->row_ptr, c->csr_col, c->csr_rc, st.nib,
+                               c->nstride);
+            LSHMF_LAUNCHED("k_nbr_codes");
+        }
     }
     st.codes = true;
     return LSHMF_OK;

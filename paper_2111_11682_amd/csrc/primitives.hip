@@ -253,17 +253,67 @@ int radix_sort(uint64_t* keys[2], uint32_t* vals[2], int64_t n, int bits, int64_
 }
 
 // --------------------------------------------------------------- counting
+// Up to kCountLds bins per window: every workgroup counts its share of the
+// input in LDS (so the ratings of a popular item do not queue on one global
+// counter) and adds its non-zero bins to the global counts.  Larger ranges
+// (users, blocks) count with global atomics after merging runs of equal
+// consecutive ids inside each wave (inputs grouped by user give one atomic
+// per run).
+constexpr int kCountLds = 16384;
+constexpr int kCountThreads = 256;
+
+__global__ __launch_bounds__(kCountThreads) void k_count_lds(const int32_t* idx, int64_t n, int64_t nbins,
+                                                             unsigned long long* cnt)
+{
+    __shared__ uint32_t h[kCountLds];
+    const int64_t lo = (int64_t)blockIdx.y * kCountLds;
+    const int64_t width = nbins - lo < kCountLds ? nbins - lo : kCountLds;
+    for (int x = threadIdx.x; x < width; x += kCountThreads) h[x] = 0;
+    __syncthreads();
+    for (int64_t x = blockIdx.x * (int64_t)kCountThreads + threadIdx.x; x < n;
+         x += (int64_t)gridDim.x * kCountThreads) {
+        const int64_t b = (int64_t)idx[x] - lo;
+        if (b >= 0 && b < width) atomicAdd(&h[b], 1u);
+    }
+    __syncthreads();
+    for (int x = threadIdx.x; x < width; x += kCountThreads)
+        if (h[x]) atomicAdd(&cnt[lo + x], (unsigned long long)h[x]);
+}
+
 __global__ void k_count(const int32_t* idx, int64_t n, unsigned long long* cnt)
 {
-    for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < n;
-         x += (int64_t)gridDim.x * blockDim.x)
-        atomicAdd(&cnt[idx[x]], 1ull);
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    // whole waves step together so that every lane takes part in the ballots
+    for (int64_t x0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x - lane; x0 < n; x0 += stride) {
+        const int64_t x = x0 + lane;
+        const bool valid = x < n;
+        const int32_t v = valid ? idx[x] : -1;
+        const int32_t prev = __shfl_up(v, 1, kWave);
+        const bool head = valid && (lane == 0 || prev != v);
+        const uint64_t heads = __ballot(head);
+        const uint64_t vmask = __ballot(valid);     // a prefix of the wave
+        if (head) {
+            const uint64_t above = lane == kWave - 1 ? 0ull : heads >> (lane + 1) << (lane + 1);
+            const int end = above ? __ffsll((unsigned long long)above) - 1 : 64 - __clzll((long long)vmask);
+            atomicAdd(&cnt[v], (unsigned long long)(end - lane));
+        }
+    }
 }
 
 int count_bins(const int32_t* idx, int64_t n, int64_t* cnt, int64_t nbins, hipStream_t s)
 {
     LSHMF_TRY(fill_i64(cnt, nbins, 0, s));
     if (n <= 0) return LSHMF_OK;
+    if (nbins <= 4 * kCountLds) {
+        int64_t blocks = ceil_div(n, 16 * kCountThreads);
+        if (blocks > 512) blocks = 512;
+        const unsigned windows = (unsigned)ceil_div(nbins, kCountLds);
+        hipLaunchKernelGGL(k_count_lds, dim3((unsigned)blocks, windows), dim3(kCountThreads), 0, s, idx, n, nbins,
+                           (unsigned long long*)cnt);
+        LSHMF_LAUNCHED("k_count_lds");
+        return LSHMF_OK;
+    }
     int64_t blocks = ceil_div(n, 256);
     if (blocks > 16384) blocks = 16384;
     hipLaunchKernelGGL(k_count, dim3((unsigned)blocks), dim3(256), 0, s, idx, n,

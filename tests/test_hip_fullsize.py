@@ -3,9 +3,10 @@ launch configuration bench.py times (P = 256 strata, needs an MI355X).
 
 69,878 users x 10,677 items, 9.9M training ratings, F = 64, K = 50, 128 hash
 bits.  Hash sums, signatures, neighbour lists and the whole stratified stream
-must match bit for bit; one SGD epoch over all ratings within 1e-4 element
-by element (tablecmp.py); predictions on sampled pairs within 1e-5; the
-held-out RMSE after all 20 epochs within 0.5% of the oracle's.
+must match bit for bit, the neighbour codes of sampled records byte for
+byte; one SGD epoch over all ratings within 1e-4 element by element
+(tablecmp.py); predictions on sampled pairs within 1e-5; the held-out RMSE
+after all 20 epochs within 0.5% of the oracle's.
 """
 import sys
 
@@ -16,6 +17,7 @@ torch = pytest.importorskip("torch")
 
 from oracle import oracle as orc
 from paper_2111_11682_amd import synth
+from nbrcodes import expected_codes
 from tablecmp import compare_tables
 
 pytestmark = pytest.mark.gpu
@@ -75,6 +77,13 @@ def test_fullsize_stream_order_bit_exact():
     assert np.array_equal(pk >> 4, d["train_u"][order].astype(np.uint32))
     assert np.array_equal(pk & 15, d["train_rc"][order].astype(np.uint32))
     assert np.array_equal(m.arena_view(lay.sj, nnz, torch.int32).cpu().numpy(), d["train_i"][order])
+    # neighbour codes of 300,000 sampled records, every byte
+    _, _, JK = _oracle_neighbours()
+    x = np.sort(np.random.default_rng(5).choice(nnz, 300_000, replace=False))
+    nib = m.arena_view(lay.nib, nnz * lay.nstride, torch.uint8).view(nnz, lay.nstride)
+    nib = nib[torch.from_numpy(x).to(m.device)].cpu().numpy()
+    assert np.array_equal(nib, expected_codes(w.N, w.K, d["train_u"], d["train_i"], d["train_rc"], order[x],
+                                                 JK, lay.nstride))
 
 
 def test_fullsize_one_epoch_and_predictions():

@@ -4,7 +4,8 @@
 128 hash bits, in the launch configuration bench.py times (1,536 strata),
 storage mode BF16 (FP32 masters, BF16 copies that predict reads), then again
 with the user rows stored in BF16 only (storage BF16_U).  Hash sums,
-signatures and neighbour lists bit for bit; one SGD epoch over all ratings
+signatures and neighbour lists bit for bit, neighbour codes of sampled
+records byte for byte; one SGD epoch over all ratings
 within 1e-4 element by element (tablecmp.py); held-out RMSE after that epoch,
 predicted from the BF16 copies, within 0.5% of the FP64 oracle's, in both
 storage modes.
@@ -19,6 +20,7 @@ torch = pytest.importorskip("torch")
 
 from oracle import oracle as orc
 from paper_2111_11682_amd import synth
+from nbrcodes import expected_codes
 from tablecmp import compare_tables
 
 pytestmark = pytest.mark.gpu
@@ -58,6 +60,15 @@ def test_netflix_shape_neighbours_epoch_and_bf16_rmse():
                   d["U0"], d["V0"])
     o.sgd_epoch(w.n_strata, w.alpha, w.lam, w.beta, 0)
     _say("[gpu] netflix oracle epoch in %.0f s" % (time.time() - t0))
+    # neighbour codes of 200,000 sampled records, every byte
+    n = d["train_u"].size
+    lay = m.layout()
+    x = np.sort(np.random.default_rng(5).choice(n, 200_000, replace=False))
+    nib = m.arena_view(lay.nib, n * lay.nstride, torch.uint8).view(n, lay.nstride)
+    nib = nib[torch.from_numpy(x).to(dev)].cpu().numpy()
+    order = o._sched[w.n_strata][0]
+    assert np.array_equal(nib, expected_codes(w.N, w.K, d["train_u"], d["train_i"], d["train_rc"], order[x],
+                                                 JK, lay.nstride))
     compare_tables({k: (getattr(m, k).double().cpu().numpy().reshape(getattr(o, k).shape), getattr(o, k))
                     for k in ("U", "V", "bu", "bv", "W", "C")}, 1e-4, _say, "netflix one epoch")
     tu, ti, trc = (torch.from_numpy(d[k]).to(dev) for k in ("test_u", "test_i", "test_rc"))

@@ -15,6 +15,7 @@ torch = pytest.importorskip("torch")
 
 from oracle import oracle as orc
 from paper_2111_11682_amd import synth
+from nbrcodes import expected_codes
 from tablecmp import compare_tables
 
 pytestmark = pytest.mark.gpu
@@ -142,25 +143,15 @@ def test_signatures_and_neighbours_bit_exact(name):
 
 @pytest.mark.parametrize("name", ["small", "ml100k", "nfsmall", "wide"])
 def test_neighbour_codes_exact(name):
+    """Every byte of every record, against codes looked up from the triples."""
     w, d, m = gpu_model(name)
     nnz = d["train_u"].size
     lay = m.layout()
     nib = m.arena_view(lay.nib, nnz * lay.nstride, torch.uint8).cpu().numpy().reshape(nnz, lay.nstride)
     order, _ = orc.schedule(w.n_strata, d["train_u"], d["train_i"])
     _, _, JK = oracle_neighbours(name)
-    lookup = {}
-    for a, b, r in zip(d["train_u"], d["train_i"], d["train_rc"]):
-        lookup[(int(a), int(b))] = int(r)
-    rng = np.random.default_rng(0)
-    for x in rng.choice(nnz, min(nnz, 3000), replace=False):
-        e = order[x]
-        i, j = int(d["train_u"][e]), int(d["train_i"][e])
-        for k in range(w.K):
-            want = lookup.get((i, int(JK[j, k])), 0)
-            got = (int(nib[x, k >> 1]) >> (4 * (k & 1))) & 15
-            assert got == want
-        for k in range(w.K, 2 * lay.nstride):
-            assert (int(nib[x, k >> 1]) >> (4 * (k & 1))) & 15 == 0
+    assert np.array_equal(nib, expected_codes(w.N, w.K, d["train_u"], d["train_i"], d["train_rc"], order, JK,
+                                              lay.nstride))
 
 
 # ---------------------------------------------------------------- predict
