@@ -457,38 +457,30 @@ __global__ __launch_bounds__(256) void k_nbr_codes(const uint32_t* pk, const int
     }
 }
 
-// The same codes by user row, for streams that hold most of the store.
-// k_stream_csr_pos finds each stream rating's CSR position (one binary search
-// per rating, one lane each) and records the stream position there; entries
-// of the store outside the stream keep -1.  k_nbr_codes_rows then takes one
-// user row at a time per workgroup: the row's rating codes are scattered into
-// an LDS byte map indexed by item (N bytes), and every 4-byte word of every
+// The same codes by user row, for a stream that holds the whole store.  The
+// stream positions are sorted by user (stable, so ascending inside a user),
+// which groups them as the CSR rows are grouped: user i's ratings take
+// positions row_ptr[i] .. row_ptr[i+1] of the sorted list.  One workgroup
+// takes one user row at a time: the row's rating codes are scattered into an
+// LDS byte map indexed by item (N bytes), and every 4-byte word of every
 // record of the row (8 slots) is resolved with 8 LDS reads, so a rating costs
 // its K neighbour ids from L2 instead of K binary searches in HBM.
 constexpr int kCodeMapMax = 65536;   // items an LDS byte map can hold
+constexpr int kCodeUnroll = 4;       // records words in flight per thread
 
-__global__ void k_stream_csr_pos(const uint32_t* pk, const int32_t* sj, int64_t n, const int64_t* row_ptr,
-                                 const int32_t* csr_col, int32_t* pos)
+__global__ void k_keys_user(const uint32_t* pk, int64_t n, uint64_t* keys, uint32_t* vals)
 {
     for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < n;
          p += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t i = pk[p] >> 4;
-        const int32_t j = sj[p];
-        const int64_t z = row_ptr[i + 1];
-        int64_t l = row_ptr[i], r = z;
-        while (l < r) {
-            const int64_t m = (l + r) >> 1;
-            if (csr_col[m] < j) l = m + 1;
-            else r = m;
-        }
-        if (l < z && csr_col[l] == j) pos[l] = (int32_t)p;
+        keys[p] = pk[p] >> 4;
+        vals[p] = (uint32_t)p;
     }
 }
 
 __global__ __launch_bounds__(256) void k_nbr_codes_rows(const int64_t* row_ptr, const int32_t* csr_col,
                                                         const uint8_t* csr_rc, int32_t M, int32_t N,
-                                                        const int32_t* pos, const int32_t* JK, int K,
-                                                        uint8_t* nib, int nstride)
+                                                        const uint32_t* by_user, const int32_t* sj,
+                                                        const int32_t* JK, int K, uint8_t* nib, int nstride)
 {
     extern __shared__ uint32_t map_words[];
     uint8_t* map = reinterpret_cast<uint8_t*>(map_words);
@@ -496,30 +488,51 @@ __global__ __launch_bounds__(256) void k_nbr_codes_rows(const int64_t* row_ptr, 
     for (int x = tid; x < (N + 3) / 4; x += nt) map_words[x] = 0;
     const int wpr = nstride / 4;               // 4-byte words per record
     const bool quads = (K & 3) == 0;           // JK rows 16-byte aligned
+    // a thread's work items t = tid + m * nt as (record e, word w) = divmod(t, wpr)
+    const int e0 = tid / wpr, w0 = tid - e0 * wpr;
+    const int de = nt / wpr, dw = nt - de * wpr;
     for (int32_t i = blockIdx.x; i < M; i += gridDim.x) {
         const int64_t a = row_ptr[i];
         const int32_t deg = (int32_t)(row_ptr[i + 1] - a);
         __syncthreads();                       // the previous row's map is clear
         for (int32_t x = tid; x < deg; x += nt) map[csr_col[a + x]] = csr_rc[a + x];
         __syncthreads();
-        const int32_t work = deg * wpr;
-        for (int32_t t = tid; t < work; t += nt) {
-            const int32_t e = t / wpr, w = t - e * wpr;
-            const int32_t p = pos[a + e];
-            if (p < 0) continue;
-            const int32_t* jk = JK + (int64_t)csr_col[a + e] * K;
-            const int k0 = 8 * w;
-            uint32_t word = 0;
-            if (quads && k0 + 8 <= K) {
-                const int4 q0 = *reinterpret_cast<const int4*>(jk + k0);
-                const int4 q1 = *reinterpret_cast<const int4*>(jk + k0 + 4);
-                word = (uint32_t)map[q0.x] | (uint32_t)map[q0.y] << 4 | (uint32_t)map[q0.z] << 8 |
-                       (uint32_t)map[q0.w] << 12 | (uint32_t)map[q1.x] << 16 | (uint32_t)map[q1.y] << 20 |
-                       (uint32_t)map[q1.z] << 24 | (uint32_t)map[q1.w] << 28;
-            } else {
-                for (int h = 0; h < 8 && k0 + h < K; ++h) word |= (uint32_t)map[jk[k0 + h]] << (4 * h);
+        int e = e0, w = w0;
+        while (e < deg) {
+            int ee[kCodeUnroll], ww[kCodeUnroll];
+            uint32_t p[kCodeUnroll];
+#pragma unroll
+            for (int u = 0; u < kCodeUnroll; ++u) {
+                ee[u] = e;
+                ww[u] = w;
+                p[u] = e < deg ? by_user[a + e] : 0u;
+                e += de;
+                w += dw;
+                if (w >= wpr) {
+                    w -= wpr;
+                    ++e;
+                }
             }
-            *reinterpret_cast<uint32_t*>(nib + (int64_t)p * nstride + 4 * w) = word;
+            int32_t j[kCodeUnroll];
+#pragma unroll
+            for (int u = 0; u < kCodeUnroll; ++u) j[u] = ee[u] < deg ? sj[p[u]] : 0;
+#pragma unroll
+            for (int u = 0; u < kCodeUnroll; ++u) {
+                if (ee[u] >= deg) continue;
+                const int32_t* jk = JK + (int64_t)j[u] * K;
+                const int k0 = 8 * ww[u];
+                uint32_t word = 0;
+                if (quads && k0 + 8 <= K) {
+                    const int4 q0 = *reinterpret_cast<const int4*>(jk + k0);
+                    const int4 q1 = *reinterpret_cast<const int4*>(jk + k0 + 4);
+                    word = (uint32_t)map[q0.x] | (uint32_t)map[q0.y] << 4 | (uint32_t)map[q0.z] << 8 |
+                           (uint32_t)map[q0.w] << 12 | (uint32_t)map[q1.x] << 16 | (uint32_t)map[q1.y] << 20 |
+                           (uint32_t)map[q1.z] << 24 | (uint32_t)map[q1.w] << 28;
+                } else {
+                    for (int h = 0; h < 8 && k0 + h < K; ++h) word |= (uint32_t)map[jk[k0 + h]] << (4 * h);
+                }
+                *reinterpret_cast<uint32_t*>(nib + (int64_t)p[u] * nstride + 4 * ww[u]) = word;
+            }
         }
         __syncthreads();
         for (int32_t x = tid; x < deg; x += nt) map[csr_col[a + x]] = 0;
@@ -646,17 +659,17 @@ int neighbours_for(lshmf_ctx* c, int32_t j_first, int32_t count, uint64_t seed_f
 int stream_codes(lshmf_ctx* c, Stream& st, hipStream_t s)
 {
     if (st.n > 0 && c->d.K > 0) {
-        if (c->N <= kCodeMapMax && st.n * 4 >= c->nnz) {
-            // by user row: c->e2s (free outside a stream build) holds the
-            // stream position of every CSR entry
-            LSHMF_TRY(fill_i32(c->e2s, c->nnz, -1, s));
-            hipLaunchKernelGGL(k_stream_csr_pos, dim3(grid_for(st.n)), dim3(256), 0, s, st.pk, st.sj, st.n,
-                               c->row_ptr, c->csr_col, c->e2s);
-            LSHMF_LAUNCHED("k_stream_csr_pos");
+        if (c->N <= kCodeMapMax && st.n == c->nnz) {
+            // the stream is the store (no pair twice), so its ratings of user i
+            // are exactly CSR row i
+            hipLaunchKernelGGL(k_keys_user, dim3(grid_for(st.n)), dim3(256), 0, s, st.pk, st.n, c->sk[0], c->sv[0]);
+            LSHMF_LAUNCHED("k_keys_user");
+            int ri = 0;
+            LSHMF_TRY(radix_sort(c->sk, c->sv, st.n, bits_for((uint64_t)c->M), c->hist, c->scan_tmp, s, &ri));
             const size_t lds = sizeof(uint32_t) * (size_t)((c->N + 3) / 4);
             const unsigned grid = (unsigned)(c->M < 4096 ? (c->M > 0 ? c->M : 1) : 4096);
             hipLaunchKernelGGL(k_nbr_codes_rows, dim3(grid), dim3(256), lds, s, c->row_ptr, c->csr_col, c->csr_rc,
-                               c->M, c->N, c->e2s, c->t.JK, c->d.K, st.nib, c->nstride);
+                               c->M, c->N, c->sv[ri], st.sj, c->t.JK, c->d.K, st.nib, c->nstride);
             LSHMF_LAUNCHED("k_nbr_codes_rows");
         } else {
             hipLaunchKernelGGL(k_nbr_codes, dim3(grid_for(st.n * kWave, 256, 65536)), dim3(256), 0, s, st.pk,
