@@ -14,6 +14,7 @@ namespace lshmf {
 
 constexpr int kWave = 64;
 constexpr int kStreamPad = 64;  // zeroed records after the stream arrays (read-ahead of the SGD)
+constexpr int kLightNnz = 64;   // SGD blocks with at most this many ratings run in teams
 
 // ---------------------------------------------------------------- errors
 void set_error(const char* fmt, ...);
@@ -106,6 +107,7 @@ struct Stream {
     int64_t* seg_start;        // cap + 1
     int32_t* blk_slots;        // P*P               mailbox slots per block
     int32_t* blk_order;        // P*P               dispatch order of each stratum's blocks: most ratings first
+    int32_t* heavy;            // P                 blocks of each stratum with more than kLightNnz ratings
     int64_t n = 0;             // host copies after a build
     int64_t max_block_nnz = 0;
     int64_t max_block_slots = 0;

@@ -230,6 +230,22 @@ __global__ void k_keys_blkorder(const int64_t* blk_ptr, int64_t P, int pb, uint6
     }
 }
 
+// Blocks of each stratum with more than kLightNnz ratings: they come first in
+// the dispatch order, so a binary search over it finds where they end.
+__global__ void k_heavy_count(const int64_t* blk_ptr, const int32_t* blk_order, int64_t P, int32_t* heavy)
+{
+    for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < P; s += (int64_t)gridDim.x * blockDim.x) {
+        int64_t lo = 0, hi = P;
+        while (lo < hi) {
+            const int64_t mid = (lo + hi) >> 1;
+            const int64_t b = s * P + blk_order[s * P + mid];
+            if (blk_ptr[b + 1] - blk_ptr[b] > kLightNnz) lo = mid + 1;
+            else hi = mid;
+        }
+        heavy[s] = (int32_t)lo;
+    }
+}
+
 __global__ void k_block_slots(const int64_t* blk_ptr, const int64_t* ex, int64_t nblk, int32_t* out)
 {
     for (int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; b < nblk;
@@ -608,6 +624,8 @@ int build_stream_async(lshmf_ctx* c, Stream& st, const int32_t* u, const int32_t
         int ro = 0;
         LSHMF_TRY(radix_sort(c->sk, c->sv, P * P, pb + 32 + pb, c->hist, c->scan_tmp, s, &ro));
         LSHMF_HIP(hipMemcpyAsync(st.blk_order, c->sv[ro], sizeof(int32_t) * P * P, hipMemcpyDeviceToDevice, s));
+        hipLaunchKernelGGL(k_heavy_count, dim3(grid_for(P)), dim3(256), 0, s, st.blk_ptr, st.blk_order, P, st.heavy);
+        LSHMF_LAUNCHED("k_heavy_count");
     }
     // zero tails: the SGD kernel reads a few records past a run's end
     LSHMF_TRY(fill_i32(reinterpret_cast<int32_t*>(st.pk) + n, kStreamPad, 0, s));

@@ -28,6 +28,7 @@ constexpr int kGangWaves = kHelpers + 1;
 constexpr int kMaxGangs = 2;                     // gangs per block
 constexpr int kGangMin = 48;                     // shortest segment given a gang
 constexpr int kHG = 6;                           // ratings per helper pipeline stage
+constexpr int kTeam = 4;                         // light blocks per team workgroup
 // ring slots of a gang: a multiple of kHelpers, so that every slot belongs to
 // one helper, and 2 * kHG + 3 per helper, so that a helper can prepare two
 // stages ahead of the item wave
@@ -37,6 +38,7 @@ constexpr int kSpinLimit = 1 << 24;              // bounded wait: a broken hand-
 constexpr int kMaxMailboxBytes = 150 * 1024;     // mailbox part of a block's dynamic LDS
 constexpr int kMaxLdsBytes = 160 * 1024 - 256;   // all of it (static LDS aside)
 static_assert(kMaxGangs * kGangWaves <= kSgdWaves, "every gang role needs a wave");
+static_assert(kSgdWaves % kTeam == 0, "team members take equal shares of the waves");
 constexpr int kMaxChainPos = (1 << 14) - 1;      // link encoding limits
 constexpr int kMaxSlots = (1 << 16) - 2;
 
@@ -45,6 +47,7 @@ struct SgdArgs {
     const int64_t* blk_ptr;
     const int64_t* blk_seg;
     const int32_t* blk_order;  // P*P: block run by each workgroup of a stratum
+    const int32_t* heavy;      // P: blocks of each stratum run one per workgroup (the rest in teams)
     const int32_t* seg_col;
     const int64_t* seg_start;
     const float* nbr_b0;
@@ -62,6 +65,9 @@ struct SgdArgs {
     int F, K, P, nstride, s, slots;
     int upd;          // bit 0: update the user side {b_i, u_i}; bit 1: the item side {bh_j, v_j, w_j, c_j}
     int max_gangs;    // gangs the LDS holds (0: every segment is run by a single wave)
+    int team;         // light blocks per team workgroup (1: every block has a workgroup of its own)
+    int team_slots;   // mailbox slots of a team member (a light block has at most kLightNnz / 2)
+    int team_floats;  // floats of LDS per team member
     int ring_off;     // float offset of the gang rings in dynamic LDS
     int ring_rs;      // floats per ring slot: u (64 FP), rw (64 KP), cn (64 KP), zero-padded
     float inv_s;
@@ -95,40 +101,61 @@ __global__ __launch_bounds__(kSgdWaves* kWave) void k_sgd_stratum(SgdArgs a, con
 {
     // mailbox: slots + 1 rows (the last is a write sink) of F floats, b_i, sequence
     extern __shared__ float smem[];
-    __shared__ int next_seg;
+    __shared__ int next_seg[kTeam];
     const int F = a.F, K = a.K;
-    const int dummy = a.slots;
-    float* mb_u = smem;
-    float* mb_b = smem + (size_t)(dummy + 1) * F;
-    int* mb_seq = reinterpret_cast<int*>(mb_b + dummy + 1);
     const int lane = threadIdx.x & (kWave - 1);
-    const int64_t blk = (int64_t)a.s * a.P + a.blk_order[(int64_t)a.s * a.P + blockIdx.x];
-    const int64_t g0 = a.blk_seg[blk], g1 = a.blk_seg[blk + 1];
+    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));  // wave-uniform
+    // The first heavy[s] workgroups run one block each (the heaviest, with
+    // gangs); each later one runs a team of up to a.team light blocks, member m
+    // on waves [m W, (m+1) W) with a mailbox of its own.  Blocks of a stratum
+    // share no user and no item, so the members never interact.
+    const int64_t sP = (int64_t)a.s * a.P;
+    const int nh = a.team > 1 ? a.heavy[a.s] : a.P;
+    const bool in_team = (int)blockIdx.x >= nh;
+    const int member = in_team ? wv / (kSgdWaves / a.team) : 0;
+    int64_t blk = -1;  // -1: no block for this wave's member
+    if (!in_team) {
+        blk = sP + a.blk_order[sP + blockIdx.x];
+    } else {
+        const int64_t x = nh + ((int64_t)blockIdx.x - nh) * a.team + member;
+        if (x < a.P) blk = sP + a.blk_order[sP + x];
+    }
+    const int dummy = in_team ? a.team_slots : a.slots;
+    float* mb_u = smem + (in_team ? (size_t)member * a.team_floats : 0);
+    float* mb_b = mb_u + (size_t)(dummy + 1) * F;
+    int* mb_seq = reinterpret_cast<int*>(mb_b + dummy + 1);
+    const int64_t g0 = blk >= 0 ? a.blk_seg[blk] : 0, g1 = blk >= 0 ? a.blk_seg[blk + 1] : 0;
     const int nsegs = (int)(g1 - g0);
     // The first segments of the block, while long, each get a gang: an item
     // wave that keeps the item state and runs only the dependent update chain,
     // fed through an LDS ring by helper waves that load and prepare the
     // user-side inputs of every rating.
     int ngang = 0;
-    for (int k = 0; k < a.max_gangs && k < nsegs; ++k) {
+    for (int k = 0; !in_team && k < a.max_gangs && k < nsegs; ++k) {
         if (a.seg_start[g0 + k + 1] - a.seg_start[g0 + k] < kGangMin) break;
         ngang = k + 1;
     }
     const int RS = a.ring_rs;
     const int GS = kRing * (RS + 6);  // floats per gang: data, headers, ready, done
     float* rings = smem + a.ring_off;
-    for (int x = threadIdx.x; x <= dummy; x += blockDim.x) mb_seq[x] = 0;
-    for (int gi = 0; gi < ngang; ++gi) {
-        int* ready = reinterpret_cast<int*>(rings + (size_t)gi * GS + kRing * RS + kRing * 4);
-        for (int x = threadIdx.x; x < 2 * kRing; x += blockDim.x) ready[x] = 0;  // ready[] and done[]
+    if (!in_team) {
+        for (int x = threadIdx.x; x <= dummy; x += blockDim.x) mb_seq[x] = 0;
+        for (int gi = 0; gi < ngang; ++gi) {
+            int* ready = reinterpret_cast<int*>(rings + (size_t)gi * GS + kRing * RS + kRing * 4);
+            for (int x = threadIdx.x; x < 2 * kRing; x += blockDim.x) ready[x] = 0;  // ready[] and done[]
+        }
+        if (threadIdx.x == 0) next_seg[0] = ngang;
+    } else {
+        // each member's waves clear its own sequence words
+        const int wpm = kSgdWaves / a.team;
+        for (int x = (int)threadIdx.x - member * wpm * kWave; x <= dummy; x += wpm * kWave) mb_seq[x] = 0;
+        if (threadIdx.x < (unsigned)a.team) next_seg[threadIdx.x] = 0;
     }
-    if (threadIdx.x == 0) next_seg = ngang;
     __syncthreads();
     const float mu = (float)(*a.mu);
     const float inv_s = a.inv_s;
     const bool usr = (a.upd & 1) != 0;
     const bool itm = (a.upd & 2) != 0;
-    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));  // wave-uniform
 
     if (wv < ngang * kGangWaves) {
         // Ring protocol.  Helper h prepares ratings n = h, h + H, ... into
@@ -473,7 +500,7 @@ __global__ __launch_bounds__(kSgdWaves* kWave) void k_sgd_stratum(SgdArgs a, con
 
     while (true) {
         int g = 0;
-        if (lane == 0) g = atomicAdd(&next_seg, 1);
+        if (lane == 0) g = atomicAdd(&next_seg[member], 1);
         g = __builtin_amdgcn_readfirstlane(g);
         if (g >= nsegs) break;
         const int64_t seg = g0 + g;
@@ -730,7 +757,9 @@ static int kp_of(int K) { return K > kWave ? 2 : 1; }
 static size_t sgd_lds_bytes(const SgdArgs& args)
 {
     const size_t gs = (size_t)kRing * (args.ring_rs + 6);
-    return ((size_t)args.ring_off + (size_t)args.max_gangs * gs) * sizeof(float);
+    const size_t one = ((size_t)args.ring_off + (size_t)args.max_gangs * gs) * sizeof(float);
+    const size_t team = (size_t)args.team * (size_t)args.team_floats * sizeof(float);
+    return one > team ? one : team;
 }
 
 template <int FP, int KP, bool UB>
@@ -807,7 +836,16 @@ int run_sgd(lshmf_ctx* c, Stream& st, const lshmf_hparams* hp, int epoch, int up
     a.ring_off = (int)(((st.max_block_slots + 1) * (d.F + 2) + 3) & ~3LL);
     a.ring_rs = kWave * (fp_of(d.F) + 2 * kp_of(d.K));
     a.max_gangs = kMaxGangs;
+    a.team = 1;
+    a.team_slots = kLightNnz / 2;
+    a.team_floats = (int)(((int64_t)(a.team_slots + 1) * (d.F + 2) + 3) & ~3LL);
     while (a.max_gangs > 0 && sgd_lds_bytes(a) > (size_t)kMaxLdsBytes) --a.max_gangs;
+    // light blocks in teams where their mailboxes fit in the block's LDS
+    a.heavy = st.heavy;
+    for (int t = kTeam; t > 1 && a.team == 1; t /= 2) {
+        a.team = t;
+        if (sgd_lds_bytes(a) > (size_t)kMaxLdsBytes) a.team = 1;
+    }
     // Eq. (learn_rate): gamma_t = alpha / (1 + beta * t^1.5)
     const double den = 1.0 + (double)hp->beta * std::pow((double)epoch, 1.5);
     for (int x = 0; x < 6; ++x) {
