@@ -154,8 +154,6 @@ __global__ __launch_bounds__(kSgdWaves* kWave) void k_sgd_stratum(SgdArgs a, con
     __syncthreads();
     const float mu = (float)(*a.mu);
     const float inv_s = a.inv_s;
-    const bool usr = (a.upd & 1) != 0;
-    const bool itm = (a.upd & 2) != 0;
 
     if (wv < ngang * kGangWaves) {
         // Ring protocol.  Helper h prepares ratings n = h, h + H, ... into
@@ -211,54 +209,48 @@ __global__ __launch_bounds__(kSgdWaves* kWave) void k_sgd_stratum(SgdArgs a, con
                 }
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
             };
-            float pu[kIG][FP], prw[kIG][KP], pcn[kIG][KP];
-            float preff = 0.0f, pbi = 0.0f;  // lane t: r - mu - b_i and b_i of rating gs + t
-            int pi = 0, plw = 0;               // lane t: user and hand-over word of rating gs + t
+            // Inputs of a group from the ring.  Two of them alternate, one
+            // computed while the other is loaded, so nothing is copied.
+            struct IBuf {
+                float u[kIG][FP], rw[kIG][KP], cn[kIG][KP];
+                float reff, bi;  // lane t: r - mu - b_i and b_i of rating gs + t
+                int i, lw;       // lane t: user and hand-over word of rating gs + t
+            };
             // Slot sections are whole multiples of 64 floats, zero past F and
             // K, so every lane loads straight into its register (no selects:
             // the loads of a group issue back to back).
-            auto load_group = [&](int gs, int cnt) {
+            auto load_group = [&](IBuf& B, int gs, int cnt) {
 #pragma unroll
                 for (int t = 0; t < kIG; ++t) {
                     const float* d = rdata + ((gs + t) % kRing) * RS + lane;
 #pragma unroll
-                    for (int x = 0; x < FP; ++x) pu[t][x] = d[x * kWave];
+                    for (int x = 0; x < FP; ++x) B.u[t][x] = d[x * kWave];
 #pragma unroll
                     for (int y = 0; y < KP; ++y) {
-                        prw[t][y] = d[(FP + y) * kWave];
-                        pcn[t][y] = d[(FP + KP + y) * kWave];
+                        B.rw[t][y] = d[(FP + y) * kWave];
+                        B.cn[t][y] = d[(FP + KP + y) * kWave];
                     }
                 }
                 const int* hd = rhdr + ((gs + (lane < cnt ? lane : 0)) % kRing) * 4;
-                preff = __int_as_float(hd[0]);
-                pbi = __int_as_float(hd[1]);
-                pi = hd[2];
-                plw = hd[3];
+                B.reff = __int_as_float(hd[0]);
+                B.bi = __int_as_float(hd[1]);
+                B.i = hd[2];
+                B.lw = hd[3];
             };
-            wait_group(0, len < kIG ? len : kIG);
-            load_group(0, len < kIG ? len : kIG);
-            for (int gs = 0; gs < len; gs += kIG) {
+            // the last feature pass is the only one with lanes past F
+            const bool last_full = F == FP * kWave;
+            // One group: Eq. (rr) and Eq. (sgd_update) for its ratings in order,
+            // the next group's inputs loaded into N when they are already there,
+            // then the group published.  The rates of a side that is not
+            // updated are zero, so its parameters keep their values exactly.
+            auto run_group = [&](IBuf& B, IBuf& N, int gs) {
                 const int cnt = len - gs < kIG ? len - gs : kIG;
-                float u[kIG][FP], rw[kIG][KP], cn[kIG][KP];
-#pragma unroll
-                for (int t = 0; t < kIG; ++t) {
-#pragma unroll
-                    for (int x = 0; x < FP; ++x) u[t][x] = pu[t][x];
-#pragma unroll
-                    for (int y = 0; y < KP; ++y) {
-                        rw[t][y] = prw[t][y];
-                        cn[t][y] = pcn[t][y];
-                    }
-                }
-                const float reff_v = preff, bi_v = pbi;
-                const int i_v = pi, lw_v = plw;
-                // the next group's inputs, if they are already there
                 const int gn = gs + kIG;
                 const int cntn = len - gn < kIG ? len - gn : kIG;
                 bool have_next = false;
                 if (gn < len && group_ready(gn, cntn)) {
                     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
-                    load_group(gn, cntn);
+                    load_group(N, gn, cntn);
                     have_next = true;
                 }
                 float errv = 0.0f;  // lane t: error of rating gs + t
@@ -266,18 +258,18 @@ __global__ __launch_bounds__(kSgdWaves* kWave) void k_sgd_stratum(SgdArgs a, con
                 for (int t = 0; t < kIG; ++t) {
                     if (t >= cnt) break;
                     const float reff = __builtin_bit_cast(
-                        float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, reff_v), t));
+                        float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, B.reff), t));
                     float part = 0.0f;
 #pragma unroll
-                    for (int x = 0; x < FP; ++x) part += u[t][x] * v[x];
+                    for (int x = 0; x < FP; ++x) part += B.u[t][x] * v[x];
 #pragma unroll
-                    for (int y = 0; y < KP; ++y) part += rw[t][y] * w[y] + cn[t][y] * c[y];
+                    for (int y = 0; y < KP; ++y) part += B.rw[t][y] * w[y] + B.cn[t][y] * c[y];
                     const float err = reff - (bh + wave_sum(part));
                     errv = lane == t ? err : errv;
                     // u_i's new row: to the mailbox for the user's next rating in
                     // the block, else to HBM (the other store goes to a sink)
-                    const int64_t i = (int64_t)__builtin_amdgcn_readlane(i_v, t);
-                    const uint32_t lw = (uint32_t)__builtin_amdgcn_readlane(lw_v, t);
+                    const int64_t i = (int64_t)__builtin_amdgcn_readlane(B.i, t);
+                    const uint32_t lw = (uint32_t)__builtin_amdgcn_readlane(B.lw, t);
                     const bool has_succ = (lw >> 31) != 0;
                     const int ws = has_succ ? (int)(lw & 0xFFFFu) : dummy;
                     // wave-uniform destinations: the HBM row or a sink row (FP32,
@@ -289,41 +281,40 @@ __global__ __launch_bounds__(kSgdWaves* kWave) void k_sgd_stratum(SgdArgs a, con
 #pragma unroll
                     for (int x = 0; x < FP; ++x) {
                         const int f = lane + x * kWave;
-                        const float unew = usr ? u[t][x] + a.g[2] * (err * v[x] - a.l[2] * u[t][x]) : u[t][x];
-                        if (f < F) {
+                        const float uo = B.u[t][x];
+                        const float unew = uo + a.g[2] * (err * v[x] - a.l[2] * uo);
+                        if (x < FP - 1 || last_full || f < F) {
                             mrow[f] = unew;
                             if constexpr (UB) hrow[f] = to_bf16(unew);
                             else urow[f] = unew;
                         }
-                        const float vn = v[x] + a.g[3] * (err * u[t][x] - a.l[3] * v[x]);
-                        v[x] = itm ? vn : v[x];
+                        v[x] = v[x] + a.g[3] * (err * uo - a.l[3] * v[x]);
                     }
-                    const float bh_new = bh + a.g[1] * (err - a.l[1] * bh);
-                    bh = itm ? bh_new : bh;
+                    bh = bh + a.g[1] * (err - a.l[1] * bh);
 #pragma unroll
                     for (int y = 0; y < KP; ++y) {
                         // an explicit slot has cn == 0; padding slots stay zero either way
-                        const bool rs = cn[t][y] == 0.0f;
-                        const float wn = w[y] + a.g[4] * (err * rw[t][y] - a.l[4] * w[y]);
-                        const float cnn = c[y] + a.g[5] * (err * cn[t][y] - a.l[5] * c[y]);
-                        w[y] = (itm && rs) ? wn : w[y];
-                        c[y] = (itm && !rs) ? cnn : c[y];
+                        const bool rs = B.cn[t][y] == 0.0f;
+                        const float wn = w[y] + a.g[4] * (err * B.rw[t][y] - a.l[4] * w[y]);
+                        const float cnn = c[y] + a.g[5] * (err * B.cn[t][y] - a.l[5] * c[y]);
+                        w[y] = rs ? wn : w[y];
+                        c[y] = rs ? c[y] : cnn;
                     }
                 }
                 // publish the group (lane t: rating gs + t): b_i to the mailbox or
                 // HBM, then the hand-over sequence numbers and the done flags
                 {
                     const bool live = lane < cnt;
-                    const bool succ = live && ((uint32_t)lw_v >> 31) != 0;
-                    const int ws = succ ? (lw_v & 0xFFFF) : dummy;
-                    const float bnew = usr ? bi_v + a.g[0] * (errv - a.l[0] * bi_v) : bi_v;
+                    const bool succ = live && ((uint32_t)B.lw >> 31) != 0;
+                    const int ws = succ ? (B.lw & 0xFFFF) : dummy;
+                    const float bnew = B.bi + a.g[0] * (errv - a.l[0] * B.bi);
                     if (live) {
                         mb_b[ws] = bnew;
-                        *(succ ? a.trash + 2 * kWave * FP + lane : a.bu + i_v) = bnew;
+                        *(succ ? a.trash + 2 * kWave * FP + lane : a.bu + B.i) = bnew;
                     }
                     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
                     if (live) {
-                        __hip_atomic_store(&mb_seq[ws], ((lw_v >> 16) & 0x3FFF) + 1, __ATOMIC_RELAXED,
+                        __hip_atomic_store(&mb_seq[ws], ((B.lw >> 16) & 0x3FFF) + 1, __ATOMIC_RELAXED,
                                            __HIP_MEMORY_SCOPE_WORKGROUP);
                         __hip_atomic_store(&rdone[(gs + lane) % kRing], gs + lane + 1, __ATOMIC_RELAXED,
                                            __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -331,8 +322,17 @@ __global__ __launch_bounds__(kSgdWaves* kWave) void k_sgd_stratum(SgdArgs a, con
                 }
                 if (gn < len && !have_next) {
                     wait_group(gn, cntn);
-                    load_group(gn, cntn);
+                    load_group(N, gn, cntn);
                 }
+            };
+            IBuf BA, BB;
+            wait_group(0, len < kIG ? len : kIG);
+            load_group(BA, 0, len < kIG ? len : kIG);
+            for (int gs = 0;; gs += 2 * kIG) {
+                run_group(BA, BB, gs);
+                if (gs + kIG >= len) break;
+                run_group(BB, BA, gs + kIG);
+                if (gs + 2 * kIG >= len) break;
             }
             __builtin_amdgcn_s_setprio(0);
 #pragma unroll
@@ -661,16 +661,16 @@ __global__ __launch_bounds__(kSgdWaves* kWave) void k_sgd_stratum(SgdArgs a, con
                 // every lane issues the same stores without branches.
                 const bool to_hbm = valid && !has_succ;
                 const int ws = has_succ ? slot : dummy;
-                const float bnew = usr ? bi + a.g[0] * (err - a.l[0] * bi) : bi;
+                const float bnew = bi + a.g[0] * (err - a.l[0] * bi);
                 float* bsink = a.trash + 2 * kWave * FP;
                 *((lane == 0 && to_hbm) ? a.bu + i : bsink + lane) = bnew;
                 mb_b[lane == 0 ? ws : dummy] = bnew;
                 const float bh_new = bh + a.g[1] * (err - a.l[1] * bh);
-                bh = (valid && itm) ? bh_new : bh;
+                bh = valid ? bh_new : bh;
 #pragma unroll
                 for (int x = 0; x < FP; ++x) {
                     const int f = lane + x * kWave;
-                    const float unew = usr ? u[x] + a.g[2] * (err * v[x] - a.l[2] * u[x]) : u[x];
+                    const float unew = u[x] + a.g[2] * (err * v[x] - a.l[2] * u[x]);
                     if constexpr (UB) {
                         uint16_t* hs = reinterpret_cast<uint16_t*>(a.trash + 3 * kWave * FP);
                         *((to_hbm && f < F) ? a.U16 + i * F + f : hs + f) = to_bf16(unew);
@@ -679,15 +679,15 @@ __global__ __launch_bounds__(kSgdWaves* kWave) void k_sgd_stratum(SgdArgs a, con
                     }
                     mb_u[f < F ? ws * F + f : dummy * F] = unew;
                     const float vn = v[x] + a.g[3] * (err * u[x] - a.l[3] * v[x]);
-                    v[x] = (valid && itm) ? vn : v[x];
+                    v[x] = valid ? vn : v[x];
                 }
 #pragma unroll
                 for (int y = 0; y < KP; ++y) {
                     const bool in_k = lane + y * kWave < K;
                     const float wn = w[y] + a.g[4] * (sR * err * resid[y] - a.l[4] * w[y]);
                     const float cn = c[y] + a.g[5] * (sN * err - a.l[5] * c[y]);
-                    w[y] = (valid && itm && in_k && code[y]) ? wn : w[y];
-                    c[y] = (valid && itm && in_k && !code[y]) ? cn : c[y];
+                    w[y] = (valid && in_k && code[y]) ? wn : w[y];
+                    c[y] = (valid && in_k && !code[y]) ? cn : c[y];
                 }
             }
             // the mailbox rows are written: publish their sequence numbers
@@ -855,6 +855,9 @@ int run_sgd(lshmf_ctx* c, Stream& st, const lshmf_hparams* hp, int epoch, int up
     // plain MF (Alg. CUSGD++'s model, rhat = u . v): no biases to learn; with
     // zero rates the bias updates leave b and bh exactly at their zero start
     if (d.model == LSHMF_PLAIN_MF) a.g[0] = a.g[1] = 0.0f;
+    // a side that is not updated gets zero rates: x + 0 * (...) == x exactly
+    if (!(upd & 1)) a.g[0] = a.g[2] = 0.0f;
+    if (!(upd & 2)) a.g[1] = a.g[3] = a.g[4] = a.g[5] = 0.0f;
     const int fp = (d.F + kWave - 1) / kWave;
     for (int stratum = 0; stratum < c->P; ++stratum) {
         a.s = stratum;
