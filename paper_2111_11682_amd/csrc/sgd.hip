@@ -24,7 +24,7 @@ namespace lshmf {
 constexpr int kSgdWaves = 16;
 constexpr int kGroup = 4;                        // ratings per pipeline stage
 constexpr int kHelpers = 4;                      // helper waves of a gang
-constexpr int kGangWaves = kHelpers + 1;
+constexpr int kGangWaves = kHelpers + 2;         // item wave, helpers, writer wave
 constexpr int kMaxGangs = 2;                     // gangs per block
 constexpr int kGangMin = 48;                     // shortest segment given a gang
 constexpr int kHG = 6;                           // ratings per helper pipeline stage
@@ -77,6 +77,14 @@ struct SgdArgs {
 // User-side HBM inputs of one group of ratings, loaded a group ahead of use.
 // A user rated earlier in the same block is read from the block's LDS mailbox
 // instead, when its rating is computed.
+// One parameter update of Eq. (sgd_update), x + g (e q - l x), as the item wave
+// and the writer wave of a gang both evaluate it: the writer replays the item
+// wave's updates of v_j and must reach the same values bit for bit.
+__device__ __forceinline__ float sgd_step(float x, float g, float e, float q, float l)
+{
+    return __builtin_fmaf(g, __builtin_fmaf(e, q, -(l * x)), x);
+}
+
 template <int FP, int KP>
 struct Stage {
     float gu[kGroup][FP];
@@ -136,13 +144,13 @@ __global__ __launch_bounds__(kSgdWaves* kWave) void k_sgd_stratum(SgdArgs a, con
         ngang = k + 1;
     }
     const int RS = a.ring_rs;
-    const int GS = kRing * (RS + 6);  // floats per gang: data, headers, ready, done
+    const int GS = kRing * (RS + 7) + 4;  // floats per gang: data, headers, ready, done, errors, count
     float* rings = smem + a.ring_off;
     if (!in_team) {
         for (int x = threadIdx.x; x <= dummy; x += blockDim.x) mb_seq[x] = 0;
         for (int gi = 0; gi < ngang; ++gi) {
             int* ready = reinterpret_cast<int*>(rings + (size_t)gi * GS + kRing * RS + kRing * 4);
-            for (int x = threadIdx.x; x < 2 * kRing; x += blockDim.x) ready[x] = 0;  // ready[] and done[]
+            for (int x = threadIdx.x; x < 3 * kRing + 1; x += blockDim.x) ready[x] = 0;  // ready, done, err, count
         }
         if (threadIdx.x == 0) next_seg[0] = ngang;
     } else {
@@ -158,13 +166,14 @@ __global__ __launch_bounds__(kSgdWaves* kWave) void k_sgd_stratum(SgdArgs a, con
     if (wv < ngang * kGangWaves) {
         // Ring protocol.  Helper h prepares ratings n = h, h + H, ... into
         // slot n % kRing and sets ready; the item wave runs each group of kIG
-        // ratings, writes each u_i's new row to the mailbox (the user rates
-        // again later in the block) or to HBM, then publishes b_i, the
-        // hand-over sequence numbers and done for the group.  A slot is
-        // reused by the same helper kRing / H of its ratings later, once the
-        // slot's previous rating is done.  The item wave waits only after
-        // publishing all it has done, and a helper waits only for ratings
-        // below those it prepares, so every wait ends.
+        // ratings (the dependent chain of v_j, bh_j, w_j, c_j) and publishes
+        // the group's errors; the writer wave then writes each u_i's new row
+        // to the mailbox (the user rates again later in the block) or to HBM,
+        // b_i, the hand-over sequence numbers and done.  A slot is reused by
+        // the same helper kRing / H of its ratings later, once the slot's
+        // previous rating is done.  The item wave waits only for ready slots
+        // and the writer only for published errors, both of ratings the
+        // helpers prepare without waiting on them, so every wait ends.
         const int gang = wv / kGangWaves, role = wv % kGangWaves;
         const int64_t seg = g0 + gang;
         const int64_t j = a.seg_col[seg];
@@ -174,6 +183,8 @@ __global__ __launch_bounds__(kSgdWaves* kWave) void k_sgd_stratum(SgdArgs a, con
         int* rhdr = reinterpret_cast<int*>(rdata + kRing * RS);
         int* rready = rhdr + kRing * 4;
         int* rdone = rready + kRing;
+        float* rerr = reinterpret_cast<float*>(rdone + kRing);
+        int* rcount = reinterpret_cast<int*>(rerr + kRing);  // ratings whose errors are published
         if (role == 0) {
             // ---- item wave: Eq. (rr) and Eq. (sgd_update) in stream order
             __builtin_amdgcn_s_setprio(3);
@@ -213,8 +224,7 @@ __global__ __launch_bounds__(kSgdWaves* kWave) void k_sgd_stratum(SgdArgs a, con
             // computed while the other is loaded, so nothing is copied.
             struct IBuf {
                 float u[kIG][FP], rw[kIG][KP], cn[kIG][KP];
-                float reff, bi;  // lane t: r - mu - b_i and b_i of rating gs + t
-                int i, lw;       // lane t: user and hand-over word of rating gs + t
+                float reff;  // lane t: r - mu - b_i of rating gs + t
             };
             // Slot sections are whole multiples of 64 floats, zero past F and
             // K, so every lane loads straight into its register (no selects:
@@ -231,18 +241,13 @@ __global__ __launch_bounds__(kSgdWaves* kWave) void k_sgd_stratum(SgdArgs a, con
                         B.cn[t][y] = d[(FP + KP + y) * kWave];
                     }
                 }
-                const int* hd = rhdr + ((gs + (lane < cnt ? lane : 0)) % kRing) * 4;
-                B.reff = __int_as_float(hd[0]);
-                B.bi = __int_as_float(hd[1]);
-                B.i = hd[2];
-                B.lw = hd[3];
+                B.reff = __int_as_float(rhdr[((gs + (lane < cnt ? lane : 0)) % kRing) * 4]);
             };
-            // the last feature pass is the only one with lanes past F
-            const bool last_full = F == FP * kWave;
-            // One group: Eq. (rr) and Eq. (sgd_update) for its ratings in order,
-            // the next group's inputs loaded into N when they are already there,
-            // then the group published.  The rates of a side that is not
-            // updated are zero, so its parameters keep their values exactly.
+            // One group: Eq. (rr) and Eq. (sgd_update) of the item side for its
+            // ratings in order, the next group's inputs loaded into N when they
+            // are already there, then the group's errors published.  The rates
+            // of a side that is not updated are zero, so its parameters keep
+            // their values exactly.
             auto run_group = [&](IBuf& B, IBuf& N, int gs) {
                 const int cnt = len - gs < kIG ? len - gs : kIG;
                 const int gn = gs + kIG;
@@ -266,60 +271,23 @@ __global__ __launch_bounds__(kSgdWaves* kWave) void k_sgd_stratum(SgdArgs a, con
                     for (int y = 0; y < KP; ++y) part += B.rw[t][y] * w[y] + B.cn[t][y] * c[y];
                     const float err = reff - (bh + wave_sum(part));
                     errv = lane == t ? err : errv;
-                    // u_i's new row: to the mailbox for the user's next rating in
-                    // the block, else to HBM (the other store goes to a sink)
-                    const int64_t i = (int64_t)__builtin_amdgcn_readlane(B.i, t);
-                    const uint32_t lw = (uint32_t)__builtin_amdgcn_readlane(B.lw, t);
-                    const bool has_succ = (lw >> 31) != 0;
-                    const int ws = has_succ ? (int)(lw & 0xFFFFu) : dummy;
-                    // wave-uniform destinations: the HBM row or a sink row (FP32,
-                    // or BF16 with round to nearest even in storage mode BF16_U)
-                    float* urow = (has_succ || UB) ? a.trash + kWave * FP : a.U + i * F;
-                    uint16_t* hrow = (!has_succ && UB) ? a.U16 + i * F
-                                                          : reinterpret_cast<uint16_t*>(a.trash + 3 * kWave * FP);
-                    float* mrow = mb_u + ws * F;
 #pragma unroll
-                    for (int x = 0; x < FP; ++x) {
-                        const int f = lane + x * kWave;
-                        const float uo = B.u[t][x];
-                        const float unew = uo + a.g[2] * (err * v[x] - a.l[2] * uo);
-                        if (x < FP - 1 || last_full || f < F) {
-                            mrow[f] = unew;
-                            if constexpr (UB) hrow[f] = to_bf16(unew);
-                            else urow[f] = unew;
-                        }
-                        v[x] = v[x] + a.g[3] * (err * uo - a.l[3] * v[x]);
-                    }
-                    bh = bh + a.g[1] * (err - a.l[1] * bh);
+                    for (int x = 0; x < FP; ++x) v[x] = sgd_step(v[x], a.g[3], err, B.u[t][x], a.l[3]);
+                    bh = sgd_step(bh, a.g[1], err, 1.0f, a.l[1]);
 #pragma unroll
                     for (int y = 0; y < KP; ++y) {
                         // an explicit slot has cn == 0; padding slots stay zero either way
                         const bool rs = B.cn[t][y] == 0.0f;
-                        const float wn = w[y] + a.g[4] * (err * B.rw[t][y] - a.l[4] * w[y]);
-                        const float cnn = c[y] + a.g[5] * (err * B.cn[t][y] - a.l[5] * c[y]);
+                        const float wn = sgd_step(w[y], a.g[4], err, B.rw[t][y], a.l[4]);
+                        const float cnn = sgd_step(c[y], a.g[5], err, B.cn[t][y], a.l[5]);
                         w[y] = rs ? wn : w[y];
                         c[y] = rs ? c[y] : cnn;
                     }
                 }
-                // publish the group (lane t: rating gs + t): b_i to the mailbox or
-                // HBM, then the hand-over sequence numbers and the done flags
-                {
-                    const bool live = lane < cnt;
-                    const bool succ = live && ((uint32_t)B.lw >> 31) != 0;
-                    const int ws = succ ? (B.lw & 0xFFFF) : dummy;
-                    const float bnew = B.bi + a.g[0] * (errv - a.l[0] * B.bi);
-                    if (live) {
-                        mb_b[ws] = bnew;
-                        *(succ ? a.trash + 2 * kWave * FP + lane : a.bu + B.i) = bnew;
-                    }
-                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
-                    if (live) {
-                        __hip_atomic_store(&mb_seq[ws], ((B.lw >> 16) & 0x3FFF) + 1, __ATOMIC_RELAXED,
-                                           __HIP_MEMORY_SCOPE_WORKGROUP);
-                        __hip_atomic_store(&rdone[(gs + lane) % kRing], gs + lane + 1, __ATOMIC_RELAXED,
-                                           __HIP_MEMORY_SCOPE_WORKGROUP);
-                    }
-                }
+                // the group's errors, for the writer wave
+                if (lane < cnt) rerr[(gs + lane) % kRing] = errv;
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+                if (lane == 0) __hip_atomic_store(rcount, gs + cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
                 if (gn < len && !have_next) {
                     wait_group(gn, cntn);
                     load_group(N, gn, cntn);
@@ -349,6 +317,84 @@ __global__ __launch_bounds__(kSgdWaves* kWave) void k_sgd_stratum(SgdArgs a, con
                 if (k < K) {
                     a.W[j * K + k] = w[y];
                     a.C[j * K + k] = c[y];
+                }
+            }
+        } else if (role == kHelpers + 1) {
+            // ---- writer wave: the user side of each rating from the item
+            // wave's errors.  It replays v_j's updates (the same sgd_step on the
+            // same values) to have v_j as it was before every rating.
+            float v[FP];
+#pragma unroll
+            for (int x = 0; x < FP; ++x) {
+                const int f = lane + x * kWave;
+                v[x] = f < F ? a.V[j * F + f] : 0.0f;
+            }
+            bool dead = false;
+            for (int gs = 0; gs < len; gs += kIG) {
+                const int cnt = len - gs < kIG ? len - gs : kIG;
+                int spins = 0;
+                while (!dead && __builtin_amdgcn_readfirstlane(__hip_atomic_load(
+                                    rcount, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) < gs + cnt) {
+                    if (++spins > kSpinLimit) {
+                        if (lane == 0) atomicOr(a.err, 4);
+                        dead = true;
+                    }
+                    __builtin_amdgcn_s_sleep(1);
+                }
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+                // lane t: error, b_i, user and hand-over word of rating gs + t
+                const int sl_l = (gs + (lane < cnt ? lane : 0)) % kRing;
+                const float errv = rerr[sl_l];
+                const int* hd = rhdr + sl_l * 4;
+                const float bi_v = __int_as_float(hd[1]);
+                const int i_v = hd[2], lw_v = hd[3];
+#pragma unroll
+                for (int t = 0; t < kIG; ++t) {
+                    if (t >= cnt) break;
+                    const float err =
+                        __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, errv), t));
+                    const int64_t i = (int64_t)__builtin_amdgcn_readlane(i_v, t);
+                    const uint32_t lw = (uint32_t)__builtin_amdgcn_readlane(lw_v, t);
+                    const bool has_succ = (lw >> 31) != 0;
+                    const int ws = has_succ ? (int)(lw & 0xFFFFu) : dummy;
+                    // wave-uniform destinations: the mailbox row of the user's
+                    // next rating in the block, else the HBM row (FP32, or BF16
+                    // with round to nearest even in storage mode BF16_U); the
+                    // store that must not happen goes to a sink
+                    float* urow = (has_succ || UB) ? a.trash + kWave * FP : a.U + i * F;
+                    uint16_t* hrow = (!has_succ && UB) ? a.U16 + i * F
+                                                          : reinterpret_cast<uint16_t*>(a.trash + 3 * kWave * FP);
+                    float* mrow = mb_u + ws * F;
+                    const float* d = rdata + ((gs + t) % kRing) * RS + lane;
+#pragma unroll
+                    for (int x = 0; x < FP; ++x) {
+                        const int f = lane + x * kWave;
+                        const float uo = d[x * kWave];
+                        const float unew = sgd_step(uo, a.g[2], err, v[x], a.l[2]);
+                        if (f < F) {
+                            mrow[f] = unew;
+                            if constexpr (UB) hrow[f] = to_bf16(unew);
+                            else urow[f] = unew;
+                        }
+                        v[x] = sgd_step(v[x], a.g[3], err, uo, a.l[3]);
+                    }
+                }
+                // b_i to the mailbox or HBM, then the hand-over sequence numbers
+                // and the done flags (lane t: rating gs + t)
+                const bool live = lane < cnt;
+                const bool succ = live && ((uint32_t)lw_v >> 31) != 0;
+                const int ws = succ ? (lw_v & 0xFFFF) : dummy;
+                const float bnew = sgd_step(bi_v, a.g[0], errv, 1.0f, a.l[0]);
+                if (live) {
+                    mb_b[ws] = bnew;
+                    *(succ ? a.trash + 2 * kWave * FP + lane : a.bu + i_v) = bnew;
+                }
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+                if (live) {
+                    __hip_atomic_store(&mb_seq[ws], ((lw_v >> 16) & 0x3FFF) + 1, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_WORKGROUP);
+                    __hip_atomic_store(&rdone[(gs + lane) % kRing], gs + lane + 1, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_WORKGROUP);
                 }
             }
         } else {
@@ -756,7 +802,7 @@ static int kp_of(int K) { return K > kWave ? 2 : 1; }
 // a sequence word) and the gang rings.
 static size_t sgd_lds_bytes(const SgdArgs& args)
 {
-    const size_t gs = (size_t)kRing * (args.ring_rs + 6);
+    const size_t gs = (size_t)kRing * (args.ring_rs + 7) + 4;
     const size_t one = ((size_t)args.ring_off + (size_t)args.max_gangs * gs) * sizeof(float);
     const size_t team = (size_t)args.team * (size_t)args.team_floats * sizeof(float);
     return one > team ? one : team;
