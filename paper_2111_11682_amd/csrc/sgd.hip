@@ -323,6 +323,7 @@ __global__ __launch_bounds__(kSgdWaves* kWave) void k_sgd_stratum(SgdArgs a, con
             // ---- writer wave: the user side of each rating from the item
             // wave's errors.  It replays v_j's updates (the same sgd_step on the
             // same values) to have v_j as it was before every rating.
+            __builtin_amdgcn_s_setprio(2);
             float v[FP];
 #pragma unroll
             for (int x = 0; x < FP; ++x) {
@@ -371,7 +372,7 @@ __global__ __launch_bounds__(kSgdWaves* kWave) void k_sgd_stratum(SgdArgs a, con
                         const int f = lane + x * kWave;
                         const float uo = d[x * kWave];
                         const float unew = sgd_step(uo, a.g[2], err, v[x], a.l[2]);
-                        if (f < F) {
+                        if (x < FP - 1 || f < F) {  // only the last pass has lanes past F
                             mrow[f] = unew;
                             if constexpr (UB) hrow[f] = to_bf16(unew);
                             else urow[f] = unew;
@@ -397,6 +398,7 @@ __global__ __launch_bounds__(kSgdWaves* kWave) void k_sgd_stratum(SgdArgs a, con
                                        __HIP_MEMORY_SCOPE_WORKGROUP);
                 }
             }
+            __builtin_amdgcn_s_setprio(0);
         } else {
             // ---- helper wave h: ratings n = h, h + H, ... of the segment
             const int h = role - 1;

@@ -24,15 +24,23 @@ __device__ inline uint16_t to_bf16(float x)
 __device__ inline float from_bf16(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
 // Full 64-lane sum with DPP row operations; the total ends in lane 63 and is
-// broadcast through a scalar register.  Fixed association order.
+// broadcast through a scalar register.  Fixed association order.  The two
+// row_bcast steps are single DPP adds (the compiler would emit a move of zero,
+// a DPP move and an add for each); rows they leave disabled keep their value,
+// which lane 63 never reads.  The s_nop before each gives the DPP read the two
+// wait states a VALU result needs (the compiler does not look inside asm).
 __device__ inline float wave_sum(float v)
 {
     v += dpp_f32<0xB1, 0xF, true>(v);    // quad_perm [1,0,3,2]
     v += dpp_f32<0x4E, 0xF, true>(v);    // quad_perm [2,3,0,1]
     v += dpp_f32<0x141, 0xF, true>(v);   // row_half_mirror
     v += dpp_f32<0x140, 0xF, true>(v);   // row_mirror: every lane holds its row's sum
-    v += dpp_f32<0x142, 0xA, false>(v);  // row_bcast:15 into rows 1 and 3
-    v += dpp_f32<0x143, 0xC, false>(v);  // row_bcast:31 into rows 2 and 3
+    asm volatile(
+        "s_nop 1\n\t"
+        "v_add_f32_dpp %0, %0, %0 row_bcast:15 row_mask:0xa bank_mask:0xf\n\t"  // rows 1, 3 += lane 15, 47
+        "s_nop 1\n\t"
+        "v_add_f32_dpp %0, %0, %0 row_bcast:31 row_mask:0xc bank_mask:0xf"  // rows 2, 3 += lane 31
+        : "+v"(v));
     return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 63));
 }
 
