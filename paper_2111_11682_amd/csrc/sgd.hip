@@ -29,11 +29,15 @@ constexpr int kMaxGangs = 2;                     // gangs per block
 constexpr int kGangMin = 48;                     // shortest segment given a gang
 constexpr int kHG = 6;                           // ratings per helper pipeline stage
 constexpr int kTeam = 4;                         // light blocks per team workgroup
-// ring slots of a gang: a multiple of kHelpers, so that every slot belongs to
-// one helper, and 2 * kHG + 3 per helper, so that a helper can prepare two
-// stages ahead of the item wave
-constexpr int kRing = (2 * kHG + 3) * kHelpers;
 constexpr int kIG = 8;                           // ratings per item-wave group
+// ring slots of a gang: a power of two (slot = rating & (kRing - 1)) and a
+// multiple of kHelpers, so that every slot belongs to one helper, and of kIG,
+// so that no group wraps; at least 2 * kHG + 3 per helper, so that a helper
+// can prepare two stages ahead of the item wave
+constexpr int kRing = 64;
+static_assert((kRing & (kRing - 1)) == 0 && kRing % kHelpers == 0 && kRing % kIG == 0 &&
+                  kRing >= (2 * kHG + 3) * kHelpers,
+              "ring size");
 constexpr int kSpinLimit = 1 << 24;              // bounded wait: a broken hand-over ends the kernel
 constexpr int kMaxMailboxBytes = 150 * 1024;     // mailbox part of a block's dynamic LDS
 constexpr int kMaxLdsBytes = 160 * 1024 - 256;   // all of it (static LDS aside)
@@ -165,7 +169,7 @@ __global__ __launch_bounds__(kSgdWaves* kWave) void k_sgd_stratum(SgdArgs a, con
 
     if (wv < ngang * kGangWaves) {
         // Ring protocol.  Helper h prepares ratings n = h, h + H, ... into
-        // slot n % kRing and sets ready; the item wave runs each group of kIG
+        // slot n & (kRing - 1) and sets ready; the item wave runs each group of kIG
         // ratings (the dependent chain of v_j, bh_j, w_j, c_j) and publishes
         // the group's errors; the writer wave then writes each u_i's new row
         // to the mailbox (the user rates again later in the block) or to HBM,
@@ -204,7 +208,7 @@ __global__ __launch_bounds__(kSgdWaves* kWave) void k_sgd_stratum(SgdArgs a, con
             bool dead = false;  // after one failed wait, later waits are skipped so the kernel ends
             // lane t < cnt checks slot (g0 + t): are all kIG inputs of the group there?
             auto group_ready = [&](int gs, int cnt) {
-                const int sl = (gs + lane) % kRing;
+                const int sl = (gs + lane) & (kRing - 1);
                 const int want = gs + lane + 1;
                 const bool ok = lane >= cnt ||
                                 __hip_atomic_load(&rready[sl], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) == want;
@@ -232,7 +236,7 @@ __global__ __launch_bounds__(kSgdWaves* kWave) void k_sgd_stratum(SgdArgs a, con
             auto load_group = [&](IBuf& B, int gs, int cnt) {
 #pragma unroll
                 for (int t = 0; t < kIG; ++t) {
-                    const float* d = rdata + ((gs + t) % kRing) * RS + lane;
+                    const float* d = rdata + ((gs + t) & (kRing - 1)) * RS + lane;
 #pragma unroll
                     for (int x = 0; x < FP; ++x) B.u[t][x] = d[x * kWave];
 #pragma unroll
@@ -241,7 +245,7 @@ __global__ __launch_bounds__(kSgdWaves* kWave) void k_sgd_stratum(SgdArgs a, con
                         B.cn[t][y] = d[(FP + KP + y) * kWave];
                     }
                 }
-                B.reff = __int_as_float(rhdr[((gs + (lane < cnt ? lane : 0)) % kRing) * 4]);
+                B.reff = __int_as_float(rhdr[((gs + (lane < cnt ? lane : 0)) & (kRing - 1)) * 4]);
             };
             // One group: Eq. (rr) and Eq. (sgd_update) of the item side for its
             // ratings in order, the next group's inputs loaded into N when they
@@ -285,7 +289,7 @@ __global__ __launch_bounds__(kSgdWaves* kWave) void k_sgd_stratum(SgdArgs a, con
                     }
                 }
                 // the group's errors, for the writer wave
-                if (lane < cnt) rerr[(gs + lane) % kRing] = errv;
+                if (lane < cnt) rerr[(gs + lane) & (kRing - 1)] = errv;
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
                 if (lane == 0) __hip_atomic_store(rcount, gs + cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
                 if (gn < len && !have_next) {
@@ -344,11 +348,20 @@ __global__ __launch_bounds__(kSgdWaves* kWave) void k_sgd_stratum(SgdArgs a, con
                 }
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
                 // lane t: error, b_i, user and hand-over word of rating gs + t
-                const int sl_l = (gs + (lane < cnt ? lane : 0)) % kRing;
+                const int sl_l = (gs + (lane < cnt ? lane : 0)) & (kRing - 1);
                 const float errv = rerr[sl_l];
                 const int* hd = rhdr + sl_l * 4;
                 const float bi_v = __int_as_float(hd[1]);
                 const int i_v = hd[2], lw_v = hd[3];
+                // the group's u rows, all loads in flight at once (slots past
+                // cnt hold stale values that are never used)
+                float ug[kIG][FP];
+#pragma unroll
+                for (int t = 0; t < kIG; ++t) {
+                    const float* d = rdata + ((gs + t) & (kRing - 1)) * RS + lane;
+#pragma unroll
+                    for (int x = 0; x < FP; ++x) ug[t][x] = d[x * kWave];
+                }
 #pragma unroll
                 for (int t = 0; t < kIG; ++t) {
                     if (t >= cnt) break;
@@ -366,11 +379,10 @@ __global__ __launch_bounds__(kSgdWaves* kWave) void k_sgd_stratum(SgdArgs a, con
                     uint16_t* hrow = (!has_succ && UB) ? a.U16 + i * F
                                                           : reinterpret_cast<uint16_t*>(a.trash + 3 * kWave * FP);
                     float* mrow = mb_u + ws * F;
-                    const float* d = rdata + ((gs + t) % kRing) * RS + lane;
 #pragma unroll
                     for (int x = 0; x < FP; ++x) {
                         const int f = lane + x * kWave;
-                        const float uo = d[x * kWave];
+                        const float uo = ug[t][x];
                         const float unew = sgd_step(uo, a.g[2], err, v[x], a.l[2]);
                         if (x < FP - 1 || f < F) {  // only the last pass has lanes past F
                             mrow[f] = unew;
@@ -394,7 +406,7 @@ __global__ __launch_bounds__(kSgdWaves* kWave) void k_sgd_stratum(SgdArgs a, con
                 if (live) {
                     __hip_atomic_store(&mb_seq[ws], ((lw_v >> 16) & 0x3FFF) + 1, __ATOMIC_RELAXED,
                                        __HIP_MEMORY_SCOPE_WORKGROUP);
-                    __hip_atomic_store(&rdone[(gs + lane) % kRing], gs + lane + 1, __ATOMIC_RELAXED,
+                    __hip_atomic_store(&rdone[(gs + lane) & (kRing - 1)], gs + lane + 1, __ATOMIC_RELAXED,
                                        __HIP_MEMORY_SCOPE_WORKGROUP);
                 }
             }
@@ -452,7 +464,7 @@ __global__ __launch_bounds__(kSgdWaves* kWave) void k_sgd_stratum(SgdArgs a, con
                     const int tt = t0 + t;
                     if (tt >= nbw) break;
                     const int n = h + kHelpers * (mb + tt);
-                    const int sl = n % kRing;
+                    const int sl = n & (kRing - 1);
                     const uint32_t pw = S.pw[t], lw = S.lw[t];
                     // the slot's previous rating, n - kRing, must be done
                     if (n >= kRing) {
