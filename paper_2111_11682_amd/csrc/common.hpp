@@ -5,6 +5,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <vector>
 
 #include "lshmf.h"
 
@@ -107,7 +108,9 @@ struct Stream {
     int64_t* seg_start;        // cap + 1
     int32_t* blk_slots;        // P*P               mailbox slots per block
     int32_t* blk_order;        // P*P               dispatch order of each stratum's blocks: most ratings first
-    int32_t* heavy;            // P                 blocks of each stratum with more than kLightNnz ratings
+    int32_t* heavy;            // 2P                per stratum: blocks with more than kLightNnz ratings, then
+                               //                   blocks with any (both lead the dispatch order)
+    std::vector<int32_t> hcounts;  // host copy of heavy (2P), read with the statistics
     int64_t n = 0;             // host copies after a build
     int64_t max_block_nnz = 0;
     int64_t max_block_slots = 0;

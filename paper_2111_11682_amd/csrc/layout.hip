@@ -230,19 +230,23 @@ __global__ void k_keys_blkorder(const int64_t* blk_ptr, int64_t P, int pb, uint6
     }
 }
 
-// Blocks of each stratum with more than kLightNnz ratings: they come first in
-// the dispatch order, so a binary search over it finds where they end.
+// Per stratum, the blocks with more than kLightNnz ratings and the blocks with
+// any: both come first in the dispatch order (ratings descending), so binary
+// searches over it find where they end.
 __global__ void k_heavy_count(const int64_t* blk_ptr, const int32_t* blk_order, int64_t P, int32_t* heavy)
 {
     for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < P; s += (int64_t)gridDim.x * blockDim.x) {
-        int64_t lo = 0, hi = P;
-        while (lo < hi) {
-            const int64_t mid = (lo + hi) >> 1;
-            const int64_t b = s * P + blk_order[s * P + mid];
-            if (blk_ptr[b + 1] - blk_ptr[b] > kLightNnz) lo = mid + 1;
-            else hi = mid;
+        for (int h = 0; h < 2; ++h) {
+            const int64_t above = h == 0 ? kLightNnz : 0;
+            int64_t lo = 0, hi = P;
+            while (lo < hi) {
+                const int64_t mid = (lo + hi) >> 1;
+                const int64_t b = s * P + blk_order[s * P + mid];
+                if (blk_ptr[b + 1] - blk_ptr[b] > above) lo = mid + 1;
+                else hi = mid;
+            }
+            heavy[h * P + s] = (int32_t)lo;
         }
-        heavy[s] = (int32_t)lo;
     }
 }
 
@@ -660,6 +664,8 @@ int build_stream(lshmf_ctx* c, Stream& st, const int32_t* u, const int32_t* it, 
     if (n == 0) return LSHMF_OK;
     int64_t h[4] = {0, 0, 0, 0};
     LSHMF_HIP(hipMemcpyAsync(h, st.stats, sizeof(h), hipMemcpyDeviceToHost, s));
+    LSHMF_HIP(hipMemcpyAsync(st.hcounts.data(), st.heavy, sizeof(int32_t) * st.hcounts.size(),
+                             hipMemcpyDeviceToHost, s));
     LSHMF_TRY(sync_status(c, s));
     stream_finish(st, h);
     return LSHMF_OK;

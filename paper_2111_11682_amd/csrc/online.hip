@@ -121,8 +121,11 @@ static int check_and_layout(lshmf_ctx* c, const int32_t* u, const int32_t* it, c
     for (int k = 0; k < 3 && status == LSHMF_OK; ++k) {
         status = build_stream_async(c, c->phase[k], c->bat_u + off, c->bat_i + off, c->bat_rc + off, cnt[k], s);
         if (status == LSHMF_OK && cnt[k] > 0) {
-            const hipError_t e = hipMemcpyAsync(stats[k], c->phase[k].stats, sizeof(stats[k]),
-                                                hipMemcpyDeviceToHost, s);
+            Stream& ph = c->phase[k];
+            hipError_t e = hipMemcpyAsync(stats[k], ph.stats, sizeof(stats[k]), hipMemcpyDeviceToHost, s);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(ph.hcounts.data(), ph.heavy, sizeof(int32_t) * ph.hcounts.size(),
+                                   hipMemcpyDeviceToHost, s);
             if (e != hipSuccess) status = hip_fail(e, "hipMemcpyAsync(stream stats)");
         }
         off += cnt[k];

@@ -67,6 +67,7 @@ struct SgdArgs {
     float* trash;
     int32_t* err;
     int F, K, P, nstride, s, slots;
+    int grid;         // workgroups of this stratum's launch
     int upd;          // bit 0: update the user side {b_i, u_i}; bit 1: the item side {bh_j, v_j, w_j, c_j}
     int max_gangs;    // gangs the LDS holds (0: every segment is run by a single wave)
     int team;         // light blocks per team workgroup (1: every block has a workgroup of its own)
@@ -831,8 +832,8 @@ static int launch_sgd(const SgdArgs& args, const uint32_t* pk, const uint32_t* l
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return hip_fail(e, "hipFuncSetAttribute(k_sgd_stratum)");
     }
-    hipLaunchKernelGGL((k_sgd_stratum<FP, KP, UB>), dim3((unsigned)args.P), dim3(kSgdWaves * kWave), lds, s, args,
-                       pk, link);
+    hipLaunchKernelGGL((k_sgd_stratum<FP, KP, UB>), dim3((unsigned)args.grid), dim3(kSgdWaves * kWave), lds, s,
+                       args, pk, link);
     LSHMF_LAUNCHED("k_sgd_stratum");
     return LSHMF_OK;
 }
@@ -919,8 +920,14 @@ int run_sgd(lshmf_ctx* c, Stream& st, const lshmf_hparams* hp, int epoch, int up
     if (!(upd & 1)) a.g[0] = a.g[2] = 0.0f;
     if (!(upd & 2)) a.g[1] = a.g[3] = a.g[4] = a.g[5] = 0.0f;
     const int fp = (d.F + kWave - 1) / kWave;
-    for (int stratum = 0; stratum < c->P; ++stratum) {
+    const int P = c->P;
+    for (int stratum = 0; stratum < P; ++stratum) {
+        // workgroups: the heavy blocks one each, the other non-empty blocks in
+        // teams; a stratum without ratings is not launched
+        const int nh = st.hcounts[stratum], ne = st.hcounts[P + stratum];
+        if (ne == 0) continue;
         a.s = stratum;
+        a.grid = a.team > 1 ? nh + (ne - nh + a.team - 1) / a.team : ne;
         switch (fp) {
             case 1: LSHMF_TRY(launch_sgd_k<1>(a, st.pk, st.link, s)); break;
             case 2: LSHMF_TRY(launch_sgd_k<2>(a, st.pk, st.link, s)); break;
