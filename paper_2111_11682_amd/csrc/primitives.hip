@@ -173,60 +173,99 @@ __global__ __launch_bounds__(kRsThreads) void k_rs_hist(const uint64_t* keys, in
     hist[(int64_t)threadIdx.x * ntiles + blockIdx.x] = cnt[threadIdx.x];
 }
 
-// Stable scatter: keys of a tile are ranked in their original order.  Each
-// round handles 256 consecutive keys (thread t takes the t-th); the rank of a
-// key among equal digits is (keys of earlier rounds) + (earlier waves of this
-// round) + (lower lanes of its own wave).
+// Stable scatter of one tile.  Wave w ranks keys [w * 1024, (w + 1) * 1024) of
+// the tile in rounds of 64: lanes with equal digits find each other with 8
+// ballots, and a key's rank among its wave's equal digits is the wave's count
+// so far plus the lanes below it.  The tile is then sorted by digit in LDS
+// (digit start + earlier waves' counts + rank) and written out in that order,
+// so a digit's keys of the tile go to consecutive addresses.
+constexpr int kRsRounds = kRsTile / (kRsThreads / kWave) / kWave;  // rounds of 64 keys per wave
+
 __global__ __launch_bounds__(kRsThreads) void k_rs_scatter(const uint64_t* kin, const uint32_t* vin,
                                                            uint64_t* kout, uint32_t* vout, int64_t n,
                                                            int shift, const int64_t* offs,
                                                            int64_t ntiles)
 {
     constexpr int kWaves = kRsThreads / kWave;
-    __shared__ int64_t base[kRsBins];
-    __shared__ int wcnt[kWaves][kRsBins];
+    __shared__ uint64_t skey[kRsTile];
+    __shared__ uint32_t sval[kRsTile];
+    __shared__ int wcnt[kWaves][kRsBins];  // per wave: digit counts, then the digit's first slot
+    __shared__ int lstart[kRsBins];        // first slot of each digit in the sorted tile
+    __shared__ int wsum[kWaves];
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
-    base[tid] = offs[(int64_t)tid * ntiles + blockIdx.x];
     for (int w = 0; w < kWaves; ++w) wcnt[w][tid] = 0;
     __syncthreads();
     const int64_t tile0 = (int64_t)blockIdx.x * kRsTile;
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
-    for (int r = 0; r < kRsItems; ++r) {
-        const int64_t x = tile0 + (int64_t)r * kRsThreads + tid;
+    uint64_t key[kRsRounds];
+    uint32_t val[kRsRounds];
+    int rank[kRsRounds];
+#pragma unroll
+    for (int r = 0; r < kRsRounds; ++r) {
+        const int64_t x = tile0 + (int64_t)wave * (kRsRounds * kWave) + r * kWave + lane;
         const bool valid = x < n;
-        uint64_t key = 0;
-        uint32_t val = 0;
-        int d = 0;
-        if (valid) {
-            key = kin[x];
-            val = vin[x];
-            d = (int)((key >> shift) & (kRsBins - 1));
-        }
-        // lanes of this wave with the same digit
+        key[r] = valid ? kin[x] : 0ull;
+        val[r] = valid ? vin[x] : 0u;
+    }
+#pragma unroll
+    for (int r = 0; r < kRsRounds; ++r) {
+        const int64_t x = tile0 + (int64_t)wave * (kRsRounds * kWave) + r * kWave + lane;
+        const bool valid = x < n;
+        const int d = (int)((key[r] >> shift) & (kRsBins - 1));
         uint64_t same = __ballot(valid);
 #pragma unroll
         for (int b = 0; b < 8; ++b) {
             const uint64_t bal = __ballot(valid && ((d >> b) & 1));
             same &= ((d >> b) & 1) ? bal : ~bal;
         }
-        const int rank_w = __popcll(same & lt_mask);
-        const bool leader = valid && rank_w == 0;
-        if (leader) wcnt[wave][d] = __popcll(same);
-        __syncthreads();
-        if (valid) {
-            int64_t pos = base[d] + rank_w;
-            for (int w = 0; w < wave; ++w) pos += wcnt[w][d];
-            kout[pos] = key;
-            vout[pos] = val;
+        const int below = __popcll(same & lt_mask);
+        const int before = valid ? wcnt[wave][d] : 0;  // read by all lanes before the leader adds
+        rank[r] = before + below;
+        if (valid && below == 0) wcnt[wave][d] = before + __popcll(same);
+    }
+    __syncthreads();
+    // thread tid = digit: the tile's count, its first slot (scan over digits)
+    // and each wave's first slot within the digit
+    int tot = 0;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) tot += wcnt[w][tid];
+    int incl = tot;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        const int y = __shfl_up(incl, o, kWave);
+        if (lane >= o) incl += y;
+    }
+    if (lane == kWave - 1) wsum[wave] = incl;
+    __syncthreads();
+    int start = incl - tot;
+    for (int w = 0; w < wave; ++w) start += wsum[w];
+    lstart[tid] = start;
+    int acc = start;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) {
+        const int c = wcnt[w][tid];
+        wcnt[w][tid] = acc;
+        acc += c;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kRsRounds; ++r) {
+        const int64_t x = tile0 + (int64_t)wave * (kRsRounds * kWave) + r * kWave + lane;
+        if (x < n) {
+            const int d = (int)((key[r] >> shift) & (kRsBins - 1));
+            const int pos = wcnt[wave][d] + rank[r];
+            skey[pos] = key[r];
+            sval[pos] = val[r];
         }
-        __syncthreads();
-        int add = 0;
-        for (int w = 0; w < kWaves; ++w) {
-            add += wcnt[w][tid];
-            wcnt[w][tid] = 0;
-        }
-        base[tid] += add;
-        __syncthreads();
+    }
+    __syncthreads();
+    const int64_t tile_n = n - tile0 < kRsTile ? n - tile0 : kRsTile;
+    for (int p = tid; p < tile_n; p += kRsThreads) {
+        const uint64_t k = skey[p];
+        const int d = (int)((k >> shift) & (kRsBins - 1));
+        const int64_t g = offs[(int64_t)d * ntiles + blockIdx.x] + (p - lstart[d]);
+        kout[g] = k;
+        vout[g] = sval[p];
     }
 }
 
