@@ -51,7 +51,6 @@ struct SgdArgs {
     const int64_t* blk_ptr;
     const int64_t* blk_seg;
     const int32_t* blk_order;  // P*P: block run by each workgroup of a stratum
-    const int32_t* heavy;      // P: blocks of each stratum run one per workgroup (the rest in teams)
     const int32_t* seg_col;
     const int64_t* seg_start;
     const float* nbr_b0;
@@ -68,6 +67,7 @@ struct SgdArgs {
     int32_t* err;
     int F, K, P, nstride, s, slots;
     int grid;         // workgroups of this stratum's launch
+    int nh;           // heavy blocks of this stratum (the first nh workgroups run one each)
     int upd;          // bit 0: update the user side {b_i, u_i}; bit 1: the item side {bh_j, v_j, w_j, c_j}
     int max_gangs;    // gangs the LDS holds (0: every segment is run by a single wave)
     int team;         // light blocks per team workgroup (1: every block has a workgroup of its own)
@@ -118,12 +118,12 @@ __global__ __launch_bounds__(kSgdWaves* kWave) void k_sgd_stratum(SgdArgs a, con
     const int F = a.F, K = a.K;
     const int lane = threadIdx.x & (kWave - 1);
     const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));  // wave-uniform
-    // The first heavy[s] workgroups run one block each (the heaviest, with
+    // The first a.nh workgroups run one block each (the heaviest, with
     // gangs); each later one runs a team of up to a.team light blocks, member m
     // on waves [m W, (m+1) W) with a mailbox of its own.  Blocks of a stratum
     // share no user and no item, so the members never interact.
     const int64_t sP = (int64_t)a.s * a.P;
-    const int nh = a.team > 1 ? a.heavy[a.s] : a.P;
+    const int nh = a.team > 1 ? a.nh : a.P;
     const bool in_team = (int)blockIdx.x >= nh;
     const int member = in_team ? wv / (kSgdWaves / a.team) : 0;
     int64_t blk = -1;  // -1: no block for this wave's member
@@ -902,7 +902,6 @@ int run_sgd(lshmf_ctx* c, Stream& st, const lshmf_hparams* hp, int epoch, int up
     a.team_floats = (int)(((int64_t)(a.team_slots + 1) * (d.F + 2) + 3) & ~3LL);
     while (a.max_gangs > 0 && sgd_lds_bytes(a) > (size_t)kMaxLdsBytes) --a.max_gangs;
     // light blocks in teams where their mailboxes fit in the block's LDS
-    a.heavy = st.heavy;
     for (int t = kTeam; t > 1 && a.team == 1; t /= 2) {
         a.team = t;
         if (sgd_lds_bytes(a) > (size_t)kMaxLdsBytes) a.team = 1;
@@ -927,6 +926,7 @@ int run_sgd(lshmf_ctx* c, Stream& st, const lshmf_hparams* hp, int epoch, int up
         const int nh = st.hcounts[stratum], ne = st.hcounts[P + stratum];
         if (ne == 0) continue;
         a.s = stratum;
+        a.nh = nh;
         a.grid = a.team > 1 ? nh + (ne - nh + a.team - 1) / a.team : ne;
         switch (fp) {
             case 1: LSHMF_TRY(launch_sgd_k<1>(a, st.pk, st.link, s)); break;
