@@ -50,6 +50,7 @@ void carve_stream(Carver& k, Stream& st, int64_t cap, int64_t P, int nstride)
     st.seg_start = k.take<int64_t>(cap + 1);
     st.blk_slots = k.take<int32_t>(P * P);
     st.blk_order = k.take<int32_t>(P * P);
+    st.blk_run = k.take<int32_t>(2 * P * P);
     st.heavy = k.take<int32_t>(2 * P);
     st.hcounts.assign((size_t)(2 * P), 0);
     st.stats = k.take<int64_t>(4);

@@ -108,6 +108,8 @@ struct Stream {
     int64_t* seg_start;        // cap + 1
     int32_t* blk_slots;        // P*P               mailbox slots per block
     int32_t* blk_order;        // P*P               dispatch order of each stratum's blocks: most ratings first
+    int32_t* blk_run;          // 2 P*P             per stratum and dispatch position: the block's first run
+                               //                   (segment) and its run count
     int32_t* heavy;            // 2P                per stratum: blocks with more than kLightNnz ratings, then
                                //                   blocks with any (both lead the dispatch order)
     std::vector<int32_t> hcounts;  // host copy of heavy (2P), read with the statistics

@@ -250,6 +250,18 @@ __global__ void k_heavy_count(const int64_t* blk_ptr, const int32_t* blk_order, 
     }
 }
 
+// The runs of the block at each dispatch position, read by the SGD kernel in
+// one load instead of two dependent ones (dispatch order, then run range).
+__global__ void k_block_runs(const int32_t* blk_order, const int64_t* blk_seg, int64_t P, int32_t* blk_run)
+{
+    for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < P * P;
+         x += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t b = (x / P) * P + blk_order[x];
+        blk_run[2 * x] = (int32_t)blk_seg[b];
+        blk_run[2 * x + 1] = (int32_t)(blk_seg[b + 1] - blk_seg[b]);
+    }
+}
+
 __global__ void k_block_slots(const int64_t* blk_ptr, const int64_t* ex, int64_t nblk, int32_t* out)
 {
     for (int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; b < nblk;
@@ -630,6 +642,9 @@ int build_stream_async(lshmf_ctx* c, Stream& st, const int32_t* u, const int32_t
         LSHMF_HIP(hipMemcpyAsync(st.blk_order, c->sv[ro], sizeof(int32_t) * P * P, hipMemcpyDeviceToDevice, s));
         hipLaunchKernelGGL(k_heavy_count, dim3(grid_for(P)), dim3(256), 0, s, st.blk_ptr, st.blk_order, P, st.heavy);
         LSHMF_LAUNCHED("k_heavy_count");
+        hipLaunchKernelGGL(k_block_runs, dim3(grid_for(P * P)), dim3(256), 0, s, st.blk_order, st.blk_seg, P,
+                           st.blk_run);
+        LSHMF_LAUNCHED("k_block_runs");
     }
     // zero tails: the SGD kernel reads a few records past a run's end
     LSHMF_TRY(fill_i32(reinterpret_cast<int32_t*>(st.pk) + n, kStreamPad, 0, s));

@@ -49,8 +49,7 @@ constexpr int kMaxSlots = (1 << 16) - 2;
 struct SgdArgs {
     const uint8_t* nib;
     const int64_t* blk_ptr;
-    const int64_t* blk_seg;
-    const int32_t* blk_order;  // P*P: block run by each workgroup of a stratum
+    const int32_t* blk_run;    // 2 P*P: first run and run count of the block at each dispatch position
     const int32_t* seg_col;
     const int64_t* seg_start;
     const float* nbr_b0;
@@ -126,19 +125,19 @@ __global__ __launch_bounds__(kSgdWaves* kWave) void k_sgd_stratum(SgdArgs a, con
     const int nh = a.team > 1 ? a.nh : a.P;
     const bool in_team = (int)blockIdx.x >= nh;
     const int member = in_team ? wv / (kSgdWaves / a.team) : 0;
-    int64_t blk = -1;  // -1: no block for this wave's member
-    if (!in_team) {
-        blk = sP + a.blk_order[sP + blockIdx.x];
-    } else {
-        const int64_t x = nh + ((int64_t)blockIdx.x - nh) * a.team + member;
-        if (x < a.P) blk = sP + a.blk_order[sP + x];
+    // dispatch position of this wave's block (-1: none for this member)
+    int64_t xpos = (int64_t)blockIdx.x;
+    if (in_team) {
+        xpos = nh + ((int64_t)blockIdx.x - nh) * a.team + member;
+        if (xpos >= a.P) xpos = -1;
     }
     const int dummy = in_team ? a.team_slots : a.slots;
     float* mb_u = smem + (in_team ? (size_t)member * a.team_floats : 0);
     float* mb_b = mb_u + (size_t)(dummy + 1) * F;
     int* mb_seq = reinterpret_cast<int*>(mb_b + dummy + 1);
-    const int64_t g0 = blk >= 0 ? a.blk_seg[blk] : 0, g1 = blk >= 0 ? a.blk_seg[blk + 1] : 0;
-    const int nsegs = (int)(g1 - g0);
+    const int2 brun = xpos >= 0 ? *reinterpret_cast<const int2*>(a.blk_run + 2 * (sP + xpos)) : make_int2(0, 0);
+    const int64_t g0 = brun.x;
+    const int nsegs = brun.y;
     // The first segments of the block, while long, each get a gang: an item
     // wave that keeps the item state and runs only the dependent update chain,
     // fed through an LDS ring by helper waves that load and prepare the
@@ -870,8 +869,7 @@ int run_sgd(lshmf_ctx* c, Stream& st, const lshmf_hparams* hp, int epoch, int up
     // K = 0: no codes; the kernel's clamped code reads then land on the sink
     a.nib = c->nstride > 0 ? st.nib : reinterpret_cast<const uint8_t*>(c->trash);
     a.blk_ptr = st.blk_ptr;
-    a.blk_seg = st.blk_seg;
-    a.blk_order = st.blk_order;
+    a.blk_run = st.blk_run;
     a.seg_col = st.seg_col;
     a.seg_start = st.seg_start;
     a.nbr_b0 = c->nbr_b0;
