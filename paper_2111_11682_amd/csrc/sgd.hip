@@ -27,7 +27,7 @@ constexpr int kHelpers = 4;                      // helper waves of a gang
 constexpr int kGangWaves = kHelpers + 2;         // item wave, helpers, writer wave
 constexpr int kMaxGangs = 2;                     // gangs per block
 constexpr int kGangMin = 48;                     // shortest segment given a gang
-constexpr int kHG = 4;                           // ratings per helper pipeline stage
+constexpr int kHG = 1;                           // ratings per helper pipeline stage
 constexpr int kTeam = 4;                         // light blocks per team workgroup
 constexpr int kIG = 8;                           // ratings per item-wave group
 // ring slots of a gang: a power of two (slot = rating & (kRing - 1)) and a
