@@ -26,7 +26,10 @@ constexpr int kGroup = 4;                        // ratings per pipeline stage
 constexpr int kHelpers = 4;                      // helper waves of a gang
 constexpr int kGangWaves = kHelpers + 2;         // item wave, helpers, writer wave
 constexpr int kMaxGangs = 2;                     // gangs per block
-constexpr int kGangMin = 48;                     // shortest segment given a gang
+// shortest segment given a gang: 48 ratings when a block can hold two gangs,
+// 32 when its LDS holds one (measured on the ML-10M and Netflix shapes)
+constexpr int kGangMin2 = 48;
+constexpr int kGangMin1 = 32;
 constexpr int kHG = 1;                           // ratings per helper pipeline stage
 constexpr int kTeam = 4;                         // light blocks per team workgroup
 constexpr int kIG = 8;                           // ratings per item-wave group
@@ -69,6 +72,7 @@ struct SgdArgs {
     int nh;           // heavy blocks of this stratum (the first nh workgroups run one each)
     int upd;          // bit 0: update the user side {b_i, u_i}; bit 1: the item side {bh_j, v_j, w_j, c_j}
     int max_gangs;    // gangs the LDS holds (0: every segment is run by a single wave)
+    int gang_min;     // shortest segment given a gang
     int team;         // light blocks per team workgroup (1: every block has a workgroup of its own)
     int team_slots;   // mailbox slots of a team member (a light block has at most kLightNnz / 2)
     int team_floats;  // floats of LDS per team member
@@ -144,7 +148,7 @@ __global__ __launch_bounds__(kSgdWaves* kWave) void k_sgd_stratum(SgdArgs a, con
     // user-side inputs of every rating.
     int ngang = 0;
     for (int k = 0; !in_team && k < a.max_gangs && k < nsegs; ++k) {
-        if (a.seg_start[g0 + k + 1] - a.seg_start[g0 + k] < kGangMin) break;
+        if (a.seg_start[g0 + k + 1] - a.seg_start[g0 + k] < a.gang_min) break;
         ngang = k + 1;
     }
     const int RS = a.ring_rs;
@@ -899,6 +903,7 @@ int run_sgd(lshmf_ctx* c, Stream& st, const lshmf_hparams* hp, int epoch, int up
     a.team_slots = kLightNnz / 2;
     a.team_floats = (int)(((int64_t)(a.team_slots + 1) * (d.F + 2) + 3) & ~3LL);
     while (a.max_gangs > 0 && sgd_lds_bytes(a) > (size_t)kMaxLdsBytes) --a.max_gangs;
+    a.gang_min = a.max_gangs >= 2 ? kGangMin2 : kGangMin1;
     // light blocks in teams where their mailboxes fit in the block's LDS
     for (int t = kTeam; t > 1 && a.team == 1; t /= 2) {
         a.team = t;
