@@ -4,8 +4,8 @@ The SGD reads each user row from HBM as BF16, computes in FP32 and writes it
 back rounded to nearest even (inside a block the row passes between ratings
 in FP32); the item side keeps FP32 masters.  The arithmetic is no longer
 that of the FP64 oracle up to FP32 rounding: every store of a user row drops
-to 8 significant bits.  The bar is the benchmark spec's for BF16 storage: held-out
-RMSE within 0.5% of the FP64 oracle's.  The tests also show that the FP32 U
+to 8 significant bits.  The bar is the one for BF16 storage: held-out RMSE
+within 0.5% of the FP64 oracle's.  The tests also show that the FP32 U
 table is not read (NaN there changes nothing), and print the one-epoch
 distance of every table from the oracle for the record.
 """
