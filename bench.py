@@ -317,7 +317,7 @@ def main():
     w = synth.WORKLOADS[args.workload]
     epochs = args.epochs or w.epochs
     t0 = time.time()
-    d = synth.generate(w)
+    d = synth.generate(w, log=log if w.nnz > 200_000_000 else None)
     log("generated %s: %d train / %d test ratings in %.1fs" %
         (w.name, d["train_u"].size, d["test_u"].size, time.time() - t0))
     dev = torch.device("cuda:0")

@@ -419,11 +419,12 @@ __global__ __launch_bounds__(kTopkThreads) void k_topk(const int32_t* bitem, con
 // -------------------------------------------------------- neighbour codes
 // One wave per stream rating; lane L resolves slots L and L + 64 by binary
 // search in the user's CSR row, then byte x of the record packs slots 2x
-// (low nibble) and 2x+1 (high nibble).
+// (low nibble) and 2x+1 (high nibble).  Ratings of users with at most
+// row_min ratings in the store are skipped (row_min < 0: none is).
 __global__ __launch_bounds__(256) void k_nbr_codes(const uint32_t* pk, const int32_t* sj, int64_t n,
                                                    const int32_t* JK, int K, const int64_t* row_ptr,
                                                    const int32_t* csr_col, const uint8_t* csr_rc,
-                                                   uint8_t* nib, int nstride)
+                                                   uint8_t* nib, int nstride, int64_t row_min)
 {
     const int lane = threadIdx.x & (kWave - 1);
     const int64_t w0 = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kWave;
@@ -432,6 +433,7 @@ __global__ __launch_bounds__(256) void k_nbr_codes(const uint32_t* pk, const int
         const int64_t i = pk[p] >> 4;
         const int64_t j = sj[p];
         const int64_t a = row_ptr[i], z = row_ptr[i + 1];
+        if (z - a <= row_min) continue;
         int code[2] = {0, 0};
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
@@ -536,6 +538,100 @@ __global__ __launch_bounds__(256) void k_nbr_codes_rows(const int64_t* row_ptr, 
         }
         __syncthreads();
         for (int32_t x = tid; x < deg; x += nt) map[csr_col[a + x]] = 0;
+    }
+}
+
+// The same by user row for any item count: the row's (item, code) pairs sit
+// in an LDS open-addressing table (linear probing, Fibonacci hash of the
+// item id, at most half full; a quarter for rows of up to kHashCap / 4
+// ratings), so a slot costs a probe sequence instead of a byte-map read.
+// Rows longer than kHashCap / 2 are skipped here and resolved by k_nbr_codes.
+constexpr int kHashLg = 14;
+constexpr int kHashCap = 1 << kHashLg;   // table entries (64 KB of LDS)
+constexpr int kHashThreads = 512;
+constexpr uint32_t kHashEmpty = 0xFFFFFFFFu;
+
+__device__ __forceinline__ uint32_t hash_code(const uint32_t* tab, uint32_t mask, int sh, int32_t item)
+{
+    uint32_t h = ((uint32_t)item * 2654435769u) >> sh;
+    while (true) {
+        const uint32_t e = tab[h];
+        if (e == kHashEmpty) return 0u;
+        if ((int32_t)(e >> 4) == item) return e & 15u;
+        h = (h + 1) & mask;
+    }
+}
+
+__global__ __launch_bounds__(kHashThreads) void k_nbr_codes_hash(const int64_t* row_ptr, const int32_t* csr_col,
+                                                                 const uint8_t* csr_rc, int32_t M,
+                                                                 const uint32_t* by_user, const int32_t* sj,
+                                                                 const int32_t* JK, int K, uint8_t* nib,
+                                                                 int nstride)
+{
+    __shared__ uint32_t tab[kHashCap];
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int wpr = nstride / 4;               // 4-byte words per record
+    const bool quads = (K & 3) == 0;           // JK rows 16-byte aligned
+    const int e0 = tid / wpr, w0 = tid - e0 * wpr;
+    const int de = nt / wpr, dw = nt - de * wpr;
+    for (int32_t i = blockIdx.x; i < M; i += gridDim.x) {
+        const int64_t a = row_ptr[i];
+        const int32_t deg = (int32_t)(row_ptr[i + 1] - a);
+        if (deg == 0 || deg > kHashCap / 2) continue;    // the same for every thread of the block
+        int lg = 6;
+        while (lg < kHashLg && (1 << lg) < 4 * deg) ++lg;
+        const uint32_t mask = (1u << lg) - 1u;
+        const int sh = 32 - lg;
+        __syncthreads();                       // the previous row's lookups are done
+        for (int x = tid; x <= (int)mask; x += nt) tab[x] = kHashEmpty;
+        __syncthreads();
+        for (int32_t x = tid; x < deg; x += nt) {  // items of a row are distinct: no key is inserted twice
+            const int32_t it = csr_col[a + x];
+            const uint32_t key = ((uint32_t)it << 4) | (uint32_t)csr_rc[a + x];
+            uint32_t h = ((uint32_t)it * 2654435769u) >> sh;
+            while (atomicCAS(&tab[h], kHashEmpty, key) != kHashEmpty) h = (h + 1) & mask;
+        }
+        __syncthreads();
+        int e = e0, w = w0;
+        while (e < deg) {
+            int ee[kCodeUnroll], ww[kCodeUnroll];
+            uint32_t p[kCodeUnroll];
+#pragma unroll
+            for (int u = 0; u < kCodeUnroll; ++u) {
+                ee[u] = e;
+                ww[u] = w;
+                p[u] = e < deg ? by_user[a + e] : 0u;
+                e += de;
+                w += dw;
+                if (w >= wpr) {
+                    w -= wpr;
+                    ++e;
+                }
+            }
+            int32_t j[kCodeUnroll];
+#pragma unroll
+            for (int u = 0; u < kCodeUnroll; ++u) j[u] = ee[u] < deg ? sj[p[u]] : 0;
+#pragma unroll
+            for (int u = 0; u < kCodeUnroll; ++u) {
+                if (ee[u] >= deg) continue;
+                const int32_t* jk = JK + (int64_t)j[u] * K;
+                const int k0 = 8 * ww[u];
+                int32_t nb[8];
+                if (quads && k0 + 8 <= K) {
+                    const int4 q0 = *reinterpret_cast<const int4*>(jk + k0);
+                    const int4 q1 = *reinterpret_cast<const int4*>(jk + k0 + 4);
+                    nb[0] = q0.x; nb[1] = q0.y; nb[2] = q0.z; nb[3] = q0.w;
+                    nb[4] = q1.x; nb[5] = q1.y; nb[6] = q1.z; nb[7] = q1.w;
+                } else {
+                    for (int h = 0; h < 8; ++h) nb[h] = k0 + h < K ? jk[k0 + h] : -1;
+                }
+                uint32_t word = 0;
+#pragma unroll
+                for (int h = 0; h < 8; ++h)
+                    if (nb[h] >= 0) word |= hash_code(tab, mask, sh, nb[h]) << (4 * h);
+                *reinterpret_cast<uint32_t*>(nib + (int64_t)p[u] * nstride + 4 * ww[u]) = word;
+            }
+        }
     }
 }
 
@@ -659,22 +755,34 @@ int neighbours_for(lshmf_ctx* c, int32_t j_first, int32_t count, uint64_t seed_f
 int stream_codes(lshmf_ctx* c, Stream& st, hipStream_t s)
 {
     if (st.n > 0 && c->d.K > 0) {
-        if (c->N <= kCodeMapMax && st.n == c->nnz) {
+        if (st.n == c->nnz && c->N < (1 << 27)) {
             // the stream is the store (no pair twice), so its ratings of user i
             // are exactly CSR row i
             hipLaunchKernelGGL(k_keys_user, dim3(grid_for(st.n)), dim3(256), 0, s, st.pk, st.n, c->sk[0], c->sv[0]);
             LSHMF_LAUNCHED("k_keys_user");
             int ri = 0;
             LSHMF_TRY(radix_sort(c->sk, c->sv, st.n, bits_for((uint64_t)c->M), c->hist, c->scan_tmp, s, &ri));
-            const size_t lds = sizeof(uint32_t) * (size_t)((c->N + 3) / 4);
             const unsigned grid = (unsigned)(c->M < 4096 ? (c->M > 0 ? c->M : 1) : 4096);
-            hipLaunchKernelGGL(k_nbr_codes_rows, dim3(grid), dim3(256), lds, s, c->row_ptr, c->csr_col, c->csr_rc,
-                               c->M, c->N, c->sv[ri], st.sj, c->t.JK, c->d.K, st.nib, c->nstride);
-            LSHMF_LAUNCHED("k_nbr_codes_rows");
+            if (c->N <= kCodeMapMax) {
+                const size_t lds = sizeof(uint32_t) * (size_t)((c->N + 3) / 4);
+                hipLaunchKernelGGL(k_nbr_codes_rows, dim3(grid), dim3(256), lds, s, c->row_ptr, c->csr_col,
+                                   c->csr_rc, c->M, c->N, c->sv[ri], st.sj, c->t.JK, c->d.K, st.nib, c->nstride);
+                LSHMF_LAUNCHED("k_nbr_codes_rows");
+            } else {
+                // item ids above the byte map's reach: hash tables for rows of up
+                // to kHashCap / 2 ratings, binary searches for the longer rows
+                hipLaunchKernelGGL(k_nbr_codes_hash, dim3(grid), dim3(kHashThreads), 0, s, c->row_ptr, c->csr_col,
+                                   c->csr_rc, c->M, c->sv[ri], st.sj, c->t.JK, c->d.K, st.nib, c->nstride);
+                LSHMF_LAUNCHED("k_nbr_codes_hash");
+                hipLaunchKernelGGL(k_nbr_codes, dim3(grid_for(st.n * kWave, 256, 65536)), dim3(256), 0, s, st.pk,
+                                   st.sj, st.n, c->t.JK, c->d.K, c->row_ptr, c->csr_col, c->csr_rc, st.nib,
+                                   c->nstride, (int64_t)(kHashCap / 2));
+                LSHMF_LAUNCHED("k_nbr_codes(long rows)");
+            }
         } else {
             hipLaunchKernelGGL(k_nbr_codes, dim3(grid_for(st.n * kWave, 256, 65536)), dim3(256), 0, s, st.pk,
                                st.sj, st.n, c->t.JK, c->d.K, c->row_ptr, c->csr_col, c->csr_rc, st.nib,
-                               c->nstride);
+                               c->nstride, (int64_t)-1);
             LSHMF_LAUNCHED("k_nbr_codes");
         }
     }

@@ -29,7 +29,7 @@ from __future__ import annotations
 
 import dataclasses
 import math
-from typing import Dict, Optional, Tuple
+from typing import Callable, Dict, Optional, Tuple
 
 import numpy as np
 
@@ -92,6 +92,11 @@ WORKLOADS: Dict[str, Workload] = {
     "netflix": Workload("netflix", 480_189, 17_770, 100_000_000, 1, 1.2, "lognormal",
                         4.5, 1.2, 1, 1_408_395, 128, 100, 8, 1, 16, 20,
                         _NF_ALPHA, _NF_LAM, 0.3, n_strata=1536),
+    # the largest single-GPU shape: 2M users x 500k items, 1B integer ratings,
+    # Zipf s = 1.3 items, F = 128, K = 64, 256 hash bits as (8, 2, 16)
+    "large1b": Workload("large1b", 2_000_000, 500_000, 1_000_000_000, 1, 1.3, "lognormal",
+                        _ln_mu_for_mean(500.0, 1.2), 1.2, 1, 1_000_000, 128, 64, 8, 2, 16, 20,
+                        _NF_ALPHA, _NF_LAM, 0.3, n_strata=4096),
     # small shapes for CPU tests
     "tiny": Workload("tiny", 120, 90, 2_400, 1, 1.0, "c1", 0.0, 1.0, 5,
                      240, 8, 6, 8, 1, 4, 3, (0.01,) * 6, (0.05,) * 6, 0.0,
@@ -108,6 +113,12 @@ WORKLOADS: Dict[str, Workload] = {
     "wide": Workload("wide", 900, 600, 40_000, 2, 1.1, "lognormal",
                      _ln_mu_for_mean(44.0, 1.0), 1.0, 5, 2_000, 200, 70, 8, 1, 8, 2,
                      _ML_ALPHA, _ML_LAM, 0.3, n_strata=12),
+    # more items than an LDS byte map holds, a few users past 8192 ratings:
+    # neighbour codes by hashed user rows plus binary searches; K = 20 mixes
+    # whole and partial 8-slot words
+    "manyitems": Workload("manyitems", 1_500, 80_000, 1_200_000, 1, 1.0, "lognormal",
+                          _ln_mu_for_mean(800.0, 1.2), 1.2, 1, 2_000, 16, 20, 8, 1, 8, 2,
+                          _ML_ALPHA, _ML_LAM, 0.3, n_strata=64),
 }
 
 # The same workloads with K = 0: biased MF without the neighbour term, on the
@@ -239,14 +250,14 @@ def _sample_chunk(need: np.ndarray, cdf: np.ndarray, N: int, rng: np.random.Gene
 CHUNK_USERS = 16384
 
 
-def sample_items(deg: np.ndarray, N: int, s: float, rng: np.random.Generator
-                 ) -> Tuple[np.ndarray, np.ndarray]:
+def sample_items(deg: np.ndarray, N: int, s: float, rng: np.random.Generator,
+                 log: Optional[Callable[[str], None]] = None) -> Tuple[np.ndarray, np.ndarray]:
     """Successive sampling without replacement from Zipf(s) popularity ranks.
 
     Users are drawn in fixed chunks of CHUNK_USERS, each chunk from its own
     generator seeded from `rng`, so the result does not depend on how many
     threads draw the chunks.  Returns (user, rank) pairs, users ascending,
-    ranks in draw order per user.
+    ranks in draw order per user.  `log`, if given, hears every 16th chunk.
     """
     import concurrent.futures
     import os
@@ -261,6 +272,8 @@ def sample_items(deg: np.ndarray, N: int, s: float, rng: np.random.Generator
         lo = k * CHUNK_USERS
         g = np.random.Generator(np.random.PCG64(np.random.SeedSequence([root, k])))
         u, r = _sample_chunk(deg[lo: lo + CHUNK_USERS], cdf, N, g)
+        if log is not None and k % 16 == 15:
+            log("  items: chunk %d of %d drawn" % (k + 1, n_chunks))
         return u + lo, r
 
     workers = max(1, min(16, os.cpu_count() or 1, n_chunks))
@@ -317,12 +330,15 @@ def hash_strings(M: int, B: int, rng: np.random.Generator) -> np.ndarray:
     return H
 
 
-def generate(w: Workload, seed: int = MASTER_SEED, with_tables: bool = True) -> Dict[str, np.ndarray]:
+def generate(w: Workload, seed: int = MASTER_SEED, with_tables: bool = True,
+             log: Optional[Callable[[str], None]] = None) -> Dict[str, np.ndarray]:
     """All inputs of one workload, deterministic in (w, seed).
 
     Keys: train_u, train_i, train_rc, test_u, test_i, test_rc (int32/uint8 COO),
     H (uint32 [M, ceil(B/32)]), U0 (f32 [M, F]), V0 (f32 [N, F]).
+    `log`, if given, hears each step (the 1B-rating shape takes minutes).
     """
+    say = log if log is not None else (lambda msg: None)
     rng_deg = _rng(seed, 1)
     rng_items = _rng(seed, 2)
     rng_perm = _rng(seed, 3)
@@ -332,15 +348,22 @@ def generate(w: Workload, seed: int = MASTER_SEED, with_tables: bool = True) -> 
     rng_init = _rng(seed, 7)
 
     deg = user_degrees(w, rng_deg)
-    u, rank = sample_items(deg, w.N, w.zipf_s, rng_items)
+    say("  %s: user degrees drawn" % w.name)
+    u, rank = sample_items(deg, w.N, w.zipf_s, rng_items, log)
     user_perm = rng_perm.permutation(w.M)
     item_perm = rng_perm.permutation(w.N)
     uid = user_perm[u].astype(np.int32)
+    del u
     iid = item_perm[rank].astype(np.int32)
+    del rank
+    say("  %s: %d items drawn" % (w.name, uid.shape[0]))
     rc = planted_ratings(uid, iid, w.M, w.N, w.rscale, rng_rate)
+    say("  %s: ratings drawn" % w.name)
     order = rng_split.permutation(uid.shape[0])
     test_idx = np.sort(order[: w.n_test])
     train_idx = np.sort(order[w.n_test:])
+    del order
+    say("  %s: split drawn" % w.name)
     out = {
         "train_u": np.ascontiguousarray(uid[train_idx]),
         "train_i": np.ascontiguousarray(iid[train_idx]),

@@ -132,7 +132,7 @@ def test_layout_matches_oracle_order(name):
     assert np.allclose(m.bh0.cpu().numpy(), bh0, rtol=0, atol=1e-6)
 
 
-@pytest.mark.parametrize("name", ["tiny", "small", "ml100k", "nfsmall", "wide"])
+@pytest.mark.parametrize("name", ["tiny", "small", "ml100k", "nfsmall", "wide", "manyitems"])
 def test_signatures_and_neighbours_bit_exact(name):
     w, d, m = gpu_model(name)
     acc, sig, JK = oracle_neighbours(name)
@@ -141,9 +141,11 @@ def test_signatures_and_neighbours_bit_exact(name):
     assert np.array_equal(m.JK.cpu().numpy(), JK)
 
 
-@pytest.mark.parametrize("name", ["small", "ml100k", "nfsmall", "wide"])
+@pytest.mark.parametrize("name", ["small", "ml100k", "nfsmall", "wide", "manyitems"])
 def test_neighbour_codes_exact(name):
-    """Every byte of every record, against codes looked up from the triples."""
+    """Every byte of every record, against codes looked up from the triples.
+    manyitems has more items than an LDS byte map holds: its rows go through
+    hash tables, and its users past 8192 ratings through binary searches."""
     w, d, m = gpu_model(name)
     nnz = d["train_u"].size
     lay = m.layout()
