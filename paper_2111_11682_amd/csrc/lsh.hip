@@ -419,12 +419,11 @@ __global__ __launch_bounds__(kTopkThreads) void k_topk(const int32_t* bitem, con
 // -------------------------------------------------------- neighbour codes
 // One wave per stream rating; lane L resolves slots L and L + 64 by binary
 // search in the user's CSR row, then byte x of the record packs slots 2x
-// (low nibble) and 2x+1 (high nibble).  Ratings of users with at most
-// row_min ratings in the store are skipped (row_min < 0: none is).
+// (low nibble) and 2x+1 (high nibble).
 __global__ __launch_bounds__(256) void k_nbr_codes(const uint32_t* pk, const int32_t* sj, int64_t n,
                                                    const int32_t* JK, int K, const int64_t* row_ptr,
                                                    const int32_t* csr_col, const uint8_t* csr_rc,
-                                                   uint8_t* nib, int nstride, int64_t row_min)
+                                                   uint8_t* nib, int nstride)
 {
     const int lane = threadIdx.x & (kWave - 1);
     const int64_t w0 = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kWave;
@@ -433,7 +432,6 @@ __global__ __launch_bounds__(256) void k_nbr_codes(const uint32_t* pk, const int
         const int64_t i = pk[p] >> 4;
         const int64_t j = sj[p];
         const int64_t a = row_ptr[i], z = row_ptr[i + 1];
-        if (z - a <= row_min) continue;
         int code[2] = {0, 0};
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
@@ -541,13 +539,18 @@ __global__ __launch_bounds__(256) void k_nbr_codes_rows(const int64_t* row_ptr, 
     }
 }
 
-// The same by user row for any item count: the row's (item, code) pairs sit
-// in an LDS open-addressing table (linear probing, Fibonacci hash of the
-// item id, at most half full; a quarter for rows of up to kHashCap / 4
-// ratings), so a slot costs a probe sequence instead of a byte-map read.
-// Rows longer than kHashCap / 2 are skipped here and resolved by k_nbr_codes.
+// The same by user row for any item count: a row's (item, code) pairs sit in
+// an LDS open-addressing table (linear probing on a Fibonacci hash of the item
+// id, at most half full), so a slot costs a short probe sequence instead of a
+// byte-map read.  Rows of up to kHashRow ratings take one table (a quarter
+// full when they have at most kHashRow / 2).  A longer row is cut into chunks
+// of kHashRow consecutive CSR entries: every chunk, in a workgroup of its own,
+// resolves the slots whose items it holds for every record of the row and ORs
+// them into the record (zeroed beforehand), so the row's cost is spread over
+// its chunks' workgroups.
 constexpr int kHashLg = 14;
 constexpr int kHashCap = 1 << kHashLg;   // table entries (64 KB of LDS)
+constexpr int kHashRow = kHashCap / 2;
 constexpr int kHashThreads = 512;
 constexpr uint32_t kHashEmpty = 0xFFFFFFFFu;
 
@@ -562,76 +565,140 @@ __device__ __forceinline__ uint32_t hash_code(const uint32_t* tab, uint32_t mask
     }
 }
 
+// Table of n CSR entries from `a` on (2^lg entries); the caller synchronises
+// before (the table is free) and after (it is complete).
+__device__ __forceinline__ void hash_fill(uint32_t* tab, int lg, const int32_t* csr_col, const uint8_t* csr_rc,
+                                          int64_t a, int32_t n)
+{
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const uint32_t mask = (1u << lg) - 1u;
+    for (int x = tid; x <= (int)mask; x += nt) tab[x] = kHashEmpty;
+    __syncthreads();
+    for (int32_t x = tid; x < n; x += nt) {  // items of a row are distinct: no key is inserted twice
+        const int32_t it = csr_col[a + x];
+        const uint32_t key = ((uint32_t)it << 4) | (uint32_t)csr_rc[a + x];
+        uint32_t h = ((uint32_t)it * 2654435769u) >> (32 - lg);
+        while (atomicCAS(&tab[h], kHashEmpty, key) != kHashEmpty) h = (h + 1) & mask;
+    }
+}
+
+// Every 4-byte word of the records of the row's deg ratings (stream positions
+// by_user[a ..]): the codes the table holds; stored, or ORed in when nonzero.
+template <bool kOr>
+__device__ __forceinline__ void hash_resolve(const uint32_t* tab, int lg, int64_t a, int32_t deg,
+                                             const uint32_t* by_user, const int32_t* sj, const int32_t* JK, int K,
+                                             uint8_t* nib, int nstride)
+{
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const uint32_t mask = (1u << lg) - 1u;
+    const int sh = 32 - lg;
+    const int wpr = nstride / 4;               // 4-byte words per record
+    const bool quads = (K & 3) == 0;           // JK rows 16-byte aligned
+    // a thread's work items t = tid + m * nt as (record e, word w) = divmod(t, wpr)
+    int e = tid / wpr, w = tid - (tid / wpr) * wpr;
+    const int de = nt / wpr, dw = nt - de * wpr;
+    while (e < deg) {
+        int ee[kCodeUnroll], ww[kCodeUnroll];
+        uint32_t p[kCodeUnroll];
+#pragma unroll
+        for (int u = 0; u < kCodeUnroll; ++u) {
+            ee[u] = e;
+            ww[u] = w;
+            p[u] = e < deg ? by_user[a + e] : 0u;
+            e += de;
+            w += dw;
+            if (w >= wpr) {
+                w -= wpr;
+                ++e;
+            }
+        }
+        int32_t j[kCodeUnroll];
+#pragma unroll
+        for (int u = 0; u < kCodeUnroll; ++u) j[u] = ee[u] < deg ? sj[p[u]] : 0;
+#pragma unroll
+        for (int u = 0; u < kCodeUnroll; ++u) {
+            if (ee[u] >= deg) continue;
+            const int32_t* jk = JK + (int64_t)j[u] * K;
+            const int k0 = 8 * ww[u];
+            int32_t nb[8];
+            if (quads && k0 + 8 <= K) {
+                const int4 q0 = *reinterpret_cast<const int4*>(jk + k0);
+                const int4 q1 = *reinterpret_cast<const int4*>(jk + k0 + 4);
+                nb[0] = q0.x; nb[1] = q0.y; nb[2] = q0.z; nb[3] = q0.w;
+                nb[4] = q1.x; nb[5] = q1.y; nb[6] = q1.z; nb[7] = q1.w;
+            } else {
+                for (int h = 0; h < 8; ++h) nb[h] = k0 + h < K ? jk[k0 + h] : -1;
+            }
+            uint32_t word = 0;
+#pragma unroll
+            for (int h = 0; h < 8; ++h)
+                if (nb[h] >= 0) word |= hash_code(tab, mask, sh, nb[h]) << (4 * h);
+            uint32_t* dst = reinterpret_cast<uint32_t*>(nib + (int64_t)p[u] * nstride + 4 * ww[u]);
+            if (!kOr) *dst = word;
+            else if (word != 0u) atomicOr(dst, word);
+        }
+    }
+}
+
+// Rows of up to kHashRow ratings; a longer row gets its records zeroed and
+// its id appended to long_rows (long_cnt[0] rows, long_cnt[1] the most
+// ratings of one), in no particular order.
 __global__ __launch_bounds__(kHashThreads) void k_nbr_codes_hash(const int64_t* row_ptr, const int32_t* csr_col,
                                                                  const uint8_t* csr_rc, int32_t M,
                                                                  const uint32_t* by_user, const int32_t* sj,
                                                                  const int32_t* JK, int K, uint8_t* nib,
-                                                                 int nstride)
+                                                                 int nstride, unsigned long long* long_cnt,
+                                                                 int32_t* long_rows)
 {
     __shared__ uint32_t tab[kHashCap];
     const int tid = threadIdx.x, nt = blockDim.x;
-    const int wpr = nstride / 4;               // 4-byte words per record
-    const bool quads = (K & 3) == 0;           // JK rows 16-byte aligned
-    const int e0 = tid / wpr, w0 = tid - e0 * wpr;
-    const int de = nt / wpr, dw = nt - de * wpr;
+    const int wpr = nstride / 4;
     for (int32_t i = blockIdx.x; i < M; i += gridDim.x) {
         const int64_t a = row_ptr[i];
         const int32_t deg = (int32_t)(row_ptr[i + 1] - a);
-        if (deg == 0 || deg > kHashCap / 2) continue;    // the same for every thread of the block
+        if (deg == 0) continue;                // the same for every thread of the block
+        if (deg > kHashRow) {
+            for (int64_t x = tid; x < (int64_t)deg * wpr; x += nt) {
+                const int64_t e = x / wpr;
+                *reinterpret_cast<uint32_t*>(nib + (int64_t)by_user[a + e] * nstride + 4 * (x - e * wpr)) = 0u;
+            }
+            if (tid == 0) {
+                long_rows[atomicAdd(&long_cnt[0], 1ull)] = i;
+                atomicMax(&long_cnt[1], (unsigned long long)deg);
+            }
+            continue;
+        }
         int lg = 6;
         while (lg < kHashLg && (1 << lg) < 4 * deg) ++lg;
-        const uint32_t mask = (1u << lg) - 1u;
-        const int sh = 32 - lg;
         __syncthreads();                       // the previous row's lookups are done
-        for (int x = tid; x <= (int)mask; x += nt) tab[x] = kHashEmpty;
+        hash_fill(tab, lg, csr_col, csr_rc, a, deg);
         __syncthreads();
-        for (int32_t x = tid; x < deg; x += nt) {  // items of a row are distinct: no key is inserted twice
-            const int32_t it = csr_col[a + x];
-            const uint32_t key = ((uint32_t)it << 4) | (uint32_t)csr_rc[a + x];
-            uint32_t h = ((uint32_t)it * 2654435769u) >> sh;
-            while (atomicCAS(&tab[h], kHashEmpty, key) != kHashEmpty) h = (h + 1) & mask;
-        }
+        hash_resolve<false>(tab, lg, a, deg, by_user, sj, JK, K, nib, nstride);
+    }
+}
+
+// The long rows' chunks: pair t = (row long_rows[t % L], chunk t / L).
+__global__ __launch_bounds__(kHashThreads) void k_nbr_codes_long(const int64_t* row_ptr, const int32_t* csr_col,
+                                                                 const uint8_t* csr_rc, const uint32_t* by_user,
+                                                                 const int32_t* sj, const int32_t* JK, int K,
+                                                                 uint8_t* nib, int nstride,
+                                                                 const unsigned long long* long_cnt,
+                                                                 const int32_t* long_rows)
+{
+    __shared__ uint32_t tab[kHashCap];
+    const int64_t L = (int64_t)long_cnt[0];
+    const int64_t chunks = ((int64_t)long_cnt[1] + kHashRow - 1) / kHashRow;
+    for (int64_t t = blockIdx.x; t < L * chunks; t += gridDim.x) {
+        const int32_t i = long_rows[t % L];
+        const int64_t lo = (t / L) * kHashRow;
+        const int64_t a = row_ptr[i];
+        const int32_t deg = (int32_t)(row_ptr[i + 1] - a);
+        if (lo >= deg) continue;               // the same for every thread of the block
+        const int32_t n = deg - lo < kHashRow ? (int32_t)(deg - lo) : kHashRow;
+        __syncthreads();                       // the previous chunk's lookups are done
+        hash_fill(tab, kHashLg, csr_col, csr_rc, a + lo, n);
         __syncthreads();
-        int e = e0, w = w0;
-        while (e < deg) {
-            int ee[kCodeUnroll], ww[kCodeUnroll];
-            uint32_t p[kCodeUnroll];
-#pragma unroll
-            for (int u = 0; u < kCodeUnroll; ++u) {
-                ee[u] = e;
-                ww[u] = w;
-                p[u] = e < deg ? by_user[a + e] : 0u;
-                e += de;
-                w += dw;
-                if (w >= wpr) {
-                    w -= wpr;
-                    ++e;
-                }
-            }
-            int32_t j[kCodeUnroll];
-#pragma unroll
-            for (int u = 0; u < kCodeUnroll; ++u) j[u] = ee[u] < deg ? sj[p[u]] : 0;
-#pragma unroll
-            for (int u = 0; u < kCodeUnroll; ++u) {
-                if (ee[u] >= deg) continue;
-                const int32_t* jk = JK + (int64_t)j[u] * K;
-                const int k0 = 8 * ww[u];
-                int32_t nb[8];
-                if (quads && k0 + 8 <= K) {
-                    const int4 q0 = *reinterpret_cast<const int4*>(jk + k0);
-                    const int4 q1 = *reinterpret_cast<const int4*>(jk + k0 + 4);
-                    nb[0] = q0.x; nb[1] = q0.y; nb[2] = q0.z; nb[3] = q0.w;
-                    nb[4] = q1.x; nb[5] = q1.y; nb[6] = q1.z; nb[7] = q1.w;
-                } else {
-                    for (int h = 0; h < 8; ++h) nb[h] = k0 + h < K ? jk[k0 + h] : -1;
-                }
-                uint32_t word = 0;
-#pragma unroll
-                for (int h = 0; h < 8; ++h)
-                    if (nb[h] >= 0) word |= hash_code(tab, mask, sh, nb[h]) << (4 * h);
-                *reinterpret_cast<uint32_t*>(nib + (int64_t)p[u] * nstride + 4 * ww[u]) = word;
-            }
-        }
+        hash_resolve<true>(tab, kHashLg, a, deg, by_user, sj, JK, K, nib, nstride);
     }
 }
 
@@ -769,20 +836,24 @@ int stream_codes(lshmf_ctx* c, Stream& st, hipStream_t s)
                                    c->csr_rc, c->M, c->N, c->sv[ri], st.sj, c->t.JK, c->d.K, st.nib, c->nstride);
                 LSHMF_LAUNCHED("k_nbr_codes_rows");
             } else {
-                // item ids above the byte map's reach: hash tables for rows of up
-                // to kHashCap / 2 ratings, binary searches for the longer rows
+                // item ids past the byte map's reach: hash tables, long rows in
+                // chunks (their list and counters in the free counter buffer)
+                unsigned long long* long_cnt = reinterpret_cast<unsigned long long*>(c->cnt);
+                int32_t* long_rows = reinterpret_cast<int32_t*>(c->cnt + 2);
+                LSHMF_TRY(fill_i64(c->cnt, 2, 0, s));
                 hipLaunchKernelGGL(k_nbr_codes_hash, dim3(grid), dim3(kHashThreads), 0, s, c->row_ptr, c->csr_col,
-                                   c->csr_rc, c->M, c->sv[ri], st.sj, c->t.JK, c->d.K, st.nib, c->nstride);
+                                   c->csr_rc, c->M, c->sv[ri], st.sj, c->t.JK, c->d.K, st.nib, c->nstride,
+                                   long_cnt, long_rows);
                 LSHMF_LAUNCHED("k_nbr_codes_hash");
-                hipLaunchKernelGGL(k_nbr_codes, dim3(grid_for(st.n * kWave, 256, 65536)), dim3(256), 0, s, st.pk,
-                                   st.sj, st.n, c->t.JK, c->d.K, c->row_ptr, c->csr_col, c->csr_rc, st.nib,
-                                   c->nstride, (int64_t)(kHashCap / 2));
-                LSHMF_LAUNCHED("k_nbr_codes(long rows)");
+                hipLaunchKernelGGL(k_nbr_codes_long, dim3(1024), dim3(kHashThreads), 0, s, c->row_ptr, c->csr_col,
+                                   c->csr_rc, c->sv[ri], st.sj, c->t.JK, c->d.K, st.nib, c->nstride, long_cnt,
+                                   long_rows);
+                LSHMF_LAUNCHED("k_nbr_codes_long");
             }
         } else {
             hipLaunchKernelGGL(k_nbr_codes, dim3(grid_for(st.n * kWave, 256, 65536)), dim3(256), 0, s, st.pk,
                                st.sj, st.n, c->t.JK, c->d.K, c->row_ptr, c->csr_col, c->csr_rc, st.nib,
-                               c->nstride, (int64_t)-1);
+                               c->nstride);
             LSHMF_LAUNCHED("k_nbr_codes");
         }
     }
