@@ -145,3 +145,24 @@ def test_create_accepts_the_papers_hash_shapes(ok):
     st, h = _create(**ok)
     assert st == 0, lshmf.lib().lshmf_last_error()
     lshmf.lib().lshmf_destroy(h)
+
+
+def test_the_1b_rating_shape_fits_one_gpu():
+    """2M users x 500k items with 999M training ratings, F = 128, K = 64,
+    B = 256 and 4096 strata: accepted, with an arena that leaves room for the
+    tables and the input triples in 288 GB of HBM."""
+    from paper_2111_11682_amd import synth
+    w = synth.WORKLOADS["large1b"]
+    nnz = w.nnz - w.n_test
+    st, h = _create(M=w.M, N=w.N, F=w.F, K=w.K, G=w.G, p=w.p, q=w.q, rscale=w.rscale,
+                    n_strata=w.n_strata, nnz=nnz)
+    assert st == 0, lshmf.lib().lshmf_last_error()
+    n = C.c_size_t()
+    assert lshmf.lib().lshmf_arena_bytes(h, C.byref(n)) == 0
+    lshmf.lib().lshmf_destroy(h)
+    tables = 4 * (w.M * w.F + w.N * w.F + 3 * w.N * w.K + w.N * w.B + 2 * (w.M + w.N))
+    inputs = 9 * nnz + 4 * (w.M + w.N) * w.F
+    assert nnz * 60 < n.value and n.value + tables + inputs < 200e9
+    # the stream sort key (block, item rank, user rank) must fit 64 bits
+    bits = lambda v: int(v - 1).bit_length()
+    assert bits(w.n_strata ** 2) + bits(w.N) + bits(w.M) <= 64
