@@ -114,8 +114,8 @@ WORKLOADS: Dict[str, Workload] = {
                      _ln_mu_for_mean(44.0, 1.0), 1.0, 5, 2_000, 200, 70, 8, 1, 8, 2,
                      _ML_ALPHA, _ML_LAM, 0.3, n_strata=12),
     # more items than an LDS byte map holds, a few users past 8192 ratings:
-    # neighbour codes by hashed user rows plus binary searches; K = 20 mixes
-    # whole and partial 8-slot words
+    # neighbour codes by hashed user rows, the long rows in chunks; K = 20
+    # mixes whole and partial 8-slot words
     "manyitems": Workload("manyitems", 1_500, 80_000, 1_200_000, 1, 1.0, "lognormal",
                           _ln_mu_for_mean(800.0, 1.2), 1.2, 1, 2_000, 16, 20, 8, 1, 8, 2,
                           _ML_ALPHA, _ML_LAM, 0.3, n_strata=64),
